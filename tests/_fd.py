@@ -1,0 +1,116 @@
+"""Central finite differences of the rendered loss through the float64 oracle.
+
+L = sum(v_image * image) + sum(v_alpha * alpha).  A perturbed Gaussian only
+enters the lists of the tiles its rectangle covers, so L(+eps) - L(-eps) is
+evaluated on those tiles alone with the per-tile definition render.  A sample
+is accepted only if the decision trace (radius, rectangle, per-pixel
+composited set with clamp states, stop point, SH clamp mask) is identical at
++eps and -eps; otherwise another parameter is drawn.
+"""
+import numpy as np
+
+from paper_2409_06765_amd import scenes as _sc
+
+
+def _rect_tiles(P, proj, n, cams):
+    out = []
+    C = proj["radii"].shape[0]
+    for c in range(C):
+        r = int(proj["radii"][c, n])
+        if r <= 0:
+            continue
+        mx, my = proj["means2d"][c, n]
+        W, H = int(cams["W"][c]), int(cams["H"][c])
+        TX, TY = -(-W // P.tile), -(-H // P.tile)
+        x0 = int(np.clip(np.floor((mx - r) / P.tile), 0, TX))
+        x1 = int(np.clip(np.floor((mx + r) / P.tile) + 1, 0, TX))
+        y0 = int(np.clip(np.floor((my - r) / P.tile), 0, TY))
+        y1 = int(np.clip(np.floor((my + r) / P.tile) + 1, 0, TY))
+        out += [(c, tx, ty) for ty in range(y0, y1) for tx in range(x0, x1)]
+    return np.array(out, np.int32).reshape(-1, 3)
+
+
+def _pixels_of(tiles, cams, tile=16):
+    pix_off = np.concatenate([[0], np.cumsum(cams["W"].astype(np.int64) * cams["H"])])
+    idx = []
+    for c, tx, ty in tiles:
+        W, H = int(cams["W"][c]), int(cams["H"][c])
+        for y in range(ty * tile, min((ty + 1) * tile, H)):
+            idx.extend(pix_off[c] + y * W + np.arange(tx * tile, min((tx + 1) * tile, W)))
+    return np.array(idx, np.int64)
+
+
+def _proj_one(o, P, sc, cams, n):
+    return o.project(P, sc["means"][n:n + 1], sc["quats"][n:n + 1], sc["scales"][n:n + 1],
+                     sc["opacities"][n:n + 1], sc["sh"][n:n + 1], cams["viewmats"], cams["Ks"], cams["W"], cams["H"])
+
+
+def _splice(proj, one, n):
+    out = {k: v.copy() for k, v in proj.items()}
+    for k in out:
+        out[k][:, n] = one[k][:, 0]
+    return out
+
+
+def param_list(sc, n, g):
+    """(name, array key, index tuple) for the eight sampled parameters of
+    Gaussian n: mean x, y, z, one quaternion component, one scale axis,
+    opacity, one DC colour channel, one higher-band coefficient."""
+    out = [("mu_x", "means", (n, 0)), ("mu_y", "means", (n, 1)), ("mu_z", "means", (n, 2)),
+           ("quat", "quats", (n, int(g.integers(4)))), ("scale", "scales", (n, int(g.integers(3)))),
+           ("opacity", "opacities", (n,))]
+    if sc["sh"].ndim == 3:
+        out.append(("sh_dc", "sh", (n, 0, int(g.integers(3)))))
+        if sc["sh"].shape[1] > 1:
+            out.append(("sh_hi", "sh", (n, int(g.integers(1, sc["sh"].shape[1])), int(g.integers(3)))))
+    else:
+        out.append(("color", "sh", (n, int(g.integers(3)))))
+    return out
+
+
+_GRAD_KEY = {"means": "v_means", "quats": "v_quats", "scales": "v_scales", "opacities": "v_opacities",
+             "sh": "v_sh"}
+
+
+def fd_check(o, P, sc, cams, v_image, v_alpha=None, background=None, n_gauss=8, eps=1e-3, seed=0):
+    """Returns (rows, rejected): rows = [(name, n, fd, analytic)]."""
+    sc = {k: (np.array(v, np.float64) if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    proj, isect, ras = o.forward(P, sc, cams, background=background)
+    g2, g3 = o.backward(P, sc, cams, proj, isect, ras, v_image, v_alpha, background)
+    touched = np.nonzero(np.abs(g2["v_colors"]).sum(axis=(0, 2)) > 0)[0]
+    g = _sc.rng("cfg2", _sc.STREAM_FD, seed)
+    order = g.permutation(touched)
+    rows, rejected, used = [], 0, 0
+    for n in order:
+        if used >= n_gauss:
+            break
+        tiles = _rect_tiles(P, proj, n, cams)
+        pix = _pixels_of(tiles, cams, P.tile)
+        ok_any = False
+        for name, key, ix in param_list(sc, n, g):
+            arr = sc[key]
+            orig = arr[ix]
+            vals, sig = [], []
+            for s in (+1, -1):
+                arr[ix] = orig + s * eps
+                one = _proj_one(o, P, sc, cams, n)
+                pj = _splice(proj, one, n)
+                r = o.render_tiles_fwd(P, pj, sc["opacities"], tiles, cams["W"], cams["H"], background=background)
+                L = float(np.sum(v_image[pix] * r["image"][pix]))
+                if v_alpha is not None:
+                    L += float(np.sum(v_alpha[pix] * r["alpha"][pix]))
+                vals.append(L)
+                sig.append((one["radii"].tobytes(), _rect_tiles(P, pj, n, cams).tobytes(),
+                            r["trace"][pix].tobytes(), r["n_eval"][pix].tobytes(),
+                            (one["colors"] == 0).tobytes()))
+            arr[ix] = orig
+            base_sig = _rect_tiles(P, proj, n, cams).tobytes()
+            if sig[0] != sig[1] or sig[0][1] != base_sig:
+                rejected += 1
+                continue
+            fd = (vals[0] - vals[1]) / (2 * eps)
+            an = float(g3[_GRAD_KEY[key]][ix])
+            rows.append((name, int(n), fd, an))
+            ok_any = True
+        used += int(ok_any)
+    return rows, rejected

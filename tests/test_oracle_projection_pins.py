@@ -1,0 +1,258 @@
+"""Pins of the oracle's projection stage against closed forms, library
+routines, Monte Carlo and finite differences (no GPU).
+
+Forward Pass / Projection of Gaussians; Data Conventions; Anti-aliasing;
+Projection Gradients; Scale and rotation gradients.
+"""
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+from scipy.special import sph_harm_y
+
+from oracle import Oracle, OracleParams
+from oracle import defs
+from paper_2409_06765_amd import scenes
+from _util import one_gaussian_scene, simple_cam
+
+O64 = Oracle(np.float64)
+O32 = Oracle(np.float32)
+
+
+# ---------------------------------------------------------------- rotation
+def test_rotation_identity_and_axis_rotation():
+    P_ = O64.cov3d(np.array([1.0, 0, 0, 0]), np.ones(3))
+    Sig, R = P_
+    np.testing.assert_array_equal(R, np.eye(3))
+    th = 0.7
+    Rz = O64.cov3d(np.array([np.cos(th / 2), 0, 0, np.sin(th / 2)]), np.ones(3))[1]
+    textbook = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+    np.testing.assert_allclose(Rz, textbook, atol=1e-15)
+
+
+def test_rotation_matches_scipy_and_is_special_orthogonal():
+    g = np.random.default_rng(1)
+    for _ in range(50):
+        q = g.standard_normal(4) * g.uniform(0.2, 3.0)   # unnormalised on purpose
+        R = O64.cov3d(q, np.ones(3))[1]
+        # scipy uses scalar-last (x, y, z, w), Hamilton convention
+        Rs = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        np.testing.assert_allclose(R, Rs, atol=1e-13)
+        np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-13)
+        assert abs(np.linalg.det(R) - 1.0) < 1e-13
+
+
+def test_covariance_eigenvalues_are_squared_scales():
+    g = np.random.default_rng(2)
+    for _ in range(50):
+        q = g.standard_normal(4)
+        s = np.exp(g.normal(-2, 1, 3))
+        Sig = O64.cov3d(q, s)[0]
+        np.testing.assert_allclose(np.sort(np.linalg.eigvalsh(Sig)), np.sort(s ** 2), rtol=1e-10, atol=1e-14)
+
+
+# ---------------------------------------------------------------- SH
+def test_sh_basis_matches_scipy_complex_harmonics():
+    g = np.random.default_rng(3)
+    for _ in range(40):
+        d = g.standard_normal(3)
+        d /= np.linalg.norm(d)
+        Y, _ = O64.sh_basis(16, d)
+        polar, azim = np.arccos(d[2]), np.arctan2(d[1], d[0])
+        ref = []
+        for l in range(4):
+            for m in range(-l, l + 1):
+                Yc = sph_harm_y(l, abs(m), polar, azim)
+                ref.append(np.sqrt(2) * Yc.real if m > 0 else (np.sqrt(2) * Yc.imag if m < 0 else Yc.real))
+        np.testing.assert_allclose(Y, ref, atol=1e-12)
+
+
+def test_sh_orthonormal_by_quadrature():
+    n = 100_000
+    i = np.arange(n) + 0.5
+    z = 1 - 2 * i / n
+    phi = np.pi * (1 + 5 ** 0.5) * i
+    r = np.sqrt(1 - z * z)
+    pts = np.stack([r * np.cos(phi), r * np.sin(phi), z], 1)
+    Ys = np.array([O64.sh_basis(16, p)[0] for p in pts[::10]])   # 10k Fibonacci points
+    gram = 4 * np.pi * Ys.T @ Ys / Ys.shape[0]
+    np.testing.assert_allclose(gram, np.eye(16), atol=2e-3)
+
+
+def test_sh_gradient_by_finite_differences():
+    g = np.random.default_rng(4)
+    for _ in range(10):
+        d = g.standard_normal(3)
+        _, dY = O64.sh_basis(16, d)
+        eps = 1e-6
+        for j in range(3):
+            e = np.zeros(3)
+            e[j] = eps
+            fd = (O64.sh_basis(16, d + e)[0] - O64.sh_basis(16, d - e)[0]) / (2 * eps)
+            np.testing.assert_allclose(dY[:, j], fd, atol=1e-7)
+
+
+def test_sh_degree0_equals_direct_colour():
+    """DC = (rgb - 0.5) / Y00 reproduces the direct colour (SH reading)."""
+    sc = scenes.scene_tiny(32, sh_degree=-1, seed=5)
+    cams = scenes.cams_tiny()
+    Y00 = 0.5 / np.sqrt(np.pi)
+    sh0 = ((sc["sh"].astype(np.float64) - 0.5) / Y00)[:, None, :]
+    pd = O64.project(OracleParams(sh_degree=-1), sc["means"], sc["quats"], sc["scales"], sc["opacities"],
+                     sc["sh"], cams["viewmats"], cams["Ks"], cams["W"], cams["H"])
+    ps = O64.project(OracleParams(sh_degree=0), sc["means"], sc["quats"], sc["scales"], sc["opacities"],
+                     sh0, cams["viewmats"], cams["Ks"], cams["W"], cams["H"])
+    np.testing.assert_allclose(ps["colors"], pd["colors"], atol=1e-6)
+
+
+# ---------------------------------------------------------------- projection closed forms
+def _proj1(P, mean, scale, quat=(1, 0, 0, 0), W=64, H=64, f=50.0, cx=None, cy=None, o=O64):
+    sc = one_gaussian_scene(mean, quat=quat, scale=scale)
+    cam = simple_cam(W, H, f, cx, cy)
+    return o.project(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cam["viewmats"],
+                     cam["Ks"], cam["W"], cam["H"])
+
+
+def test_point_on_optical_axis_maps_to_principal_point():
+    p = _proj1(OracleParams(), (0.0, 0.0, 3.0), (0.1, 0.1, 0.1), cx=31.25, cy=17.5)
+    np.testing.assert_array_equal(p["means2d"][0, 0], [31.25, 17.5])
+    assert p["depths"][0, 0] == 3.0
+
+
+@pytest.mark.parametrize("d,s,f", [(2.0, 0.05, 50.0), (5.0, 0.3, 120.0), (1.0, 0.01, 30.0), (8.0, 0.9, 400.0)])
+def test_radius_of_isotropic_gaussian_on_axis(d, s, f):
+    P = OracleParams()
+    p = _proj1(P, (0.0, 0.0, d), (s, s, s), f=f, W=2048, H=2048)
+    d, s, f = (float(np.float32(x)) for x in (d, s, f))   # the scene is stored in float32
+    expect = int(np.ceil(3 * np.sqrt((f * s / d) ** 2 + P.eps2d)))
+    assert p["radii"][0, 0] == expect
+    # conic = inverse of the dilated isotropic covariance
+    v = (f * s / d) ** 2 + P.eps2d
+    np.testing.assert_allclose(p["conics"][0, 0], [1 / v, 0.0, 1 / v], rtol=1e-12, atol=1e-18)
+
+
+def test_ewa_covariance_matches_monte_carlo():
+    """Project samples of a small, distant Gaussian exactly through the
+    pinhole; their covariance approaches J R Sigma R^T J^T."""
+    g = np.random.default_rng(6)
+    P = OracleParams(jac_clamp=0.0)
+    mean = np.array([0.4, -0.3, 6.0])
+    q = g.standard_normal(4)
+    s = np.array([0.03, 0.012, 0.02])
+    f, W, H = 400.0, 512, 512
+    sc = one_gaussian_scene(mean, quat=q, scale=s)
+    ang = 0.3
+    V = np.eye(4)
+    V[:3, :3] = Rotation.from_rotvec([0.1, ang, -0.2]).as_matrix()
+    V[:3, 3] = [0.2, 0.1, 0.5]
+    cam = simple_cam(W, H, f, viewmat=V)
+    sc64 = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    sc64["means"] = mean[None]
+    sc64["quats"] = q[None]
+    sc64["scales"] = s[None]
+    p = O64.project(P, sc64["means"], sc64["quats"], sc64["scales"], sc64["opacities"], sc64["sh"],
+                    V[None], cam["Ks"].astype(np.float64), cam["W"], cam["H"])
+    a, b, c = p["conics"][0, 0]
+    cov_d = np.linalg.inv(np.array([[a, b], [b, c]]))
+    cov = cov_d - P.eps2d * np.eye(2)
+    R = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    Sig = R @ np.diag(s ** 2) @ R.T
+    X = g.multivariate_normal(mean, Sig, 2_000_000)
+    t = X @ V[:3, :3].T + V[:3, 3]
+    uv = np.stack([f * t[:, 0] / t[:, 2] + W / 2, f * t[:, 1] / t[:, 2] + H / 2], 1)
+    emp = np.cov(uv.T)
+    np.testing.assert_allclose(cov, emp, rtol=1e-2, atol=1e-2 * np.abs(emp).max())
+    np.testing.assert_allclose(p["means2d"][0, 0], uv.mean(0), atol=2e-2)
+
+
+def test_projection_matches_numpy_definition():
+    """C oracle vs the float64 NumPy statement (inv, eigvalsh, scipy SH)."""
+    for deg in (-1, 3):
+        P = OracleParams(sh_degree=deg)
+        sc = scenes.scene_tiny(80, sh_degree=deg, seed=7, log_scale_mean=-2.0)
+        cams = scenes.cams_tiny(W=70, H=50, f=55.0, n_cams=2, seed=7)
+        p = O64.project(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],
+                        cams["Ks"], cams["W"], cams["H"])
+        for c in range(2):
+            d = defs.project(P, sc["means"], sc["quats"], sc["scales"], sc["sh"], cams["viewmats"][c],
+                             cams["Ks"][c], int(cams["W"][c]), int(cams["H"][c]))
+            np.testing.assert_array_equal(p["radii"][c] > 0, d["valid"])
+            np.testing.assert_array_equal(p["radii"][c], d["radius"])
+            v = d["valid"]
+            assert v.sum() > 10
+            np.testing.assert_allclose(p["means2d"][c][v], d["mean2d"][v], rtol=1e-12)
+            np.testing.assert_allclose(p["conics"][c][v], d["conic"][v], rtol=1e-9)
+            np.testing.assert_allclose(p["depths"][c][v], d["depth"][v], rtol=1e-13)
+            np.testing.assert_allclose(p["colors"][c][v], d["color"][v], atol=1e-12)
+
+
+def test_near_plane_is_strict_and_culls():
+    P = OracleParams()
+    p = _proj1(P, (0.0, 0.0, np.float32(0.01)), (0.5, 0.5, 0.5), o=O32)
+    assert p["radii"][0, 0] > 0                # t_z == near renders
+    p = _proj1(P, (0.0, 0.0, 0.009), (0.5, 0.5, 0.5), o=O32)
+    assert p["radii"][0, 0] == 0               # in front of the near plane: culled
+    assert np.all(p["conics"] == 0) and np.all(p["means2d"] == 0)
+
+
+def test_offscreen_gaussian_has_zero_radius():
+    p = _proj1(OracleParams(), (3.0, 0.0, 2.0), (0.01, 0.01, 0.01))   # x' = 50*1.5+32 = 107 > 64 + r
+    assert p["radii"][0, 0] == 0
+
+
+def test_antialiased_compensation_closed_form():
+    P = OracleParams(antialiased=1)
+    d, s, f = 4.0, 0.02, 100.0
+    p = _proj1(P, (0.0, 0.0, d), (s, s, s), f=f)
+    s = float(np.float32(s))
+    v = (f * s / d) ** 2
+    np.testing.assert_allclose(p["comps"][0, 0], v / (v + P.eps2d), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- projection gradients by FD
+def _proj_loss(P, sc, cams, w):
+    p = O64.project(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],
+                    cams["Ks"], cams["W"], cams["H"])
+    L = (np.sum(w["m"] * p["means2d"]) + np.sum(w["c"] * p["conics"]) + np.sum(w["col"] * p["colors"])
+         + np.sum(w["d"] * p["depths"]) + np.sum(w["o"] * p["comps"] * sc["opacities"][None, :]))
+    return L, p
+
+
+@pytest.mark.parametrize("deg,aa,jc", [(3, 0, 1.3), (-1, 0, 0.0), (2, 1, 1.3)])
+def test_projection_gradients_match_central_differences(deg, aa, jc):
+    P = OracleParams(sh_degree=deg, antialiased=aa, jac_clamp=jc)
+    sc = scenes.scene_tiny(24, sh_degree=deg, seed=11, log_scale_mean=-2.0)
+    sc = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    cams = scenes.cams_tiny(W=80, H=60, f=60.0, n_cams=2, seed=11)
+    C, N = 2, 24
+    g = np.random.default_rng(12)
+    w = dict(m=g.standard_normal((C, N, 2)), c=g.standard_normal((C, N, 3)) * 10,
+             col=g.standard_normal((C, N, 3)), d=g.standard_normal((C, N)), o=g.standard_normal((C, N)))
+    L0, p0 = _proj_loss(P, sc, cams, w)
+    vo_cn = w["o"]   # gradient w.r.t. the opacity the rasterizer uses (o * comp)
+    gr = O64.project_bwd(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],
+                         cams["Ks"], cams["W"], cams["H"], w["m"], w["c"], w["col"], vo_cn, v_depths=w["d"])
+    names = [("means", "v_means"), ("quats", "v_quats"), ("scales", "v_scales"), ("opacities", "v_opacities"),
+             ("sh", "v_sh")]
+    checked = 0
+    for key, gkey in names:
+        arr = sc[key]
+        flat = arr.reshape(-1)
+        idx = g.choice(flat.size, size=min(24, flat.size), replace=False)
+        for i in idx:
+            eps = 1e-6 * max(1.0, abs(flat[i]))
+            orig = flat[i]
+            flat[i] = orig + eps
+            Lp, pp = _proj_loss(P, sc, cams, w)
+            flat[i] = orig - eps
+            Lm, pm = _proj_loss(P, sc, cams, w)
+            flat[i] = orig
+            if not (np.array_equal(pp["radii"], p0["radii"]) and np.array_equal(pm["radii"], p0["radii"])):
+                continue
+            if not (np.array_equal(pp["colors"] == 0, p0["colors"] == 0)
+                    and np.array_equal(pm["colors"] == 0, p0["colors"] == 0)):
+                continue
+            fd = (Lp - Lm) / (2 * eps)
+            an = gr[gkey].reshape(-1)[i]
+            assert abs(fd - an) <= 1e-5 * max(1.0, abs(fd)), (key, i, fd, an)
+            checked += 1
+    assert checked > 60
