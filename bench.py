@@ -1,0 +1,228 @@
+"""Benchmark: forward + backward of the tile rasterizer, one view per step.
+
+Workload (default): 1,000,000 Gaussians in 32 clusters with degree-3 SH,
+rendered at 1920x1080 (fx = fy = 1500) from 16 viewpoints on a radius-6
+sphere; a step is the whole hot path for one view: projection, tile binning
+(count, scan, the one host wait for the intersection count), key emission,
+radix sort, tile ranges, forward compositing, backward compositing and the
+projection backward.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  value = Gaussian-pixel evaluations per second over the
+whole step (forward evaluations + backward evaluations, counted exactly by an
+untimed pass of the same views); ms_per_step = ms per forward+backward view.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms per fwd+bwd view and Gaussian-pixel evals/s @1M Gaussians 1080p; p99 serve latency"
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 4 SIMD x 16 lanes x 2 FMA x 2 packed x 2.4 GHz)
+PEAK_HBM_GBS = 8000.0
+# Algorithmic floating-point operations of the compositing formulas (an exp,
+# a min and a reciprocal count as one each; compares count as none):
+#   every evaluated entry: Delta (2), sigma (9), o exp(-sigma) (2), min (1)       = 14
+#   forward, composited:   1 - alpha, T (1 - alpha), alpha T, colour += (6)      =  9
+#   backward, composited:  1 - alpha, 1/(1-alpha), T_k, alpha T_k (4), dL/dc (3),
+#                          dL/dalpha (15 + 3), S += (6), dL/do, dL/dsigma (2),
+#                          dL/dmu' (8), dL/dconic (8)                             = 49
+FLOPS_EVAL, FLOPS_FWD_COMP, FLOPS_BWD_COMP = 14, 9, 49
+
+WORKLOADS = {
+    "cfg3": dict(desc="1M Gaussians, 32 clusters, SH degree 3, 1920x1080, fx=fy=1500, 16 views on a radius-6 sphere",
+                 scene="scene_cfg3", cams="cams_cfg3", sh_degree=3),
+    "cfg2": dict(desc="100k Gaussians, SH degree 3, 800x800, fx=fy=1100, one view on a radius-4 sphere",
+                 scene="scene_cfg2", cams="cams_cfg2", sh_degree=3),
+    "cfg4": dict(desc="3M Gaussians (2.4M in a 20x20x5 box + 0.6M on a radius-50 shell), SH degree 3, 1920x1080, "
+                      "fx=fy=1200, 4 views from inside the box",
+                 scene="scene_cfg4", cams="cams_cfg4", sh_degree=3),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg3", choices=list(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-tiles", type=int, default=96, help="tiles of view 0 the oracle rasterizes")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note, "
+              f"not an implemented path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2409_06765_amd import rasterize as R
+    from paper_2409_06765_amd import scenes
+
+    wl = WORKLOADS[args.workload]
+    dev = "cuda:0"
+    t0 = time.time()
+    sc = getattr(scenes, wl["scene"])()
+    cams = getattr(scenes, wl["cams"])()
+    n_views = len(cams["W"])
+    log(f"workload {args.workload}: N={sc['means'].shape[0]} views={n_views} generated in {time.time() - t0:.1f}s")
+    d = {k: torch.from_numpy(v).to(dev) for k, v in sc.items() if isinstance(v, np.ndarray)}
+    vms = torch.from_numpy(cams["viewmats"]).to(dev)
+    Kss = torch.from_numpy(cams["Ks"]).to(dev)
+    W, H = int(cams["W"][0]), int(cams["H"][0])
+    npix = W * H
+    v_image_np, _ = scenes.upstream_grads(args.workload, npix, seed=0)
+    v_image = torch.from_numpy(v_image_np).to(dev)
+    p = R.make_params(sh_degree=wl["sh_degree"])
+
+    def step(v, timing=None, n_eval=False):
+        vm, Ks = vms[v:v + 1], Kss[v:v + 1]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)] if timing is not None else None
+        if ev: ev[0].record()
+        proj = R.project(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, [W], [H])
+        if ev: ev[1].record()
+        isect = R.intersect(p, proj, [W], [H])
+        if ev: ev[2].record()
+        fwd = R.rasterize_forward(p, proj, d["opacities"], isect, [W], [H], None, n_eval=n_eval)
+        if ev: ev[3].record()
+        g2 = R.rasterize_backward(p, proj, d["opacities"], isect, [W], [H], fwd, v_image)
+        if ev: ev[4].record()
+        g3 = R.project_backward(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, [W], [H],
+                                proj, g2)
+        if ev:
+            ev[5].record()
+            timing.append((ev, isect["M"]))
+        return proj, isect, fwd, g2, g3
+
+    # exact evaluation counts (untimed pass over the views the timed loop uses)
+    views = [i % n_views for i in range(args.steps)]
+    counts = {}
+    for v in sorted(set(views)):
+        proj, isect, fwd, _, _ = step(v, n_eval=True)
+        ne = fwd["n_eval"].to(torch.int64)
+        last = fwd["last_ids"].to(torch.int64)
+        pix = torch.arange(npix, device=dev)
+        tile = (pix // W // 16) * ((W + 15) // 16) + (pix % W) // 16
+        start = isect["ranges"][tile, 0].to(torch.int64)
+        e_bwd = torch.where(last >= 0, last - start + 1, torch.zeros_like(last)).sum()
+        counts[v] = dict(E_fwd=int(ne[:, 0].sum()), C=int(ne[:, 1].sum()), E_bwd=int(e_bwd), M=isect["M"])
+    torch.cuda.synchronize()
+    log(f"counts view 0: {counts[views[0]]}")
+
+    for i in range(args.warmup):
+        step(views[i % len(views)])
+    torch.cuda.synchronize()
+
+    timing = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for v in views:
+        step(v, timing)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_start
+
+    stage_names = ["project_fwd", "intersect", "rasterize_fwd", "rasterize_bwd", "project_bwd"]
+    stage_ms = {k: 0.0 for k in stage_names}
+    for ev, _ in timing:
+        for i, k in enumerate(stage_names):
+            stage_ms[k] += ev[i].elapsed_time(ev[i + 1]) / len(timing)
+    ms_per_step = 1e3 * t_wall / args.steps
+    E_fwd = sum(counts[v]["E_fwd"] for v in views)
+    E_bwd = sum(counts[v]["E_bwd"] for v in views)
+    C_tot = sum(counts[v]["C"] for v in views)
+    value = (E_fwd + E_bwd) / t_wall
+
+    # dominant kernel: the backward compositing (VALU-bound)
+    bwd_flops = (FLOPS_EVAL * E_bwd + FLOPS_BWD_COMP * C_tot) / args.steps
+    bwd_ms = stage_ms["rasterize_bwd"]
+    achieved = bwd_flops / (bwd_ms * 1e-3) / 1e12
+    fwd_flops = (FLOPS_EVAL * E_fwd + FLOPS_FWD_COMP * C_tot) / args.steps
+    fwd_tflops = fwd_flops / (stage_ms["rasterize_fwd"] * 1e-3) / 1e12
+    roofline = {"kernel": "raster_bwd_kernel", "bound": "alu", "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": None}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gaussian-pixel evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded generators, activated parameters)",
+        "config": {"workload": f"{args.workload}: {wl['desc']}", "views_timed": args.steps, "width": W, "height": H,
+                   "n_gaussians": int(sc["means"].shape[0])},
+        "ms_per_view": ms_per_step,
+        "views_per_s": args.steps / t_wall,
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "evals": {"E_fwd_per_view": E_fwd / args.steps, "E_bwd_per_view": E_bwd / args.steps,
+                  "composited_per_view": C_tot / args.steps,
+                  "M_per_view": sum(counts[v]["M"] for v in views) / args.steps},
+        "evals_per_s_raster": (E_fwd + E_bwd) / (1e-3 * args.steps * (stage_ms["rasterize_fwd"] + stage_ms["rasterize_bwd"])),
+        "raster_fwd_tflops": round(fwd_tflops, 3),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, cams, wl, args, counts, views[0])
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(sc, cams, wl, args, counts, v0):
+    """The oracle (single-threaded C, float32) on view 0: full projection,
+    binning and sort, then forward + backward compositing of a sample of
+    tiles; the compositing time is scaled by the evaluation counts."""
+    from oracle import Oracle, OracleParams
+    from paper_2409_06765_amd import scenes
+
+    o = Oracle(np.float32)
+    P = OracleParams(sh_degree=wl["sh_degree"])
+    one = {k: v[v0:v0 + 1] for k, v in cams.items()}
+    W, H = int(one["W"][0]), int(one["H"][0])
+    t0 = time.perf_counter()
+    proj = o.project(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], one["viewmats"],
+                     one["Ks"], one["W"], one["H"])
+    t1 = time.perf_counter()
+    isect = o.intersect(P, proj, one["W"], one["H"])
+    t2 = time.perf_counter()
+    TX, TY = (W + 15) // 16, (H + 15) // 16
+    g = np.random.default_rng(0)
+    lens = isect["ranges"][:, 1] - isect["ranges"][:, 0]
+    busy = np.nonzero(lens > 0)[0]
+    pick = g.choice(busy, size=min(args.cpu_sample_tiles, busy.size), replace=False)
+    mask = np.zeros(TX * TY, np.uint8)
+    mask[pick] = 1
+    ras = o.rasterize_fwd(P, proj, sc["opacities"], isect["ranges"], isect["ids"], one["W"], one["H"], tile_mask=mask)
+    t3 = time.perf_counter()
+    v_image, _ = scenes.upstream_grads(args.workload, W * H, seed=0)
+    o.rasterize_bwd(P, proj, sc["opacities"], isect["ranges"], isect["ids"], one["W"], one["H"], ras["final_T"],
+                    ras["last_ids"], v_image, tile_mask=mask)
+    t4 = time.perf_counter()
+    # evaluation counts of the sample (same definitions as the GPU counts)
+    pixmask = np.zeros(W * H, bool)
+    ys, xs = np.divmod(np.arange(W * H), W)
+    pixmask = mask[(ys // 16) * TX + xs // 16] == 1
+    start = isect["ranges"][(ys // 16) * TX + xs // 16, 0]
+    last = ras["last_ids"]
+    e_fwd_s = int(ras["n_eval"][pixmask].sum())
+    e_bwd_s = int(np.where(last >= 0, last - start + 1, 0)[pixmask].sum())
+    E_view = counts[v0]["E_fwd"] + counts[v0]["E_bwd"]
+    scale = E_view / max(e_fwd_s + e_bwd_s, 1)
+    t_view = (t1 - t0) + (t2 - t1) + (t4 - t2) * scale
+    return {"value": E_view / t_view, "unit": "Gaussian-pixel evals/s", "cores": 1, "kind": "oracle",
+            "ms_per_view_est": 1e3 * t_view,
+            "sample": f"view 0: projection of all {sc['means'].shape[0]} Gaussians ({1e3 * (t1 - t0):.0f} ms), "
+                      f"binning + qsort of M={isect['M']} ({1e3 * (t2 - t1):.0f} ms), forward+backward compositing "
+                      f"of {mask.sum()} of {TX * TY} tiles ({1e3 * (t4 - t2):.0f} ms, {e_fwd_s + e_bwd_s} evals), "
+                      f"scaled by evaluations x{scale:.1f}; single thread, float32, gcc -O2"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,218 @@
+/*
+ * gsraster.h -- C ABI of the MI355X (gfx950) differentiable tile rasterizer
+ * for 3D Gaussian Splatting, following the forward and backward passes of
+ * gsplat (arXiv 2409.06765, appendices "Forward Pass", "Backward Pass",
+ * "Data Conventions", "Anti-aliasing").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Pointers.  Every tensor pointer is a DEVICE pointer (for instance a torch
+ *   HIP tensor's data_ptr()), contiguous, row-major.  The only host pointers
+ *   are the gsr_params struct, the per-camera image sizes W[C] and H[C], and
+ *   the optional total_host output of gsr_intersect_count.
+ * Types.  Floating point is float32; per-Gaussian indices and counts are
+ *   int32; prefix offsets are int64; sort keys are uint64.
+ * Layout.  C cameras (views), N Gaussians.  Per-view projected arrays are
+ *   [C, N, ...]; a projected Gaussian is addressed by its flat id c*N + n
+ *   (C*N must be below 2^31).  Images are packed per camera: pixel (c, y, x)
+ *   is element pix_off[c] + y*W[c] + x with pix_off[c] = sum_{c'<c} W[c']H[c'];
+ *   for equal sizes that is [C, H, W, ...].  Tiles are 16x16 pixels, numbered
+ *   row-major inside a camera and offset by tile_base[c] = sum_{c'<c}
+ *   ceil(W/16) ceil(H/16), so global tile ids of all cameras are disjoint.
+ * Ownership.  The caller allocates and owns every buffer; the library keeps
+ *   no pointer after a call returns and allocates no device memory.  Scratch
+ *   space is passed in as a workspace sized by gsr_workspace_bytes().
+ * Streams.  Every call takes a hipStream_t (passed as void*, NULL = the null
+ *   stream), enqueues its kernels and returns without waiting, except
+ *   gsr_intersect_count with a non-NULL total_host, which waits for the
+ *   8-byte intersection count.
+ * Errors.  Every call returns GSR_OK (0) or an error code; arguments are
+ *   checked before anything is enqueued, so an error leaves outputs
+ *   untouched.  gsr_last_error() returns a message for the calling thread.
+ *   No C++ exception crosses this boundary.
+ * Limits.  At most GSR_MAX_CAMERAS cameras per call; 1 <= W, H <= 16384;
+ *   tile must be 16; sh_degree in -1..3; C*N < 2^31; intersections M < 2^31.
+ */
+#ifndef GSRASTER_H
+#define GSRASTER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSR_ABI_VERSION 1
+#define GSR_MAX_CAMERAS 64
+
+enum gsr_status {
+    GSR_OK = 0,
+    GSR_EINVAL = 1,      /* an argument is out of range or a required pointer is NULL */
+    GSR_EOVERFLOW = 2,   /* intersections exceed the capacity passed in               */
+    GSR_EWORKSPACE = 3,  /* workspace smaller than gsr_workspace_bytes()              */
+    GSR_EHIP = 4         /* a HIP launch or runtime call failed                       */
+};
+
+/* Rasterizer constants.  Defaults (gsr_default_params): near 0.01, far +inf,
+ * eps2d 0.3, jac_clamp 1.3, alpha_min 1/255, alpha_max 0.99, T_min 1e-4,
+ * tile 16, sh_degree -1, antialiased 0. */
+typedef struct gsr_params {
+    float near_plane;   /* cull when the camera-space depth t_z < near_plane          */
+    float far_plane;    /* cull when t_z > far_plane                                   */
+    float eps2d;        /* low-pass dilation s added to the diagonal of Sigma'         */
+    float jac_clamp;    /* > 0: t_x/t_z, t_y/t_z clamped to +-jac_clamp*(W/2)/f in J   */
+    float alpha_min;    /* a Gaussian is skipped at a pixel when alpha < alpha_min      */
+    float alpha_max;    /* alpha = min(alpha_max, o exp(-sigma))                        */
+    float T_min;        /* a pixel stops before the Gaussian that would take T below it */
+    int32_t tile;       /* tile edge in pixels; must be 16                              */
+    int32_t sh_degree;  /* -1: direct colours [N,3]; 0..3: SH coefficients [N,(d+1)^2,3] */
+    int32_t antialiased;/* 1: opacity times sqrt(|Sigma'| / |Sigma' + eps2d I|)         */
+} gsr_params;
+
+typedef void *gsr_stream_t;   /* a hipStream_t */
+
+enum gsr_op {
+    GSR_OP_INTERSECT_COUNT = 1,   /* workspace of gsr_intersect_count for C*N entries */
+    GSR_OP_SORT = 2               /* workspace of gsr_sort_pairs for M pairs          */
+};
+
+int gsr_abi_version(void);
+const char *gsr_last_error(void);
+void gsr_default_params(gsr_params *p);
+
+/* Bytes of workspace the operation needs (0 if none); C, N, M as in the call. */
+size_t gsr_workspace_bytes(int op, int C, int N, int64_t M);
+
+/* Projection of Gaussians (Forward Pass, Projection; Data Conventions;
+ * Anti-aliasing).  For every camera c and Gaussian n:
+ *   t = R_cw mu + t_cw (viewmats [C,4,4] world->camera, OpenCV axes),
+ *   culled when t_z < near or t_z > far;
+ *   Sigma = R(q/|q|) diag(s)^2 R(q/|q|)^T (quats [N,4] as w,x,y,z, scales [N,3]
+ *   already activated);  T = J R_cw with J the pinhole Jacobian at t (its
+ *   t_x/t_z, t_y/t_z clamped by jac_clamp);  Sigma' = T Sigma T^T + eps2d I;
+ *   conic = entries (a, b, c) of Sigma'^-1;  radius = ceil(3 sqrt(lambda_max));
+ *   means2d = (fx t_x/t_z + cx, fy t_y/t_z + cy) with fx = K[0][0],
+ *   fy = K[1][1], cx = K[0][2], cy = K[1][2] (Ks [C,3,3]);  depth = t_z;
+ *   colour = max(SH(dir) + 0.5, 0) with dir the unit vector from the camera
+ *   centre to mu, or the direct colour when sh_degree = -1.
+ * A Gaussian is culled (radius 0, all outputs 0) also when Sigma' is not
+ * positive definite or its tile rectangle misses the image.
+ * Outputs: means2d [C,N,2], conics [C,N,3], radii [C,N] int32, depths [C,N],
+ * colors [C,N,3], compensations [C,N] (nullable; 1 unless antialiased).
+ * opacities [N] is not read (kept for a uniform argument list). */
+int gsr_project_fwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
+                    const float *means, const float *quats, const float *scales, const float *opacities,
+                    const float *sh_or_colors, const float *viewmats, const float *Ks,
+                    float *means2d, float *conics, int32_t *radii, float *depths, float *colors,
+                    float *compensations, gsr_stream_t stream);
+
+/* Tile binning (Rasterization of Gaussians, first step): the 16x16 tiles
+ * met by the square box [mu' - r, mu' + r] of each projected Gaussian, as the
+ * rectangle x0 = clamp(floor((mu'_x - r)/16), 0, TX), x1 = clamp(floor((mu'_x
+ * + r)/16) + 1, 0, TX) (same in y).  Writes tiles_per_gauss [C,N] int32
+ * (0 when radius is 0), their exclusive prefix sum offsets [C,N] int64, and
+ * the total M into total_dev (device int64[1]).  When total_host is not NULL
+ * the call also copies M to *total_host and waits for the stream.
+ * ws: workspace of gsr_workspace_bytes(GSR_OP_INTERSECT_COUNT, C, N, 0). */
+int gsr_intersect_count(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
+                        const float *means2d, const int32_t *radii, int32_t *tiles_per_gauss,
+                        int64_t *offsets, int64_t *total_dev, int64_t *total_host,
+                        void *ws, size_t ws_bytes, gsr_stream_t stream);
+
+/* One (key, id) per (Gaussian, tile): for the j-th tile of Gaussian g's
+ * rectangle in row-major order, keys[offsets[g] + j] = (global tile id << 32)
+ * | float bits of depth[g], ids[offsets[g] + j] = g (= c*N + n).  Depths are
+ * positive, so the bit order is the numeric order.  M_capacity is the length
+ * of keys/ids: pass the M of gsr_intersect_count; entries at or beyond it are
+ * never written. */
+int gsr_intersect_emit(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
+                       const float *means2d, const int32_t *radii, const float *depths,
+                       const int64_t *offsets, int64_t M_capacity, uint64_t *keys, int32_t *ids,
+                       gsr_stream_t stream);
+
+/* Stable LSD radix sort of M (key, id) pairs by the low key_bits bits of the
+ * keys (key_bits in 1..64; 32 + ceil(log2(total tiles)) suffices).  Ties keep
+ * their input order, so the emitted lists end up ordered by (tile, depth, id)
+ * (per-tile depth sort of Rasterization of Gaussians).  The sorted result is
+ * in keys/ids; keys_alt/ids_alt [M] are scratch.
+ * ws: workspace of gsr_workspace_bytes(GSR_OP_SORT, 0, 0, M). */
+int gsr_sort_pairs(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uint64_t *keys_alt,
+                   int32_t *ids_alt, void *ws, size_t ws_bytes, gsr_stream_t stream);
+
+/* ranges [total_tiles, 2] int32: [start, end) of each tile's run in the
+ * sorted keys; (0, 0) for an empty tile.  Keys must be sorted. */
+int gsr_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_t *ranges,
+                    gsr_stream_t stream);
+
+/* Front-to-back compositing (Rasterization of Gaussians).  For every pixel
+ * with centre p = (x + 0.5, y + 0.5), over its tile's sorted list:
+ *   Delta = mu' - p;  sigma = 0.5 (a Dx^2 + c Dy^2) + b Dx Dy (skipped if < 0);
+ *   alpha = min(alpha_max, o exp(-sigma)) with o = opacities[n] (times
+ *   compensations[c*N+n] when antialiased); skipped if alpha < alpha_min;
+ *   T' = T (1 - alpha); if T' < T_min the pixel stops here, without this one;
+ *   otherwise C += colour alpha T, T = T'.
+ * Finally C += T background[c] (background [C,3], NULL = black).
+ * Outputs: image [P,3], alpha [P] = 1 - T, final_T [P] = T, last_ids [P] int32
+ * (position in the sorted list of the last composited entry, -1 if none),
+ * n_eval [P,2] int32 (nullable): per pixel, the entries evaluated (including
+ * the one that stopped it) and the entries composited. */
+int gsr_rasterize_fwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
+                      const float *means2d, const float *conics, const float *colors,
+                      const float *opacities, const float *compensations, const float *background,
+                      const int32_t *ranges, const int32_t *ids, float *image, float *alpha,
+                      float *final_T, int32_t *last_ids, int32_t *n_eval, gsr_stream_t stream);
+
+/* Depth Compositing Gradients.  Per pixel, from last_ids back to its tile's
+ * start, recomputes alpha, restores T_k = T_{k+1} / (1 - alpha_k) from final_T,
+ * keeps S = sum of colour alpha T behind entry k plus final_T background, and
+ * accumulates
+ *   dL/dcolour += alpha T v_C;
+ *   dL/dalpha = sum_ch (colour T - S/(1 - alpha)) v_C + v_alpha final_T/(1 - alpha);
+ *   unless alpha was clamped at alpha_max:
+ *     dL/do += exp(-sigma) dL/dalpha,  dL/dsigma = -o exp(-sigma) dL/dalpha,
+ *     dL/dmu' += dL/dsigma Sigma'^-1 Delta,
+ *     dL/d(a, b, c) += dL/dsigma (Dx^2/2, Dx Dy, Dy^2/2).
+ * v_image [P,3], v_alpha [P] (nullable).  Outputs, overwritten: v_means2d
+ * [C,N,2], v_conics [C,N,3], v_colors [C,N,3], v_opacities [C,N] (gradient
+ * with respect to the opacity the rasterizer used, o times compensation),
+ * v_means2d_abs [C,N,2] (nullable: per-pixel absolute values of the mu'
+ * gradient summed, the absgrad statistic).  Sums use float atomics, so their
+ * rounding order is not fixed. */
+int gsr_rasterize_bwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
+                      const float *means2d, const float *conics, const float *colors,
+                      const float *opacities, const float *compensations, const float *background,
+                      const int32_t *ranges, const int32_t *ids, const float *final_T,
+                      const int32_t *last_ids, const float *v_image, const float *v_alpha,
+                      float *v_means2d, float *v_conics, float *v_colors, float *v_opacities,
+                      float *v_means2d_abs, gsr_stream_t stream);
+
+/* Projection Gradients, Scale and rotation gradients, SH backward.  Per
+ * Gaussian, summed over the C cameras (no atomics: one thread per Gaussian):
+ *   dL/dSigma' = -Y G Y with Y = Sigma'^-1, G = [[g_a, g_b/2], [g_b/2, g_c]];
+ *   dL/dSigma = T^T dL/dSigma' T;  dL/dT = 2 dL/dSigma' T Sigma;  dL/dJ =
+ *   dL/dT R_cw^T;  dL/dt from mu', from J (clamped coordinates follow t_z) and
+ *   from v_depths;  dL/dmu = R_cw^T dL/dt plus the SH direction term;
+ *   dL/dM = 2 dL/dSigma M;  dL/dR = dL/dM S^T;  dL/ds_j = (R^T dL/dM)_jj;
+ *   dL/dq through dR/dq and the normalisation q/|q|;  dL/dSH_k = Y_k(dir)
+ *   dL/dcolour (zero where the colour clamp at 0 is active).
+ * Inputs: the gsr_project_fwd inputs, its radii and compensations
+ * (nullable unless antialiased), and the per-camera gradients v_means2d,
+ * v_conics, v_colors, v_opacities_cn [C,N] (from gsr_rasterize_bwd),
+ * v_depths [C,N] (nullable).  Outputs, overwritten: v_means [N,3],
+ * v_quats [N,4], v_scales [N,3], v_opacities [N], v_sh_or_colors (shape of
+ * sh_or_colors). */
+int gsr_project_bwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
+                    const float *means, const float *quats, const float *scales, const float *opacities,
+                    const float *sh_or_colors, const float *viewmats, const float *Ks,
+                    const int32_t *radii, const float *compensations,
+                    const float *v_means2d, const float *v_conics, const float *v_colors,
+                    const float *v_opacities_cn, const float *v_depths,
+                    float *v_means, float *v_quats, float *v_scales, float *v_opacities,
+                    float *v_sh_or_colors, gsr_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSRASTER_H */

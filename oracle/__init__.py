@@ -192,7 +192,8 @@ class Oracle:
         npix = int(np.sum(Wa.astype(np.int64) * Ha))
         dt = self.dtype
         return dict(image=np.zeros((npix, 3), dt), alpha=np.zeros(npix, dt), final_T=np.zeros(npix, dt),
-                    n_eval=np.zeros(npix, np.int32), flags=np.zeros(npix, np.uint8),
+                    n_eval=np.zeros(npix, np.int32), n_comp=np.zeros(npix, np.int32),
+                    flags=np.zeros(npix, np.uint8),
                     trace=np.zeros(npix, np.uint32))
 
     def rasterize_fwd(self, P, proj, opacities, ranges, ids, W, H, background=None, tile_mask=None):
@@ -209,7 +210,8 @@ class Oracle:
                                    _p(self._r(opacities)), _p(comps), _p(self._r(background)),
                                    _p(np.ascontiguousarray(ranges, np.int32)), _p(np.ascontiguousarray(ids, np.int32)),
                                    _p(tm), _p(out["image"]), _p(out["alpha"]), _p(out["final_T"]),
-                                   _p(out["last_ids"]), _p(out["n_eval"]), _p(out["flags"]), _p(out["trace"]))
+                                   _p(out["last_ids"]), _p(out["n_eval"]), _p(out["n_comp"]), _p(out["flags"]),
+                                   _p(out["trace"]))
         return out
 
     def rasterize_bwd(self, P, proj, opacities, ranges, ids, W, H, final_T, last_ids, v_image,
@@ -252,8 +254,8 @@ class Oracle:
                                       _p(self._r(proj["depths"])), _p(self._r(background)),
                                       tiles.shape[0], _p(tiles), int(bool(untiled)), _p(out["image"]),
                                       _p(out["alpha"]), _p(out["final_T"]), _p(out["last_gid"]),
-                                      _p(out["last_pos"]), _p(out["n_eval"]), _p(out["flags"]),
-                                      _p(out["trace"]), _p(out["list_len"]))
+                                      _p(out["last_pos"]), _p(out["n_eval"]), _p(out["n_comp"]),
+                                      _p(out["flags"]), _p(out["trace"]), _p(out["list_len"]))
         return out
 
     def render_tiles_bwd(self, P, proj, opacities, tiles, W, H, v_image, v_alpha=None, background=None):

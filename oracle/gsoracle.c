@@ -599,7 +599,7 @@ int orc_rasterize_fwd(const orc_params *P, int C, int N, const int *W, const int
                       const REAL *means2d, const REAL *conics, const REAL *colors, const REAL *opacities,
                       const REAL *comps, const REAL *background, const int32_t *ranges, const int32_t *ids,
                       const uint8_t *tile_mask, REAL *image, REAL *alpha, REAL *final_T, int32_t *last_ids,
-                      int32_t *n_eval, uint8_t *flags, uint32_t *trace)
+                      int32_t *n_eval, int32_t *n_comp, uint8_t *flags, uint32_t *trace)
 {
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
@@ -624,6 +624,7 @@ int orc_rasterize_fwd(const orc_params *P, int C, int N, const int *W, const int
                         final_T[p] = po.T;
                         last_ids[p] = po.last >= 0 ? start + po.last : -1;
                         if (n_eval) n_eval[p] = po.n_eval;
+                        if (n_comp) n_comp[p] = po.n_comp;
                         if (flags) flags[p] = (uint8_t)po.flags;
                         if (trace) trace[p] = po.trace;
                     }
@@ -719,7 +720,7 @@ int orc_render_tiles_fwd(const orc_params *P, int C, int N, const int *W, const 
                          const REAL *comps, const int32_t *radii, const REAL *depths, const REAL *background,
                          int ntiles, const int32_t *tiles, int untiled,
                          REAL *image, REAL *alpha, REAL *final_T, int32_t *last_gid, int32_t *last_pos,
-                         int32_t *n_eval, uint8_t *flags, uint32_t *trace, int32_t *list_len)
+                         int32_t *n_eval, int32_t *n_comp, uint8_t *flags, uint32_t *trace, int32_t *list_len)
 {
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
@@ -744,6 +745,7 @@ int orc_render_tiles_fwd(const orc_params *P, int C, int N, const int *W, const 
                 if (last_gid) last_gid[p] = po.last >= 0 ? list[po.last] : -1;
                 if (last_pos) last_pos[p] = po.last;
                 if (n_eval) n_eval[p] = po.n_eval;
+                if (n_comp) n_comp[p] = po.n_comp;
                 if (flags) flags[p] = (uint8_t)po.flags;
                 if (trace) trace[p] = po.trace;
             }

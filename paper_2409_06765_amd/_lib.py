@@ -1,0 +1,196 @@
+"""ctypes binding of libgsraster.so (include/gsraster.h).
+
+Argument marshalling only: every entry point keeps its C name and takes torch
+tensors on the GPU (or None for a nullable pointer), host integer sequences for
+the per-camera image sizes, and an optional torch stream.  All arithmetic runs
+in the HIP library; there is no fallback.  torch is imported first so that the
+library binds to the HIP runtime torch has already loaded.
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgsraster.so")
+
+GSR_OK, GSR_EINVAL, GSR_EOVERFLOW, GSR_EWORKSPACE, GSR_EHIP = 0, 1, 2, 3, 4
+GSR_OP_INTERSECT_COUNT, GSR_OP_SORT = 1, 2
+GSR_MAX_CAMERAS = 64
+_NAMES = {0: "GSR_OK", 1: "GSR_EINVAL", 2: "GSR_EOVERFLOW", 3: "GSR_EWORKSPACE", 4: "GSR_EHIP"}
+
+
+class GsrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class gsr_params(ctypes.Structure):
+    _fields_ = [("near_plane", ctypes.c_float), ("far_plane", ctypes.c_float), ("eps2d", ctypes.c_float),
+                ("jac_clamp", ctypes.c_float), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
+                ("T_min", ctypes.c_float), ("tile", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
+                ("antialiased", ctypes.c_int32)]
+
+
+_vp, _i, _i64, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+_P = ctypes.POINTER(gsr_params)
+_SIGS = {
+    "gsr_abi_version": ([], _i),
+    "gsr_last_error": ([], ctypes.c_char_p),
+    "gsr_default_params": ([_P], None),
+    "gsr_workspace_bytes": ([_i, _i, _i, _i64], _sz),
+    "gsr_project_fwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 7 + [_vp] * 6 + [_vp], _i),
+    "gsr_intersect_count": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
+    "gsr_intersect_emit": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp], _i),
+    "gsr_sort_pairs": ([_i64, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
+    "gsr_tile_ranges": ([_i64, _vp, ctypes.c_int32, _vp, _vp], _i),
+    "gsr_rasterize_fwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 8 + [_vp] * 5 + [_vp], _i),
+    "gsr_rasterize_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 12 + [_vp] * 5 + [_vp], _i),
+    "gsr_project_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 9 + [_vp] * 5 + [_vp] * 5 + [_vp], _i),
+}
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GsrError(GSR_EHIP, f"{LIB_PATH} is missing: build it with python -m paper_2409_06765_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def default_params(**overrides):
+    p = gsr_params()
+    lib().gsr_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown rasterizer parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _sizes(xs):
+    xs = [int(v) for v in xs]
+    return (ctypes.c_int32 * max(len(xs), 1))(*xs)
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(rc):
+    if rc != GSR_OK:
+        raise GsrError(rc, lib().gsr_last_error().decode(errors="replace"))
+
+
+def abi_version():
+    return lib().gsr_abi_version()
+
+
+def workspace_bytes(op, C, N, M):
+    return int(lib().gsr_workspace_bytes(op, C, N, M))
+
+
+F32, I32, I64, U64 = torch.float32, torch.int32, torch.int64, torch.uint64
+
+
+def gsr_project_fwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors, viewmats, Ks,
+                    means2d, conics, radii, depths, colors, compensations=None, stream=None):
+    _check(lib().gsr_project_fwd(
+        ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means, F32, "means"), _ptr(quats, F32, "quats"),
+        _ptr(scales, F32, "scales"), _ptr(opacities, F32, "opacities"), _ptr(sh_or_colors, F32, "sh_or_colors"),
+        _ptr(viewmats, F32, "viewmats"), _ptr(Ks, F32, "Ks"), _ptr(means2d, F32, "means2d"),
+        _ptr(conics, F32, "conics"), _ptr(radii, I32, "radii"), _ptr(depths, F32, "depths"),
+        _ptr(colors, F32, "colors"), _ptr(compensations, F32, "compensations"), _stream(stream)))
+
+
+def gsr_intersect_count(p, C, N, W, H, means2d, radii, tiles_per_gauss, offsets, total_dev, ws, sync=True,
+                        stream=None):
+    """Returns M when ``sync`` (the call then waits for the stream), else None."""
+    host = ctypes.c_int64(0)
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    _check(lib().gsr_intersect_count(
+        ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(radii, I32, "radii"),
+        _ptr(tiles_per_gauss, I32, "tiles_per_gauss"), _ptr(offsets, I64, "offsets"), _ptr(total_dev, I64, "total"),
+        ctypes.byref(host) if sync else None, _ptr(ws, None, "workspace"), ws_bytes, _stream(stream)))
+    return int(host.value) if sync else None
+
+
+def gsr_intersect_emit(p, C, N, W, H, means2d, radii, depths, offsets, M_capacity, keys, ids, stream=None):
+    _check(lib().gsr_intersect_emit(
+        ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(radii, I32, "radii"),
+        _ptr(depths, F32, "depths"), _ptr(offsets, I64, "offsets"), int(M_capacity), _ptr(keys, U64, "keys"),
+        _ptr(ids, I32, "ids"), _stream(stream)))
+
+
+def gsr_sort_pairs(M, key_bits, keys, ids, keys_alt, ids_alt, ws, stream=None):
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    _check(lib().gsr_sort_pairs(int(M), int(key_bits), _ptr(keys, U64, "keys"), _ptr(ids, I32, "ids"),
+                                _ptr(keys_alt, U64, "keys_alt"), _ptr(ids_alt, I32, "ids_alt"),
+                                _ptr(ws, None, "workspace"), ws_bytes, _stream(stream)))
+
+
+def gsr_tile_ranges(M, keys, total_tiles, ranges, stream=None):
+    _check(lib().gsr_tile_ranges(int(M), _ptr(keys, U64, "keys"), int(total_tiles), _ptr(ranges, I32, "ranges"),
+                                 _stream(stream)))
+
+
+def gsr_rasterize_fwd(p, C, N, W, H, means2d, conics, colors, opacities, compensations, background, ranges, ids,
+                      image, alpha, final_T, last_ids, n_eval=None, stream=None):
+    _check(lib().gsr_rasterize_fwd(
+        ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(conics, F32, "conics"),
+        _ptr(colors, F32, "colors"), _ptr(opacities, F32, "opacities"), _ptr(compensations, F32, "compensations"),
+        _ptr(background, F32, "background"), _ptr(ranges, I32, "ranges"), _ptr(ids, I32, "ids"),
+        _ptr(image, F32, "image"), _ptr(alpha, F32, "alpha"), _ptr(final_T, F32, "final_T"),
+        _ptr(last_ids, I32, "last_ids"), _ptr(n_eval, I32, "n_eval"), _stream(stream)))
+
+
+def gsr_rasterize_bwd(p, C, N, W, H, means2d, conics, colors, opacities, compensations, background, ranges, ids,
+                      final_T, last_ids, v_image, v_alpha, v_means2d, v_conics, v_colors, v_opacities,
+                      v_means2d_abs=None, stream=None):
+    _check(lib().gsr_rasterize_bwd(
+        ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(conics, F32, "conics"),
+        _ptr(colors, F32, "colors"), _ptr(opacities, F32, "opacities"), _ptr(compensations, F32, "compensations"),
+        _ptr(background, F32, "background"), _ptr(ranges, I32, "ranges"), _ptr(ids, I32, "ids"),
+        _ptr(final_T, F32, "final_T"), _ptr(last_ids, I32, "last_ids"), _ptr(v_image, F32, "v_image"),
+        _ptr(v_alpha, F32, "v_alpha"), _ptr(v_means2d, F32, "v_means2d"), _ptr(v_conics, F32, "v_conics"),
+        _ptr(v_colors, F32, "v_colors"), _ptr(v_opacities, F32, "v_opacities"),
+        _ptr(v_means2d_abs, F32, "v_means2d_abs"), _stream(stream)))
+
+
+def gsr_project_bwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, radii,
+                    compensations, v_means2d, v_conics, v_colors, v_opacities_cn, v_depths, v_means, v_quats,
+                    v_scales, v_opacities, v_sh_or_colors, stream=None):
+    _check(lib().gsr_project_bwd(
+        ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means, F32, "means"), _ptr(quats, F32, "quats"),
+        _ptr(scales, F32, "scales"), _ptr(opacities, F32, "opacities"), _ptr(sh_or_colors, F32, "sh_or_colors"),
+        _ptr(viewmats, F32, "viewmats"), _ptr(Ks, F32, "Ks"), _ptr(radii, I32, "radii"),
+        _ptr(compensations, F32, "compensations"), _ptr(v_means2d, F32, "v_means2d"),
+        _ptr(v_conics, F32, "v_conics"), _ptr(v_colors, F32, "v_colors"),
+        _ptr(v_opacities_cn, F32, "v_opacities_cn"), _ptr(v_depths, F32, "v_depths"),
+        _ptr(v_means, F32, "v_means"), _ptr(v_quats, F32, "v_quats"), _ptr(v_scales, F32, "v_scales"),
+        _ptr(v_opacities, F32, "v_opacities"), _ptr(v_sh_or_colors, F32, "v_sh_or_colors"), _stream(stream)))

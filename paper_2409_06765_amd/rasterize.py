@@ -1,0 +1,192 @@
+"""Differentiable tile rasterization on top of the C ABI.
+
+``project`` / ``intersect`` / ``rasterize_forward`` / ``rasterize_backward`` /
+``project_backward`` allocate outputs with torch and call the HIP library;
+``RasterizeGaussians`` chains them in a ``torch.autograd.Function`` and
+``rasterization`` mirrors the paper's 13-line example, returning
+(image [C,H,W,3], alpha [C,H,W,1], meta).  The backward recomputes alphas
+from the saved per-pixel last index and final transmittance instead of
+keeping per-pixel lists.
+"""
+import math
+
+import torch
+
+from . import _lib as L
+
+
+def make_params(sh_degree=-1, antialiased=False, **kw):
+    return L.default_params(sh_degree=int(sh_degree), antialiased=int(bool(antialiased)), **kw)
+
+
+def _dev(t):
+    return t.device
+
+
+def _sizes_per_cam(C, width, height):
+    W = [int(width)] * C if isinstance(width, int) else [int(w) for w in width]
+    H = [int(height)] * C if isinstance(height, int) else [int(h) for h in height]
+    if len(W) != C or len(H) != C:
+        raise ValueError("one width and height per camera")
+    return W, H
+
+
+def layout(W, H, tile=16):
+    """Per-camera pixel offsets, tile offsets, total pixels and tiles."""
+    pix_off, tile_off = [0], [0]
+    for w, h in zip(W, H):
+        pix_off.append(pix_off[-1] + w * h)
+        tile_off.append(tile_off[-1] + ((w + tile - 1) // tile) * ((h + tile - 1) // tile))
+    return pix_off, tile_off
+
+
+def project(p, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H, stream=None):
+    C, N = viewmats.shape[0], means.shape[0]
+    d = _dev(means)
+    f = dict(device=d, dtype=torch.float32)
+    out = dict(means2d=torch.empty((C, N, 2), **f), conics=torch.empty((C, N, 3), **f),
+               radii=torch.empty((C, N), device=d, dtype=torch.int32), depths=torch.empty((C, N), **f),
+               colors=torch.empty((C, N, 3), **f),
+               comps=torch.empty((C, N), **f) if p.antialiased else None)
+    L.gsr_project_fwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors, viewmats, Ks,
+                      out["means2d"], out["conics"], out["radii"], out["depths"], out["colors"], out["comps"],
+                      stream=stream)
+    return out
+
+
+def intersect(p, proj, W, H, stream=None):
+    """Tile binning, key emission, stable radix sort, tile ranges.  Waits
+    once for the intersection count, which sizes the key buffers."""
+    C, N = proj["radii"].shape
+    d = proj["radii"].device
+    _, tile_off = layout(W, H)
+    total_tiles = tile_off[-1]
+    counts = torch.empty((C, N), device=d, dtype=torch.int32)
+    offsets = torch.empty((C, N), device=d, dtype=torch.int64)
+    total = torch.empty(1, device=d, dtype=torch.int64)
+    ws = torch.empty(max(L.workspace_bytes(L.GSR_OP_INTERSECT_COUNT, C, N, 0), 1), device=d, dtype=torch.uint8)
+    M = L.gsr_intersect_count(p, C, N, W, H, proj["means2d"], proj["radii"], counts, offsets, total, ws,
+                              sync=True, stream=stream)
+    keys = torch.empty(max(M, 1), device=d, dtype=torch.uint64)
+    ids = torch.empty(max(M, 1), device=d, dtype=torch.int32)
+    L.gsr_intersect_emit(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], offsets, M, keys, ids,
+                         stream=stream)
+    key_bits = 32 + max(total_tiles - 1, 0).bit_length()
+    if M > 1:
+        keys_alt = torch.empty_like(keys)
+        ids_alt = torch.empty_like(ids)
+        sws = torch.empty(max(L.workspace_bytes(L.GSR_OP_SORT, 0, 0, M), 1), device=d, dtype=torch.uint8)
+        L.gsr_sort_pairs(M, key_bits, keys, ids, keys_alt, ids_alt, sws, stream=stream)
+    ranges = torch.empty((max(total_tiles, 1), 2), device=d, dtype=torch.int32)
+    L.gsr_tile_ranges(M, keys, total_tiles, ranges, stream=stream)
+    return dict(counts=counts, offsets=offsets, M=M, keys=keys[:M], ids=ids[:M], ranges=ranges,
+                total_tiles=total_tiles, key_bits=key_bits)
+
+
+def rasterize_forward(p, proj, opacities, isect, W, H, background=None, n_eval=False, stream=None):
+    C, N = proj["radii"].shape
+    d = proj["radii"].device
+    pix_off, _ = layout(W, H)
+    P = pix_off[-1]
+    f = dict(device=d, dtype=torch.float32)
+    out = dict(image=torch.empty((P, 3), **f), alpha=torch.empty(P, **f), final_T=torch.empty(P, **f),
+               last_ids=torch.empty(P, device=d, dtype=torch.int32),
+               n_eval=torch.empty((P, 2), device=d, dtype=torch.int32) if n_eval else None)
+    L.gsr_rasterize_fwd(p, C, N, W, H, proj["means2d"], proj["conics"], proj["colors"], opacities,
+                        proj["comps"], background, isect["ranges"], isect["ids"], out["image"], out["alpha"],
+                        out["final_T"], out["last_ids"], out["n_eval"], stream=stream)
+    return out
+
+
+def rasterize_backward(p, proj, opacities, isect, W, H, fwd, v_image, v_alpha=None, background=None,
+                       absgrad=False, stream=None):
+    C, N = proj["radii"].shape
+    d = proj["radii"].device
+    f = dict(device=d, dtype=torch.float32)
+    g = dict(v_means2d=torch.empty((C, N, 2), **f), v_conics=torch.empty((C, N, 3), **f),
+             v_colors=torch.empty((C, N, 3), **f), v_opacities=torch.empty((C, N), **f),
+             v_means2d_abs=torch.empty((C, N, 2), **f) if absgrad else None)
+    L.gsr_rasterize_bwd(p, C, N, W, H, proj["means2d"], proj["conics"], proj["colors"], opacities, proj["comps"],
+                        background, isect["ranges"], isect["ids"], fwd["final_T"], fwd["last_ids"], v_image,
+                        v_alpha, g["v_means2d"], g["v_conics"], g["v_colors"], g["v_opacities"],
+                        g["v_means2d_abs"], stream=stream)
+    return g
+
+
+def project_backward(p, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H, proj, g2,
+                     v_depths=None, stream=None):
+    C, N = viewmats.shape[0], means.shape[0]
+    out = dict(v_means=torch.empty_like(means), v_quats=torch.empty_like(quats), v_scales=torch.empty_like(scales),
+               v_opacities=torch.empty_like(opacities), v_sh=torch.empty_like(sh_or_colors))
+    L.gsr_project_bwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, proj["radii"],
+                      proj["comps"], g2["v_means2d"], g2["v_conics"], g2["v_colors"], g2["v_opacities"], v_depths,
+                      out["v_means"], out["v_quats"], out["v_scales"], out["v_opacities"], out["v_sh"],
+                      stream=stream)
+    return out
+
+
+class RasterizeGaussians(torch.autograd.Function):
+    """(means, quats, scales, opacities, sh_or_colors) -> (image [P,3], alpha [P]);
+    viewmats, Ks and background are constants."""
+
+    @staticmethod
+    def forward(ctx, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, background, p, W, H, absgrad,
+                meta):
+        means, quats, scales, opacities, sh_or_colors = (t.contiguous() for t in
+                                                         (means, quats, scales, opacities, sh_or_colors))
+        proj = project(p, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H)
+        isect = intersect(p, proj, W, H)
+        fwd = rasterize_forward(p, proj, opacities, isect, W, H, background)
+        ctx.p, ctx.W, ctx.H, ctx.absgrad = p, W, H, absgrad
+        ctx.proj, ctx.isect, ctx.fwd = proj, isect, fwd
+        ctx.save_for_backward(means, quats, scales, opacities, sh_or_colors, viewmats, Ks, background)
+        ctx.meta = meta
+        meta.update(radii=proj["radii"], means2d=proj["means2d"], depths=proj["depths"], conics=proj["conics"],
+                    colors=proj["colors"], tiles_per_gauss=isect["counts"], n_intersections=isect["M"],
+                    last_ids=fwd["last_ids"], final_T=fwd["final_T"])
+        return fwd["image"], fwd["alpha"]
+
+    @staticmethod
+    def backward(ctx, v_image, v_alpha):
+        means, quats, scales, opacities, sh, viewmats, Ks, background = ctx.saved_tensors
+        p, W, H = ctx.p, ctx.W, ctx.H
+        v_image = torch.zeros_like(ctx.fwd["image"]) if v_image is None else v_image.contiguous()
+        v_alpha = None if v_alpha is None else v_alpha.contiguous()
+        g2 = rasterize_backward(p, ctx.proj, opacities, ctx.isect, W, H, ctx.fwd, v_image, v_alpha, background,
+                                absgrad=ctx.absgrad)
+        if ctx.absgrad:
+            ctx.meta["means2d_absgrad"] = g2["v_means2d_abs"]
+        g3 = project_backward(p, means, quats, scales, opacities, sh, viewmats, Ks, W, H, ctx.proj, g2)
+        return (g3["v_means"], g3["v_quats"], g3["v_scales"], g3["v_opacities"], g3["v_sh"],
+                None, None, None, None, None, None, None, None)
+
+
+def rasterization(means, quats, scales, opacities, colors, viewmats, Ks, width, height, sh_degree=None,
+                  background=None, absgrad=False, antialiased=False, **params):
+    """Render C views of N Gaussians (scales and opacities already activated).
+
+    colors: [N,3] direct colours, or [N,K,3] SH coefficients with K = (d+1)^2
+    (``sh_degree`` defaults to the largest degree K holds).  Returns
+    (image [C,H,W,3], alpha [C,H,W,1], meta); views of different sizes are
+    returned packed, as [P,3] and [P,1], when width/height are sequences.
+    """
+    C = viewmats.shape[0]
+    if colors.dim() == 3:
+        deg = int(math.isqrt(colors.shape[1])) - 1 if sh_degree is None else int(sh_degree)
+    else:
+        deg = -1
+    p = make_params(sh_degree=deg, antialiased=antialiased, **params)
+    W, H = _sizes_per_cam(C, width, height)
+    bg = None
+    if background is not None:
+        bg = background.to(torch.float32).reshape(-1, 3).expand(C, 3).contiguous()
+    meta = dict(width=W, height=H, sh_degree=deg)
+    image, alpha = RasterizeGaussians.apply(means.float(), quats.float(), scales.float(), opacities.float(),
+                                            colors.float(), viewmats.float().contiguous(), Ks.float().contiguous(),
+                                            bg, p, W, H, absgrad, meta)
+    if len(set(W)) == 1 and len(set(H)) == 1:
+        image = image.view(C, H[0], W[0], 3)
+        alpha = alpha.view(C, H[0], W[0], 1)
+    else:
+        alpha = alpha.view(-1, 1)
+    return image, alpha, meta

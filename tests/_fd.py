@@ -72,21 +72,23 @@ _GRAD_KEY = {"means": "v_means", "quats": "v_quats", "scales": "v_scales", "opac
              "sh": "v_sh"}
 
 
-def fd_check(o, P, sc, cams, v_image, v_alpha=None, background=None, n_gauss=8, eps=1e-3, seed=0):
-    """Returns (rows, rejected): rows = [(name, n, fd, analytic)]."""
+def fd_check(o, P, sc, cams, v_image, v_alpha=None, background=None, n_params=64, eps=1e-3, seed=0,
+             max_gauss=400):
+    """Draws Gaussians with at least one composited pixel and tests their
+    eight parameters until ``n_params`` samples are accepted.
+    Returns (rows, rejected): rows = [(name, n, fd, analytic)]."""
     sc = {k: (np.array(v, np.float64) if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
     proj, isect, ras = o.forward(P, sc, cams, background=background)
     g2, g3 = o.backward(P, sc, cams, proj, isect, ras, v_image, v_alpha, background)
     touched = np.nonzero(np.abs(g2["v_colors"]).sum(axis=(0, 2)) > 0)[0]
     g = _sc.rng("cfg2", _sc.STREAM_FD, seed)
     order = g.permutation(touched)
-    rows, rejected, used = [], 0, 0
-    for n in order:
-        if used >= n_gauss:
+    rows, rejected = [], 0
+    for n in order[:max_gauss]:
+        if len(rows) >= n_params:
             break
         tiles = _rect_tiles(P, proj, n, cams)
         pix = _pixels_of(tiles, cams, P.tile)
-        ok_any = False
         for name, key, ix in param_list(sc, n, g):
             arr = sc[key]
             orig = arr[ix]
@@ -111,6 +113,4 @@ def fd_check(o, P, sc, cams, v_image, v_alpha=None, background=None, n_gauss=8, 
             fd = (vals[0] - vals[1]) / (2 * eps)
             an = float(g3[_GRAD_KEY[key]][ix])
             rows.append((name, int(n), fd, an))
-            ok_any = True
-        used += int(ok_any)
-    return rows, rejected
+    return rows[:n_params], rejected

@@ -1,0 +1,97 @@
+"""Edge cases of the HIP path through the C ABI: empty scenes, fully culled
+views, a screen-filling Gaussian, the stand-alone radix sort, and batch
+independence of multi-view renders."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import Oracle, OracleParams
+from paper_2409_06765_amd import scenes
+from _util import one_gaussian_scene
+
+pytestmark = pytest.mark.gpu
+O32 = Oracle(np.float32)
+
+
+def _say(msg):
+    print(f"[gpu-edges] {msg}", flush=True)
+
+
+def test_empty_scene_renders_background():
+    from _gpu import gpu_forward, np_, params
+    _say("empty scene")
+    sc = scenes.scene_tiny(0)
+    cams = scenes.cams_tiny(W=40, H=30)
+    bg = np.array([[0.1, 0.2, 0.3]], np.float32)
+    st = gpu_forward(params(), sc, cams, background=bg)
+    assert st["isect"]["M"] == 0
+    np.testing.assert_array_equal(np_(st["fwd"]["final_T"]), 1.0)
+    np.testing.assert_array_equal(np_(st["fwd"]["last_ids"]), -1)
+    np.testing.assert_allclose(np_(st["fwd"]["image"]), np.tile(bg, (1200, 1)))
+
+
+def test_all_gaussians_behind_the_camera():
+    from _gpu import gpu_backward, gpu_forward, np_, params
+    _say("all culled")
+    sc = scenes.scene_tiny(500, seed=4)
+    sc["means"][:, 2] += 10.0      # every mean behind the camera at z = 4 looking at -z
+    cams = scenes.cams_tiny(W=64, H=64)
+    st = gpu_forward(params(), sc, cams)
+    assert st["isect"]["M"] == 0 and int(np_(st["proj"]["radii"]).max()) == 0
+    g2, g3 = gpu_backward(params(), st, np.ones((64 * 64, 3), np.float32))
+    assert float(np.abs(np_(g3["v_means"])).max()) == 0.0
+
+
+def test_screen_filling_gaussian_matches_oracle():
+    from _gpu import gpu_forward, np_, params
+    _say("screen-filling gaussian")
+    sc = one_gaussian_scene((0.02, -0.01, 1.0), scale=(0.8, 0.6, 0.5), opacity=0.97, color=(0.3, 0.6, 0.9))
+    cams = scenes.cams_tiny(W=300, H=200, f=250.0, radius=1.5)
+    st = gpu_forward(params(), sc, cams)
+    proj, isect, ras = O32.forward(OracleParams(), sc, cams)
+    assert isect["M"] == st["isect"]["M"] == 19 * 13
+    ok = ras["flags"] == 0
+    assert np.abs(np_(st["fwd"]["image"]) - ras["image"]).max(axis=1)[ok].max() <= 1e-4
+
+
+@pytest.mark.parametrize("M,key_bits,dups", [(1, 40, 1), (2, 33, 1), (3000, 45, 20), (100_003, 45, 1000),
+                                             (250_000, 64, 1), (70_001, 17, 5)])
+def test_radix_sort_is_stable_and_exact(M, key_bits, dups):
+    from paper_2409_06765_amd import _lib as L
+    _say(f"sort M={M} bits={key_bits}")
+    g = np.random.default_rng(M)
+    mask = np.uint64((1 << key_bits) - 1) if key_bits < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    base = g.integers(0, 2 ** 63, size=max(M // dups, 1), dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    keys = (base[g.integers(0, base.size, M)] & mask).astype(np.uint64)
+    ids = np.arange(M, dtype=np.int32)
+    order = np.argsort(keys, kind="stable")
+    dk = torch.from_numpy(keys).cuda()
+    di = torch.from_numpy(ids).cuda()
+    ka, ia = torch.empty_like(dk), torch.empty_like(di)
+    ws = torch.empty(max(L.workspace_bytes(L.GSR_OP_SORT, 0, 0, M), 1), dtype=torch.uint8, device="cuda")
+    L.gsr_sort_pairs(M, key_bits, dk, di, ka, ia, ws)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(dk.cpu().numpy(), keys[order])
+    np.testing.assert_array_equal(di.cpu().numpy(), ids[order])
+
+
+def test_multiview_batch_equals_each_view_alone():
+    """The forward has no atomics: a view rendered inside a batch of views of
+    different sizes is bit-identical to the same view rendered alone."""
+    from _gpu import gpu_forward, np_, params
+    sc = scenes.scene_tiny(800, sh_degree=3, seed=5, log_scale_mean=-2.6)
+    eyes = [[0, 0, 4.0], [2.0, 2.0, 2.0], [-3.0, 0.5, 2.0], [0.5, -3.5, 1.0]]
+    sizes = [(100, 80), (64, 64), (130, 47), (32, 200)]
+    cams = scenes.cameras([scenes.look_at(e) for e in eyes], [scenes.intrinsics(1.2 * w, w, h) for w, h in sizes],
+                          [w for w, _ in sizes], [h for _, h in sizes])
+    p = params(sh_degree=3)
+    _say("batch of 4 uneven views")
+    st = gpu_forward(p, sc, cams)
+    off = 0
+    for c, (w, h) in enumerate(sizes):
+        one = {k: v[c:c + 1] for k, v in cams.items()}
+        s1 = gpu_forward(p, sc, one)
+        img_b = np_(st["fwd"]["image"])[off:off + w * h]
+        np.testing.assert_array_equal(np_(s1["fwd"]["image"]), img_b)
+        np.testing.assert_array_equal(np_(s1["fwd"]["final_T"]), np_(st["fwd"]["final_T"])[off:off + w * h])
+        off += w * h

@@ -27,17 +27,18 @@ def test_rendered_loss_gradients_match_fd(deg, aa, bg):
     v_image, v_alpha = scenes.upstream_grads("tiny", npix, seed=51, with_alpha=True)
     background = np.array([[0.3, 0.1, 0.7], [0.0, 0.2, 0.4]]) if bg else None
     rows, rejected = fd_check(O64, P, sc, cams, v_image.astype(np.float64), v_alpha.astype(np.float64),
-                              background=background, n_gauss=8, eps=1e-4, seed=deg + 1 + 10 * aa)
-    _check(rows, rejected, min_rows=40)
+                              background=background, n_params=48, eps=1e-4, seed=deg + 1 + 10 * aa)
+    _check(rows, rejected, min_rows=48)
 
 
 @pytest.mark.slow
 def test_cfg2_fd_on_64_sampled_parameters():
-    """The CFG2 protocol: 100k Gaussians, SH3, 800x800, eps = 1e-3, 8 Gaussians
-    x 8 parameters (float64 oracle)."""
+    """The CFG2 protocol: 100k Gaussians, SH3, 800x800, eps = 1e-3, 64 sampled
+    parameters (eight per Gaussian; a sample whose decision trace changes
+    within +-eps is redrawn), float64 oracle."""
     P = OracleParams(sh_degree=3)
     sc = scenes.scene_cfg2()
     cams = scenes.cams_cfg2()
     v_image, _ = scenes.upstream_grads("cfg2", 800 * 800)
-    rows, rejected = fd_check(O64, P, sc, cams, v_image.astype(np.float64), None, n_gauss=8, eps=1e-3)
-    _check(rows, rejected, min_rows=56)
+    rows, rejected = fd_check(O64, P, sc, cams, v_image.astype(np.float64), None, n_params=64, eps=1e-3)
+    _check(rows, rejected, min_rows=64)
