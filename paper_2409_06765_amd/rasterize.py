@@ -79,8 +79,10 @@ def intersect(p, proj, W, H, stream=None):
         L.gsr_sort_pairs(M, key_bits, keys, ids, keys_alt, ids_alt, sws, stream=stream)
     ranges = torch.empty((max(total_tiles, 1), 2), device=d, dtype=torch.int32)
     L.gsr_tile_ranges(M, keys, total_tiles, ranges, stream=stream)
-    return dict(counts=counts, offsets=offsets, M=M, keys=keys[:M], ids=ids[:M], ranges=ranges,
-                total_tiles=total_tiles, key_bits=key_bits)
+    # keys/ids are views of length M; the *_buf tensors (length max(M, 1)) are
+    # what the library is handed, so a pointer is never NULL when M == 0
+    return dict(counts=counts, offsets=offsets, M=M, keys=keys[:M], ids=ids[:M], ids_buf=ids, keys_buf=keys,
+                ranges=ranges, total_tiles=total_tiles, key_bits=key_bits)
 
 
 def rasterize_forward(p, proj, opacities, isect, W, H, background=None, n_eval=False, stream=None):
@@ -93,7 +95,7 @@ def rasterize_forward(p, proj, opacities, isect, W, H, background=None, n_eval=F
                last_ids=torch.empty(P, device=d, dtype=torch.int32),
                n_eval=torch.empty((P, 2), device=d, dtype=torch.int32) if n_eval else None)
     L.gsr_rasterize_fwd(p, C, N, W, H, proj["means2d"], proj["conics"], proj["colors"], opacities,
-                        proj["comps"], background, isect["ranges"], isect["ids"], out["image"], out["alpha"],
+                        proj["comps"], background, isect["ranges"], isect["ids_buf"], out["image"], out["alpha"],
                         out["final_T"], out["last_ids"], out["n_eval"], stream=stream)
     return out
 
@@ -107,7 +109,7 @@ def rasterize_backward(p, proj, opacities, isect, W, H, fwd, v_image, v_alpha=No
              v_colors=torch.empty((C, N, 3), **f), v_opacities=torch.empty((C, N), **f),
              v_means2d_abs=torch.empty((C, N, 2), **f) if absgrad else None)
     L.gsr_rasterize_bwd(p, C, N, W, H, proj["means2d"], proj["conics"], proj["colors"], opacities, proj["comps"],
-                        background, isect["ranges"], isect["ids"], fwd["final_T"], fwd["last_ids"], v_image,
+                        background, isect["ranges"], isect["ids_buf"], fwd["final_T"], fwd["last_ids"], v_image,
                         v_alpha, g["v_means2d"], g["v_conics"], g["v_colors"], g["v_opacities"],
                         g["v_means2d_abs"], stream=stream)
     return g
