@@ -57,6 +57,9 @@ def main():
     ap.add_argument("--workload", default="cfg3", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-tiles", type=int, default=96, help="tiles of view 0 the oracle rasterizes")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of the one-view capacity")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note, "
@@ -170,9 +173,43 @@ def main():
         "raster_fwd_tflops": round(fwd_tflops, 3),
         "roofline": roofline,
     }
+    if not args.no_serve and args.workload == "cfg3":
+        out["serving"] = serving(d, p, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, cams, wl, args, counts, views[0])
     print(json.dumps(out), flush=True)
+
+
+def serving(d, p, args):
+    """Render requests against the resident 1M-Gaussian scene: Poisson
+    arrivals over {256^2, 512^2, 800^2, 1280x720, 1920x1080}, focal 1.2 W,
+    poses on a radius-6 sphere.  The arrival rate is a fraction of the
+    one-view-per-launch capacity measured on the same request mix; both
+    policies replay the same trace."""
+    import torch
+    from paper_2409_06765_amd import scenes
+    from paper_2409_06765_amd.serve import GpuBackend, Server, serve_one_at_a_time
+
+    be = GpuBackend(d, p)
+    probe = scenes.serving_trace(1.0, n_requests=60, seed=1)
+    for r in probe:
+        r.arrival = 0.0
+    serve_one_at_a_time(be, probe[:10])                      # warm up
+    torch.cuda.synchronize()
+    _, cap = serve_one_at_a_time(be, probe[10:])
+    rate = args.serve_load * cap.views_per_s
+    trace = scenes.serving_trace(rate, n_requests=args.serve_requests, seed=0)
+    log(f"serving: one-view capacity {cap.views_per_s:.1f} views/s, trace at {rate:.1f} req/s")
+    _, single = serve_one_at_a_time(be, trace)
+    torch.cuda.synchronize()
+    _, batched = Server(be, max_batch=16, mem_budget=24 << 30).run(trace)
+    torch.cuda.synchronize()
+    pick = lambda st: {"views_per_s": round(st.views_per_s, 2), "p50_ms": round(st.p50_ms, 3),
+                       "p99_ms": round(st.p99_ms, 3), "mean_batch": round(st.mean_batch, 2),
+                       "done": st.n_done, "rejected": st.n_rejected}
+    return {"requests": args.serve_requests, "arrival_rate_per_s": round(rate, 2),
+            "one_view_capacity_views_per_s": round(cap.views_per_s, 2),
+            "batched": pick(batched), "one_view_per_launch": pick(single)}
 
 
 def cpu_baseline(sc, cams, wl, args, counts, v0):

@@ -74,7 +74,10 @@ typedef void *gsr_stream_t;   /* a hipStream_t */
 
 enum gsr_op {
     GSR_OP_INTERSECT_COUNT = 1,   /* workspace of gsr_intersect_count for C*N entries */
-    GSR_OP_SORT = 2               /* workspace of gsr_sort_pairs for M pairs          */
+    GSR_OP_SORT = 2,              /* workspace of gsr_sort_pairs for M pairs          */
+    GSR_OP_RASTERIZE = 3,         /* workspace of gsr_rasterize_fwd / _bwd, C*N       */
+    GSR_OP_BIN_PREPARE = 4,       /* workspace kept from gsr_bin_prepare to _finish   */
+    GSR_OP_BIN_FINISH = 5         /* workspace of gsr_bin_finish for M intersections  */
 };
 
 int gsr_abi_version(void);
@@ -145,6 +148,29 @@ int gsr_sort_pairs(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uint64
 int gsr_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_t *ranges,
                     gsr_stream_t stream);
 
+/* Tile binning and per-tile depth order in two calls, giving the same ids
+ * and ranges, bit for bit, as gsr_intersect_count + gsr_intersect_emit +
+ * gsr_sort_pairs(key_bits = 32 + tile bits) + gsr_tile_ranges, with far less
+ * sorting: the projected Gaussians are stably ordered by the bits of their
+ * depth, their tiles are emitted in that order with 32-bit tile keys, and a
+ * stable sort on the tile bits alone leaves every tile's run in (depth, id)
+ * order (per-tile depth sort of Rasterization of Gaussians).
+ * gsr_bin_prepare: counts and depth order; writes M to total_dev (device,
+ * nullable) and, when total_host is not NULL, to *total_host after waiting
+ * for the stream.  ws_prep: gsr_workspace_bytes(GSR_OP_BIN_PREPARE, C, N, 0),
+ * which must be passed unchanged to gsr_bin_finish.
+ * gsr_bin_finish: ids [M] int32 and ranges [total_tiles, 2] int32 as above;
+ * keys [M] uint64 (nullable) receives the 64-bit keys of the sorted lists.
+ * ws_fin: gsr_workspace_bytes(GSR_OP_BIN_FINISH, C, N, M). */
+int gsr_bin_prepare(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
+                    const float *means2d, const int32_t *radii, const float *depths,
+                    int64_t *total_dev, int64_t *total_host, void *ws_prep, size_t ws_prep_bytes,
+                    gsr_stream_t stream);
+int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
+                   const float *means2d, const int32_t *radii, const float *depths, int64_t M,
+                   int32_t *ids, int32_t *ranges, uint64_t *keys, void *ws_prep, size_t ws_prep_bytes,
+                   void *ws_fin, size_t ws_fin_bytes, gsr_stream_t stream);
+
 /* Front-to-back compositing (Rasterization of Gaussians).  For every pixel
  * with centre p = (x + 0.5, y + 0.5), over its tile's sorted list:
  *   Delta = mu' - p;  sigma = 0.5 (a Dx^2 + c Dy^2) + b Dx Dy (skipped if < 0);
@@ -156,12 +182,14 @@ int gsr_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_
  * Outputs: image [P,3], alpha [P] = 1 - T, final_T [P] = T, last_ids [P] int32
  * (position in the sorted list of the last composited entry, -1 if none),
  * n_eval [P,2] int32 (nullable): per pixel, the entries evaluated (including
- * the one that stopped it) and the entries composited. */
+ * the one that stopped it) and the entries composited.
+ * ws: workspace of gsr_workspace_bytes(GSR_OP_RASTERIZE, C, N, 0). */
 int gsr_rasterize_fwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
                       const float *means2d, const float *conics, const float *colors,
                       const float *opacities, const float *compensations, const float *background,
                       const int32_t *ranges, const int32_t *ids, float *image, float *alpha,
-                      float *final_T, int32_t *last_ids, int32_t *n_eval, gsr_stream_t stream);
+                      float *final_T, int32_t *last_ids, int32_t *n_eval, void *ws, size_t ws_bytes,
+                      gsr_stream_t stream);
 
 /* Depth Compositing Gradients.  Per pixel, from last_ids back to its tile's
  * start, recomputes alpha, restores T_k = T_{k+1} / (1 - alpha_k) from final_T,
@@ -178,14 +206,15 @@ int gsr_rasterize_fwd(const gsr_params *p, int C, int N, const int32_t *W, const
  * with respect to the opacity the rasterizer used, o times compensation),
  * v_means2d_abs [C,N,2] (nullable: per-pixel absolute values of the mu'
  * gradient summed, the absgrad statistic).  Sums use float atomics, so their
- * rounding order is not fixed. */
+ * rounding order is not fixed.
+ * ws: workspace of gsr_workspace_bytes(GSR_OP_RASTERIZE, C, N, 0). */
 int gsr_rasterize_bwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
                       const float *means2d, const float *conics, const float *colors,
                       const float *opacities, const float *compensations, const float *background,
                       const int32_t *ranges, const int32_t *ids, const float *final_T,
                       const int32_t *last_ids, const float *v_image, const float *v_alpha,
                       float *v_means2d, float *v_conics, float *v_colors, float *v_opacities,
-                      float *v_means2d_abs, gsr_stream_t stream);
+                      float *v_means2d_abs, void *ws, size_t ws_bytes, gsr_stream_t stream);
 
 /* Projection Gradients, Scale and rotation gradients, SH backward.  Per
  * Gaussian, summed over the C cameras (no atomics: one thread per Gaussian):

@@ -15,7 +15,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libgsraster.so")
 
 GSR_OK, GSR_EINVAL, GSR_EOVERFLOW, GSR_EWORKSPACE, GSR_EHIP = 0, 1, 2, 3, 4
-GSR_OP_INTERSECT_COUNT, GSR_OP_SORT = 1, 2
+GSR_OP_INTERSECT_COUNT, GSR_OP_SORT, GSR_OP_RASTERIZE, GSR_OP_BIN_PREPARE, GSR_OP_BIN_FINISH = 1, 2, 3, 4, 5
 GSR_MAX_CAMERAS = 64
 _NAMES = {0: "GSR_OK", 1: "GSR_EINVAL", 2: "GSR_EOVERFLOW", 3: "GSR_EWORKSPACE", 4: "GSR_EHIP"}
 
@@ -45,8 +45,10 @@ _SIGS = {
     "gsr_intersect_emit": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp], _i),
     "gsr_sort_pairs": ([_i64, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
     "gsr_tile_ranges": ([_i64, _vp, ctypes.c_int32, _vp, _vp], _i),
-    "gsr_rasterize_fwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 8 + [_vp] * 5 + [_vp], _i),
-    "gsr_rasterize_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 12 + [_vp] * 5 + [_vp], _i),
+    "gsr_bin_prepare": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
+    "gsr_bin_finish": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp, _sz, _vp], _i),
+    "gsr_rasterize_fwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 8 + [_vp] * 5 + [_vp, _sz, _vp], _i),
+    "gsr_rasterize_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 12 + [_vp] * 5 + [_vp, _sz, _vp], _i),
     "gsr_project_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 9 + [_vp] * 5 + [_vp] * 5 + [_vp], _i),
 }
 
@@ -159,19 +161,40 @@ def gsr_tile_ranges(M, keys, total_tiles, ranges, stream=None):
                                  _stream(stream)))
 
 
+def gsr_bin_prepare(p, C, N, W, H, means2d, radii, depths, total_dev, ws_prep, sync=True, stream=None):
+    """Returns M when ``sync`` (the call then waits for the stream), else None."""
+    host = ctypes.c_int64(0)
+    _check(lib().gsr_bin_prepare(
+        ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(radii, I32, "radii"),
+        _ptr(depths, F32, "depths"), _ptr(total_dev, I64, "total"), ctypes.byref(host) if sync else None,
+        *_ws(ws_prep), _stream(stream)))
+    return int(host.value) if sync else None
+
+
+def gsr_bin_finish(p, C, N, W, H, means2d, radii, depths, M, ids, ranges, keys, ws_prep, ws_fin, stream=None):
+    _check(lib().gsr_bin_finish(
+        ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(radii, I32, "radii"),
+        _ptr(depths, F32, "depths"), int(M), _ptr(ids, I32, "ids"), _ptr(ranges, I32, "ranges"),
+        _ptr(keys, U64, "keys"), *_ws(ws_prep), *_ws(ws_fin), _stream(stream)))
+
+
+def _ws(ws):
+    return (_ptr(ws, None, "workspace"), ws.numel() * ws.element_size()) if ws is not None else (None, 0)
+
+
 def gsr_rasterize_fwd(p, C, N, W, H, means2d, conics, colors, opacities, compensations, background, ranges, ids,
-                      image, alpha, final_T, last_ids, n_eval=None, stream=None):
+                      image, alpha, final_T, last_ids, n_eval=None, ws=None, stream=None):
     _check(lib().gsr_rasterize_fwd(
         ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(conics, F32, "conics"),
         _ptr(colors, F32, "colors"), _ptr(opacities, F32, "opacities"), _ptr(compensations, F32, "compensations"),
         _ptr(background, F32, "background"), _ptr(ranges, I32, "ranges"), _ptr(ids, I32, "ids"),
         _ptr(image, F32, "image"), _ptr(alpha, F32, "alpha"), _ptr(final_T, F32, "final_T"),
-        _ptr(last_ids, I32, "last_ids"), _ptr(n_eval, I32, "n_eval"), _stream(stream)))
+        _ptr(last_ids, I32, "last_ids"), _ptr(n_eval, I32, "n_eval"), *_ws(ws), _stream(stream)))
 
 
 def gsr_rasterize_bwd(p, C, N, W, H, means2d, conics, colors, opacities, compensations, background, ranges, ids,
                       final_T, last_ids, v_image, v_alpha, v_means2d, v_conics, v_colors, v_opacities,
-                      v_means2d_abs=None, stream=None):
+                      v_means2d_abs=None, ws=None, stream=None):
     _check(lib().gsr_rasterize_bwd(
         ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(conics, F32, "conics"),
         _ptr(colors, F32, "colors"), _ptr(opacities, F32, "opacities"), _ptr(compensations, F32, "compensations"),
@@ -179,7 +202,7 @@ def gsr_rasterize_bwd(p, C, N, W, H, means2d, conics, colors, opacities, compens
         _ptr(final_T, F32, "final_T"), _ptr(last_ids, I32, "last_ids"), _ptr(v_image, F32, "v_image"),
         _ptr(v_alpha, F32, "v_alpha"), _ptr(v_means2d, F32, "v_means2d"), _ptr(v_conics, F32, "v_conics"),
         _ptr(v_colors, F32, "v_colors"), _ptr(v_opacities, F32, "v_opacities"),
-        _ptr(v_means2d_abs, F32, "v_means2d_abs"), _stream(stream)))
+        _ptr(v_means2d_abs, F32, "v_means2d_abs"), *_ws(ws), _stream(stream)))
 
 
 def gsr_project_bwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, radii,

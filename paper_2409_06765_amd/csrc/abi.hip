@@ -106,6 +106,9 @@ size_t gsr_workspace_bytes(int op, int C, int N, int64_t M) {
     switch (op) {
         case GSR_OP_INTERSECT_COUNT: return count_workspace_bytes((int64_t)(C > 0 ? C : 0) * (N > 0 ? N : 0));
         case GSR_OP_SORT: return sort_workspace_bytes(M > 0 ? M : 0);
+        case GSR_OP_RASTERIZE: return pack_workspace_bytes((int64_t)(C > 0 ? C : 0) * (N > 0 ? N : 0));
+        case GSR_OP_BIN_PREPARE: return bin_prepare_bytes((int64_t)(C > 0 ? C : 0) * (N > 0 ? N : 0));
+        case GSR_OP_BIN_FINISH: return bin_finish_bytes(M > 0 ? M : 0);
         default: return 0;
     }
 }
@@ -194,11 +197,61 @@ int gsr_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_
     return launch_tile_ranges(M, keys, total_tiles, ranges, (hipStream_t)stream);
 }
 
+int gsr_bin_prepare(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
+                    const float *means2d, const int32_t *radii, const float *depths,
+                    int64_t *total_dev, int64_t *total_host, void *ws_prep, size_t ws_prep_bytes,
+                    gsr_stream_t stream) {
+    static const char *fn = "gsr_bin_prepare";
+    int rc = check_params(p);
+    CamTable cams;
+    if (rc == GSR_OK) rc = make_cams(C, N, W, H, cams);
+    if (rc != GSR_OK) return rc;
+    const int64_t n = (int64_t)C * N;
+    if (n > 0) { GSR_NEED(means2d); GSR_NEED(radii); GSR_NEED(depths); }
+    const size_t need = bin_prepare_bytes(n);
+    if (!ws_prep || ws_prep_bytes < need)
+        return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_prep ? ws_prep_bytes : 0);
+    hipStream_t s = (hipStream_t)stream;
+    rc = launch_bin_prepare(*p, cams, N, means2d, radii, depths, ws_prep, total_dev, s);
+    if (rc != GSR_OK || !total_host) return rc;
+    rc = hip_check(hipMemcpyAsync(total_host, bin_total_ptr(ws_prep, n), sizeof(int64_t), hipMemcpyDeviceToHost, s),
+                   fn);
+    if (rc == GSR_OK) rc = hip_check(hipStreamSynchronize(s), fn);
+    if (rc == GSR_OK && *total_host >= (int64_t)INT32_MAX)
+        return fail(GSR_EOVERFLOW, "%s: %lld intersections exceed the int32 index range", fn, (long long)*total_host);
+    return rc;
+}
+
+int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
+                   const float *means2d, const int32_t *radii, const float *depths, int64_t M,
+                   int32_t *ids, int32_t *ranges, uint64_t *keys, void *ws_prep, size_t ws_prep_bytes,
+                   void *ws_fin, size_t ws_fin_bytes, gsr_stream_t stream) {
+    static const char *fn = "gsr_bin_finish";
+    int rc = check_params(p);
+    CamTable cams;
+    if (rc == GSR_OK) rc = make_cams(C, N, W, H, cams);
+    if (rc != GSR_OK) return rc;
+    if (M < 0 || M >= (int64_t)INT32_MAX) return fail(GSR_EINVAL, "%s: M out of range", fn);
+    const int64_t n = (int64_t)C * N;
+    if (cams.total_tiles > 0) GSR_NEED(ranges);
+    if (M > 0) { GSR_NEED(means2d); GSR_NEED(radii); GSR_NEED(depths); GSR_NEED(ids); }
+    const size_t need_p = bin_prepare_bytes(n), need_f = bin_finish_bytes(M);
+    if (!ws_prep || ws_prep_bytes < need_p)
+        return fail(GSR_EWORKSPACE, "%s: prepare workspace of %zu bytes needed", fn, need_p);
+    if (!ws_fin || ws_fin_bytes < need_f)
+        return fail(GSR_EWORKSPACE, "%s: finish workspace of %zu bytes needed, %zu given", fn, need_f,
+                    ws_fin ? ws_fin_bytes : 0);
+    if (cams.total_tiles == 0) return GSR_OK;
+    return launch_bin_finish(*p, cams, N, means2d, radii, depths, M, ws_prep, ws_fin, ids, ranges, keys,
+                             (hipStream_t)stream);
+}
+
 int gsr_rasterize_fwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
                       const float *means2d, const float *conics, const float *colors,
                       const float *opacities, const float *compensations, const float *background,
                       const int32_t *ranges, const int32_t *ids, float *image, float *alpha,
-                      float *final_T, int32_t *last_ids, int32_t *n_eval, gsr_stream_t stream) {
+                      float *final_T, int32_t *last_ids, int32_t *n_eval, void *ws, size_t ws_bytes,
+                      gsr_stream_t stream) {
     static const char *fn = "gsr_rasterize_fwd";
     int rc = check_params(p);
     CamTable cams;
@@ -208,8 +261,13 @@ int gsr_rasterize_fwd(const gsr_params *p, int C, int N, const int32_t *W, const
     GSR_NEED(ranges); GSR_NEED(image); GSR_NEED(alpha); GSR_NEED(final_T); GSR_NEED(last_ids);
     if (N > 0) { GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(colors); GSR_NEED(opacities); GSR_NEED(ids); }
     if (p->antialiased && N > 0) GSR_NEED(compensations);
+    if (N > 0) {
+        const size_t need = pack_workspace_bytes((int64_t)C * N);
+        if (!ws || ws_bytes < need)
+            return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws ? ws_bytes : 0);
+    }
     return launch_rasterize_fwd(*p, cams, N, means2d, conics, colors, opacities, compensations, background, ranges,
-                                ids, image, alpha, final_T, last_ids, n_eval, (hipStream_t)stream);
+                                ids, image, alpha, final_T, last_ids, n_eval, ws, (hipStream_t)stream);
 }
 
 int gsr_rasterize_bwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
@@ -218,7 +276,7 @@ int gsr_rasterize_bwd(const gsr_params *p, int C, int N, const int32_t *W, const
                       const int32_t *ranges, const int32_t *ids, const float *final_T,
                       const int32_t *last_ids, const float *v_image, const float *v_alpha,
                       float *v_means2d, float *v_conics, float *v_colors, float *v_opacities,
-                      float *v_means2d_abs, gsr_stream_t stream) {
+                      float *v_means2d_abs, void *ws, size_t ws_bytes, gsr_stream_t stream) {
     static const char *fn = "gsr_rasterize_bwd";
     int rc = check_params(p);
     CamTable cams;
@@ -229,9 +287,12 @@ int gsr_rasterize_bwd(const gsr_params *p, int C, int N, const int32_t *W, const
     GSR_NEED(final_T); GSR_NEED(last_ids); GSR_NEED(v_image);
     GSR_NEED(v_means2d); GSR_NEED(v_conics); GSR_NEED(v_colors); GSR_NEED(v_opacities);
     if (p->antialiased) GSR_NEED(compensations);
+    const size_t need = pack_workspace_bytes((int64_t)C * N);
+    if (!ws || ws_bytes < need)
+        return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws ? ws_bytes : 0);
     return launch_rasterize_bwd(*p, cams, N, means2d, conics, colors, opacities, compensations, background, ranges,
                                 ids, final_T, last_ids, v_image, v_alpha, v_means2d, v_conics, v_colors,
-                                v_opacities, v_means2d_abs, (hipStream_t)stream);
+                                v_opacities, v_means2d_abs, ws, (hipStream_t)stream);
 }
 
 int gsr_project_bwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,

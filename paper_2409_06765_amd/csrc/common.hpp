@@ -58,18 +58,27 @@ int launch_sort_pairs(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uin
                       int32_t *ids_alt, void *ws, hipStream_t s);
 int launch_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_t *ranges, hipStream_t s);
 
+size_t bin_prepare_bytes(int64_t n);
+size_t bin_finish_bytes(int64_t M);
+const int64_t *bin_total_ptr(void *ws_prep, int64_t n);
+int launch_bin_prepare(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
+                       const int32_t *radii, const float *depths, void *ws_prep, int64_t *total_dev, hipStream_t s);
+int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
+                      const int32_t *radii, const float *depths, int64_t M, void *ws_prep, void *ws_fin,
+                      int32_t *ids, int32_t *ranges, uint64_t *keys64, hipStream_t s);
+
 int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
                          const float *conics, const float *colors, const float *opacities,
                          const float *comps, const float *background, const int32_t *ranges,
                          const int32_t *ids, float *image, float *alpha, float *final_T, int32_t *last_ids,
-                         int32_t *n_eval, hipStream_t s);
+                         int32_t *n_eval, void *ws, hipStream_t s);
 
 int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
                          const float *conics, const float *colors, const float *opacities,
                          const float *comps, const float *background, const int32_t *ranges,
                          const int32_t *ids, const float *final_T, const int32_t *last_ids,
                          const float *v_image, const float *v_alpha, float *v_means2d, float *v_conics,
-                         float *v_colors, float *v_opac, float *v_means2d_abs, hipStream_t s);
+                         float *v_colors, float *v_opac, float *v_means2d_abs, void *ws, hipStream_t s);
 
 int launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
 
@@ -98,5 +107,55 @@ __device__ __forceinline__ void tile_rect(float mx, float my, int r, int TX, int
     y0 = (int)fminf(fmaxf(fy0, 0.0f), (float)TY);
     y1 = (int)fminf(fmaxf(fy1, 0.0f), (float)TY);
 }
+
+// Half-extents of the bounding box of a projected Gaussian's alpha >=
+// alpha_min support.  alpha = o exp(-sigma) reaches alpha_min only where
+// sigma <= L = ln(o / alpha_min), an ellipse with half-widths
+// sqrt(2 L Sigma'_xx), sqrt(2 L Sigma'_yy), Sigma' being the inverse conic.  L
+// is inflated by a margin larger than the float32 rounding of sigma at any
+// pixel (the absolute terms of sigma sum to at most 3 kappa sigma, kappa the
+// conic's condition number, so its relative error stays below about
+// 1e-6 kappa): a pixel outside the box takes the alpha < alpha_min skip in
+// the per-pixel test too.  Returns (-1e30, -1e30) when alpha never reaches
+// alpha_min and (1e30, 1e30) (no culling) for ill-conditioned conics.
+__device__ __forceinline__ float2 support_extent(float ca, float cb, float cc, float o, float alpha_min) {
+    if (!(o >= alpha_min)) return make_float2(-1e30f, -1e30f);   // o exp(-sigma) <= o < alpha_min
+    const float det = ca * cc - cb * cb;
+    if (!(det > 0.0f)) return make_float2(1e30f, 1e30f);
+    const float half_tr = 0.5f * (ca + cc);
+    const float lmax = half_tr + sqrtf(fmaxf(half_tr * half_tr - det, 0.0f));
+    const float kappa = lmax * lmax / det;
+    if (!(kappa < 1e5f)) return make_float2(1e30f, 1e30f);
+    const float L = logf(o / alpha_min);
+    const float grow = 1.0f + 4e-6f * kappa + 1e-4f;
+    const float Lp = L * grow + 1e-4f;
+    return make_float2(sqrtf(2.0f * Lp * cc / det) * grow + 1e-3f, sqrtf(2.0f * Lp * ca / det) * grow + 1e-3f);
+}
+
+// Which of the four 8x8 pixel quads of a tile (origin tile_x0, tile_y0) meet
+// the support box; bit q is quad (q & 1, q >> 1).
+__device__ __forceinline__ uint32_t quad_mask(float mx, float my, float hx, float hy, float tile_x0, float tile_y0) {
+    uint32_t m = 0u;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const float x0 = tile_x0 + (float)((q & 1) * 8) + 0.5f, x1 = x0 + 7.0f;
+        const float y0 = tile_y0 + (float)((q >> 1) * 8) + 0.5f, y1 = y0 + 7.0f;
+        if (mx + hx >= x0 && mx - hx <= x1 && my + hy >= y0 && my - hy <= y1) m |= 1u << q;
+    }
+    return m;
+}
+
+// Per projected Gaussian record read by the compositing kernels:
+// {mean x, mean y, opacity (times compensation), support half-width x},
+// {conic a, b, c, support half-width y}, {colour r, g, b, 0}.
+struct PackedGauss {
+    float4 xyoh;
+    float4 conh;
+    float4 col;
+};
+
+size_t pack_workspace_bytes(int64_t cn);
+int launch_pack(const gsr_params &p, int CN, int N, const float *means2d, const float *conics, const float *colors,
+                const float *opacities, const float *comps, PackedGauss *out, hipStream_t s);
 
 }  // namespace gsr

@@ -1,8 +1,17 @@
 // Tile binning, key emission, stable LSD radix sort and tile ranges
 // (Rasterization of Gaussians: 16x16 tiles, per-tile depth order).
 //
-// Prefix sums and the sort use reduce-then-scan (no inter-block waiting), so
-// every kernel finishes regardless of the order in which blocks are scheduled.
+// Two ways to the same per-tile lists:
+//  * the general one: (tile << 32 | depth bits, id) pairs emitted in
+//    (camera, Gaussian, row-major tile) order, stably radix-sorted on all
+//    key bits;
+//  * the binning path used by the pipeline: the projected Gaussians are
+//    first stably sorted by depth bits (C*N 32-bit keys), their tiles are then
+//    emitted in that order with 32-bit tile keys, and a stable sort on the
+//    tile bits alone (two passes at 1080p) finishes the job.  Stability makes
+//    the result (tile, depth bits, id) order, identical bit for bit.
+// Prefix sums and sorts use reduce-then-scan (no inter-block waiting), so
+// every kernel finishes whatever the order in which blocks are scheduled.
 #include "common.hpp"
 
 #pragma clang fp contract(off)
@@ -19,7 +28,6 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// Inclusive scan across the 64 lanes of a wave.
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T v) {
     const int lane = __lane_id();
@@ -60,7 +68,8 @@ __device__ __forceinline__ int tile_count(const CamTable &cams, int N, int64_t g
     return (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0;
 }
 
-// Pass 1: tiles per Gaussian and per-block sums.
+// ---- prefix sums ----------------------------------------------------------
+// Tiles per Gaussian and per-block sums.
 __global__ void __launch_bounds__(kScanThreads) count_kernel(CamTable cams, int N, int64_t n_total,
         const float *__restrict__ means2d, const int32_t *__restrict__ radii, int32_t *__restrict__ counts,
         int64_t *__restrict__ block_sums) {
@@ -80,7 +89,20 @@ __global__ void __launch_bounds__(kScanThreads) count_kernel(CamTable cams, int 
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
-// Pass 2: one block turns the block sums into exclusive block offsets.
+// Per-block sums of an int32 array.
+__global__ void __launch_bounds__(kScanThreads) block_sums_kernel(int64_t n_total, const int32_t *__restrict__ vals,
+                                                                  int64_t *__restrict__ block_sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t local = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++)
+        if (base + i < n_total) local += vals[base + i];
+    int64_t total;
+    block_exclusive_scan<int64_t>(local, total);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// One block turns the block sums into exclusive block offsets.
 __global__ void __launch_bounds__(kScanThreads) scan_sums_kernel(int64_t *__restrict__ sums, int64_t nb,
                                                                  int64_t *__restrict__ total_out) {
     int64_t carry = 0;
@@ -95,7 +117,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_sums_kernel(int64_t *__rest
     if (threadIdx.x == 0) *total_out = carry;
 }
 
-// Pass 3: per-element exclusive offsets.
+// Per-element exclusive offsets.
 __global__ void __launch_bounds__(kScanThreads) offsets_kernel(int64_t n_total, const int32_t *__restrict__ counts,
         const int64_t *__restrict__ block_off, int64_t *__restrict__ offsets) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
@@ -115,28 +137,46 @@ __global__ void __launch_bounds__(kScanThreads) offsets_kernel(int64_t n_total, 
     }
 }
 
-// Key emission, one wave per 64 consecutive projected Gaussians: the wave's
+// ---- key emission ------------------------------------------------------------
+// One wave per 64 consecutive entries of the emission sequence (projected
+// Gaussians in id order, or in depth order when `order` is given): the wave's
 // output range is contiguous, so lanes stride over it and each finds the
-// Gaussian owning its slot by binary search; writes are fully coalesced and
-// a Gaussian covering thousands of tiles is spread over the whole wave.
+// entry owning its slot by binary search; writes are fully coalesced and a
+// Gaussian covering thousands of tiles is spread over the whole wave.  Keys
+// are tile << 32 | depth bits (uint64) or the tile id alone (uint32).
 constexpr int kEmitThreads = 256;
+
+template <typename K>
+__device__ __forceinline__ K make_key(uint32_t tile, uint32_t dbits);
+template <>
+__device__ __forceinline__ uint64_t make_key<uint64_t>(uint32_t tile, uint32_t dbits) {
+    return ((uint64_t)tile << 32) | (uint64_t)dbits;
+}
+template <>
+__device__ __forceinline__ uint32_t make_key<uint32_t>(uint32_t tile, uint32_t) { return tile; }
+
+template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N, int64_t n_total,
         const float *__restrict__ means2d, const int32_t *__restrict__ radii, const float *__restrict__ depths,
-        const int64_t *__restrict__ offsets, int64_t cap, uint64_t *__restrict__ keys, int32_t *__restrict__ ids) {
+        const int32_t *__restrict__ order, const int64_t *__restrict__ offsets, int64_t cap, K *__restrict__ keys,
+        int32_t *__restrict__ ids) {
     __shared__ int32_t s_rel[kEmitThreads];   // slot of the lane's first entry, relative to the wave
-    __shared__ int32_t s_x0[kEmitThreads], s_y0[kEmitThreads], s_w[kEmitThreads];
+    __shared__ int32_t s_w[kEmitThreads];     // rectangle width in tiles
     __shared__ int32_t s_row[kEmitThreads];   // tile_base + y0 * TX + x0 of the lane's camera
     __shared__ int32_t s_TX[kEmitThreads];
     __shared__ uint32_t s_dbits[kEmitThreads];
+    __shared__ int32_t s_g[kEmitThreads];
     const int lane = __lane_id(), w = threadIdx.x / kWave;
-    const int64_t g = (int64_t)blockIdx.x * kEmitThreads + threadIdx.x;
-    const int64_t g0 = (int64_t)blockIdx.x * kEmitThreads + (int64_t)w * kWave;
-    if (g0 >= n_total) return;                // whole wave past the end (wave-uniform)
+    const int64_t s = (int64_t)blockIdx.x * kEmitThreads + threadIdx.x;
+    const int64_t s0 = (int64_t)blockIdx.x * kEmitThreads + (int64_t)w * kWave;
+    if (s0 >= n_total) return;                // whole wave past the end (wave-uniform)
     int cnt = 0, x0 = 0, x1 = 0, y0 = 0, y1 = 0, TX = 0, row = 0;
-    int64_t off = 0;
+    int64_t off = 0, g = 0;
     uint32_t dbits = 0;
-    if (g < n_total) {
-        off = offsets[g];
+    if (s < n_total) {
+        g = order ? order[s] : s;
+        if (g < 0 || g >= n_total) g = 0;     // order comes from the depth sort; this only bounds a bad input
+        off = offsets[s];
         const int r = radii[g];
         if (r > 0) {
             const int c = (int)(g / N);
@@ -149,16 +189,18 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
     }
     const int64_t wbase = __shfl(off, 0, kWave);
     int64_t end = off + cnt;
-    // wave end = the largest end (offsets are non-decreasing)
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         const int64_t o2 = __shfl_xor(end, d, kWave);
         end = o2 > end ? o2 : end;
     }
     const int total = (int)(end - wbase);
-    s_rel[threadIdx.x] = (g < n_total) ? (int)(off - wbase) : 0x7fffffff;
-    s_x0[threadIdx.x] = x0; s_y0[threadIdx.x] = y0; s_w[threadIdx.x] = x1 - x0;
-    s_row[threadIdx.x] = row; s_TX[threadIdx.x] = TX; s_dbits[threadIdx.x] = dbits;
+    s_rel[threadIdx.x] = (s < n_total) ? (int)(off - wbase) : 0x7fffffff;
+    s_w[threadIdx.x] = x1 - x0;
+    s_row[threadIdx.x] = row;
+    s_TX[threadIdx.x] = TX;
+    s_dbits[threadIdx.x] = dbits;
+    s_g[threadIdx.x] = (int32_t)g;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -172,14 +214,14 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
         }
         const int k = wb + lo;
         const int local = j - s_rel[k];
-        const int wdt = s_w[k];
+        const int wdt = max(s_w[k], 1);
         const int dy = local / wdt;
         const int dx = local - dy * wdt;
         const uint32_t tile = (uint32_t)(s_row[k] + dy * s_TX[k] + dx);
         const int64_t pos = wbase + j;
         if (pos < cap) {
-            keys[pos] = ((uint64_t)tile << 32) | (uint64_t)s_dbits[k];
-            ids[pos] = (int32_t)(g0 + lo);
+            keys[pos] = make_key<K>(tile, s_dbits[k]);
+            ids[pos] = s_g[k];
         }
     }
 }
@@ -189,19 +231,56 @@ __global__ void fill_zero_kernel(uint32_t *__restrict__ p, int64_t n_words) {
         p[i] = 0u;
 }
 
-__global__ void ranges_kernel(int64_t M, const uint64_t *__restrict__ keys, int32_t total_tiles,
-                              int32_t *__restrict__ ranges) {
+template <typename K>
+__device__ __forceinline__ int32_t tile_of(K key) { return (int32_t)(sizeof(K) == 8 ? (uint64_t)key >> 32 : key); }
+
+template <typename K>
+__global__ void ranges_kernel(int64_t M, const K *__restrict__ keys, int32_t total_tiles, int32_t *__restrict__ ranges) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
-    const int32_t t = (int32_t)(keys[i] >> 32);
+    const int32_t t = tile_of<K>(keys[i]);
     if (t < 0 || t >= total_tiles) return;
-    if (i == 0 || (int32_t)(keys[i - 1] >> 32) != t) ranges[2 * t] = (int32_t)i;
-    if (i == M - 1 || (int32_t)(keys[i + 1] >> 32) != t) ranges[2 * t + 1] = (int32_t)(i + 1);
+    if (i == 0 || tile_of<K>(keys[i - 1]) != t) ranges[2 * t] = (int32_t)i;
+    if (i == M - 1 || tile_of<K>(keys[i + 1]) != t) ranges[2 * t + 1] = (int32_t)(i + 1);
+}
+
+// ---- binning-path helpers -------------------------------------------------------
+// Depth-sort keys of the projected Gaussians (culled ones last) and their counts.
+__global__ void __launch_bounds__(256) bin_keys_kernel(CamTable cams, int N, int64_t n_total,
+        const float *__restrict__ means2d, const int32_t *__restrict__ radii, const float *__restrict__ depths,
+        int32_t *__restrict__ counts, uint32_t *__restrict__ dkeys, int32_t *__restrict__ dvals) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_total) return;
+    const int k = tile_count(cams, N, g, means2d, radii);
+    counts[g] = k;
+    dkeys[g] = k > 0 ? __float_as_uint(depths[g]) : 0xFFFFFFFFu;
+    dvals[g] = (int32_t)g;
+}
+
+// Counts in depth order.
+__global__ void __launch_bounds__(256) gather_counts_kernel(int64_t n_total, const int32_t *__restrict__ order,
+                                                            const int32_t *__restrict__ counts,
+                                                            int32_t *__restrict__ counts_sorted) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_total) return;
+    const int32_t g = order[s];
+    counts_sorted[s] = (g >= 0 && g < n_total) ? counts[g] : 0;
+}
+
+// 64-bit keys of the sorted lists (only when a caller asks for them).
+__global__ void __launch_bounds__(256) keys64_kernel(int64_t M, const uint32_t *__restrict__ tkeys,
+                                                     const int32_t *__restrict__ ids, const float *__restrict__ depths,
+                                                     int64_t n_total, uint64_t *__restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int32_t g = ids[i];
+    const uint32_t db = (g >= 0 && g < n_total) ? __float_as_uint(depths[g]) : 0u;
+    keys[i] = ((uint64_t)tkeys[i] << 32) | db;
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort of (uint64 key, int32 id), up to 8 bits per pass.
-// Per pass: (1) per-block digit histograms, stored digit-major;
+// Stable LSD radix sort of (uint64 or uint32 key, int32 id), up to 8 bits per
+// pass.  Per pass: (1) per-block digit histograms, stored digit-major;
 // (2) one block per digit scans its row over the blocks; (3) each block
 // ranks its elements stably (wave-level match on the digit bits, then wave
 // and block prefixes), reorders them in LDS and writes digit runs out.
@@ -223,14 +302,14 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, uint64_t a
     return m;
 }
 
-__global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t *__restrict__ keys, int64_t M,
+template <typename K>
+__global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K *__restrict__ keys, int64_t M,
         int shift, int bits, int nblocks, int32_t *__restrict__ hist) {
     __shared__ int32_t cnt[kBins];
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t mask = (1u << bits) - 1u;
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    const int lane = __lane_id();
 #pragma unroll
     for (int i = 0; i < kSortItems; i++) {
         const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
@@ -239,7 +318,6 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t
         const uint64_t active = __ballot(valid);
         const uint64_t peers = match_digit(d, bits, active);
         if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&cnt[d], (int32_t)__popcll(peers));
-        (void)lane;
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
@@ -262,11 +340,12 @@ __global__ void __launch_bounds__(kScanThreads) radix_rowscan_kernel(int32_t *__
     if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
-__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const uint64_t *__restrict__ keys_in,
-        const int32_t *__restrict__ ids_in, uint64_t *__restrict__ keys_out, int32_t *__restrict__ ids_out,
+template <typename K>
+__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__restrict__ keys_in,
+        const int32_t *__restrict__ ids_in, K *__restrict__ keys_out, int32_t *__restrict__ ids_out,
         int64_t M, int shift, int bits, int nblocks, const int32_t *__restrict__ hist,
         const int32_t *__restrict__ digit_tot) {
-    __shared__ uint64_t s_keys[kSortTile];
+    __shared__ K s_keys[kSortTile];
     __shared__ int32_t s_ids[kSortTile];
     __shared__ int32_t s_wcnt[kSortWaves][kBins];
     __shared__ int32_t s_dstart[kBins];
@@ -286,7 +365,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const uint6
     __syncthreads();
 
     // load, wave-striped: wave w owns [w*64*ITEMS, (w+1)*64*ITEMS) of the tile
-    uint64_t key[kSortItems];
+    K key[kSortItems];
     int32_t val[kSortItems];
     int32_t rank[kSortItems];
     const uint64_t lt = lanemask_lt();
@@ -294,7 +373,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const uint6
     for (int i = 0; i < kSortItems; i++) {
         const int64_t idx = base + (int64_t)w * (kWave * kSortItems) + i * kWave + lane;
         const bool valid = idx < M;
-        key[i] = valid ? keys_in[idx] : 0ull;
+        key[i] = valid ? keys_in[idx] : (K)0;
         val[i] = valid ? ids_in[idx] : 0;
         const uint32_t d = (uint32_t)(key[i] >> shift) & mask;
         const uint64_t active = __ballot(valid);
@@ -330,7 +409,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const uint6
     __syncthreads();
     const int n_valid = (int)((M - base) < kSortTile ? (M - base) : kSortTile);
     for (int j = t; j < n_valid; j += kSortThreads) {
-        const uint64_t k = s_keys[j];
+        const K k = s_keys[j];
         const uint32_t d = (uint32_t)(k >> shift) & mask;
         const int64_t gpos = (int64_t)s_gout[d] + (j - s_dstart[d]);
         if (gpos >= 0 && gpos < M) {
@@ -341,6 +420,109 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const uint6
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t radix_ws_bytes(int64_t M) {
+    const int64_t nb = (M + kSortTile - 1) / kSortTile;
+    return align256((size_t)kBins * (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)) + align256(kBins * sizeof(int32_t));
+}
+
+// Sorts M pairs by the low key_bits bits; an even number of passes leaves
+// the result in keys/ids.
+template <typename K>
+int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int32_t *ids_alt, void *ws,
+               hipStream_t s) {
+    if (M <= 1) return GSR_OK;
+    int passes = (key_bits + 7) / 8;
+    if (passes % 2) passes++;
+    const int width = (key_bits + passes - 1) / passes;
+    const int nb = (int)((M + kSortTile - 1) / kSortTile);
+    int32_t *hist = (int32_t *)ws;
+    int32_t *dtot = (int32_t *)((char *)ws + align256((size_t)kBins * nb * sizeof(int32_t)));
+    K *kin = keys, *kout = keys_alt;
+    int32_t *iin = ids, *iout = ids_alt;
+    for (int ps = 0; ps < passes; ps++) {
+        const int shift = ps * width;
+        int bits = key_bits - shift;
+        if (bits > width) bits = width;
+        if (bits < 0) bits = 0;   // a padding pass: every digit 0, a stable copy
+        radix_hist_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, M, shift, bits, nb, hist);
+        radix_rowscan_kernel<<<kBins, kScanThreads, 0, s>>>(hist, nb, dtot);
+        radix_scatter_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, iin, kout, iout, M, shift, bits, nb, hist, dtot);
+        K *tk = kin; kin = kout; kout = tk;
+        int32_t *ti = iin; iin = iout; iout = ti;
+    }
+    return launch_check("radix_sort");
+}
+
+// Binning workspace layout: prepare part (C*N sized, kept until finish).
+struct BinPrep {
+    int32_t *counts;         // [n] tiles per projected Gaussian
+    uint32_t *dkeys, *dkeys_alt;
+    int32_t *order, *order_alt;   // depth order of the projected Gaussians
+    int32_t *counts_sorted;  // [n]
+    int64_t *offsets_sorted; // [n]
+    int64_t *block_sums;     // scan partials
+    int64_t *total;          // [1]
+    void *sort_ws;
+};
+
+BinPrep carve_prep(void *ws, int64_t n) {
+    BinPrep b;
+    char *p = (char *)ws;
+    auto take = [&](size_t bytes) { void *q = p; p += align256(bytes); return q; };
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    b.counts = (int32_t *)take(nn * 4);
+    b.dkeys = (uint32_t *)take(nn * 4);
+    b.dkeys_alt = (uint32_t *)take(nn * 4);
+    b.order = (int32_t *)take(nn * 4);
+    b.order_alt = (int32_t *)take(nn * 4);
+    b.counts_sorted = (int32_t *)take(nn * 4);
+    b.offsets_sorted = (int64_t *)take(nn * 8);
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    b.block_sums = (int64_t *)take((size_t)(nb > 0 ? nb : 1) * 8);
+    b.total = (int64_t *)take(8);
+    b.sort_ws = (void *)take(radix_ws_bytes(n));
+    return b;
+}
+
+size_t prep_bytes(int64_t n) {
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    return 6 * align256(nn * 4) + align256(nn * 8) + align256((size_t)(nb > 0 ? nb : 1) * 8) + align256(8) +
+           radix_ws_bytes(n);
+}
+
+struct BinFin {
+    uint32_t *tkeys, *tkeys_alt;
+    int32_t *ids_alt;
+    void *sort_ws;
+};
+
+BinFin carve_fin(void *ws, int64_t M) {
+    BinFin b;
+    char *p = (char *)ws;
+    auto take = [&](size_t bytes) { void *q = p; p += align256(bytes); return q; };
+    const size_t mm = (size_t)(M > 0 ? M : 1);
+    b.tkeys = (uint32_t *)take(mm * 4);
+    b.tkeys_alt = (uint32_t *)take(mm * 4);
+    b.ids_alt = (int32_t *)take(mm * 4);
+    b.sort_ws = (void *)take(radix_ws_bytes(M));
+    return b;
+}
+
+size_t fin_bytes(int64_t M) {
+    const size_t mm = (size_t)(M > 0 ? M : 1);
+    return 3 * align256(mm * 4) + radix_ws_bytes(M);
+}
+
+int scan_counts(int64_t n, const int32_t *counts, int64_t *block_sums, int64_t *offsets, int64_t *total,
+                hipStream_t s) {
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    block_sums_kernel<<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(n, counts, block_sums);
+    scan_sums_kernel<<<1, kScanThreads, 0, s>>>(block_sums, nb, total);
+    offsets_kernel<<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(n, counts, block_sums, offsets);
+    return launch_check("scan");
+}
 
 }  // namespace
 
@@ -370,8 +552,8 @@ int launch_intersect_emit(const gsr_params &p, const CamTable &cams, int N, cons
     const int64_t n = (int64_t)cams.C * N;
     if (n == 0 || cap == 0) return GSR_OK;
     const int64_t nb = (n + kEmitThreads - 1) / kEmitThreads;
-    emit_kernel<<<dim3((unsigned)nb), dim3(kEmitThreads), 0, s>>>(cams, N, n, means2d, radii, depths, offsets,
-                                                                 cap, keys, ids);
+    emit_kernel<uint64_t><<<dim3((unsigned)nb), dim3(kEmitThreads), 0, s>>>(cams, N, n, means2d, radii, depths,
+                                                                           nullptr, offsets, cap, keys, ids);
     return launch_check("intersect_emit");
 }
 
@@ -387,39 +569,58 @@ int launch_fill_zero(void *ptr, size_t bytes, hipStream_t s) {
 int launch_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_t *ranges, hipStream_t s) {
     int rc = launch_fill_zero(ranges, (size_t)total_tiles * 2 * sizeof(int32_t), s);
     if (rc != GSR_OK || M == 0) return rc;
-    ranges_kernel<<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, keys, total_tiles, ranges);
+    ranges_kernel<uint64_t><<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, keys, total_tiles, ranges);
     return launch_check("tile_ranges");
 }
 
-size_t sort_workspace_bytes(int64_t M) {
-    const int64_t nb = (M + kSortTile - 1) / kSortTile;
-    return align256((size_t)kBins * (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)) + align256(kBins * sizeof(int32_t));
-}
+size_t sort_workspace_bytes(int64_t M) { return radix_ws_bytes(M); }
 
 int launch_sort_pairs(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uint64_t *keys_alt,
                       int32_t *ids_alt, void *ws, hipStream_t s) {
-    if (M <= 1) return GSR_OK;
-    // An even number of passes leaves the result in keys/ids.
-    int passes = (key_bits + 7) / 8;
-    if (passes % 2) passes++;
-    const int width = (key_bits + passes - 1) / passes;
-    const int nb = (int)((M + kSortTile - 1) / kSortTile);
-    int32_t *hist = (int32_t *)ws;
-    int32_t *dtot = (int32_t *)((char *)ws + align256((size_t)kBins * nb * sizeof(int32_t)));
-    uint64_t *kin = keys, *kout = keys_alt;
-    int32_t *iin = ids, *iout = ids_alt;
-    for (int ps = 0; ps < passes; ps++) {
-        const int shift = ps * width;
-        int bits = key_bits - shift;
-        if (bits > width) bits = width;
-        if (bits < 1) bits = 1;   // only when passes were padded to an even count
-        radix_hist_kernel<<<nb, kSortThreads, 0, s>>>(kin, M, shift, bits, nb, hist);
-        radix_rowscan_kernel<<<kBins, kScanThreads, 0, s>>>(hist, nb, dtot);
-        radix_scatter_kernel<<<nb, kSortThreads, 0, s>>>(kin, iin, kout, iout, M, shift, bits, nb, hist, dtot);
-        uint64_t *tk = kin; kin = kout; kout = tk;
-        int32_t *ti = iin; iin = iout; iout = ti;
-    }
-    return launch_check("sort_pairs");
+    return radix_sort<uint64_t>(M, key_bits, keys, ids, keys_alt, ids_alt, ws, s);
+}
+
+size_t bin_prepare_bytes(int64_t n) { return prep_bytes(n); }
+size_t bin_finish_bytes(int64_t M) { return fin_bytes(M); }
+const int64_t *bin_total_ptr(void *ws_prep, int64_t n) { return carve_prep(ws_prep, n).total; }
+
+int launch_bin_prepare(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
+                       const int32_t *radii, const float *depths, void *ws_prep, int64_t *total_dev, hipStream_t s) {
+    (void)p;
+    const int64_t n = (int64_t)cams.C * N;
+    BinPrep b = carve_prep(ws_prep, n);
+    if (n == 0) return launch_fill_zero(b.total, sizeof(int64_t), s);
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    bin_keys_kernel<<<nb, 256, 0, s>>>(cams, N, n, means2d, radii, depths, b.counts, b.dkeys, b.order);
+    int rc = radix_sort<uint32_t>(n, 32, b.dkeys, b.order, b.dkeys_alt, b.order_alt, b.sort_ws, s);
+    if (rc != GSR_OK) return rc;
+    gather_counts_kernel<<<nb, 256, 0, s>>>(n, b.order, b.counts, b.counts_sorted);
+    rc = scan_counts(n, b.counts_sorted, b.block_sums, b.offsets_sorted, b.total, s);
+    if (rc == GSR_OK && total_dev)
+        rc = hip_check(hipMemcpyAsync(total_dev, b.total, sizeof(int64_t), hipMemcpyDeviceToDevice, s), "bin_prepare");
+    return rc;
+}
+
+int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
+                      const int32_t *radii, const float *depths, int64_t M, void *ws_prep, void *ws_fin,
+                      int32_t *ids, int32_t *ranges, uint64_t *keys64, hipStream_t s) {
+    (void)p;
+    const int64_t n = (int64_t)cams.C * N;
+    BinPrep b = carve_prep(ws_prep, n);
+    BinFin f = carve_fin(ws_fin, M);
+    int rc = launch_fill_zero(ranges, (size_t)cams.total_tiles * 2 * sizeof(int32_t), s);
+    if (rc != GSR_OK || n == 0 || M == 0) return rc;
+    const int64_t ne = (n + kEmitThreads - 1) / kEmitThreads;
+    emit_kernel<uint32_t><<<dim3((unsigned)ne), dim3(kEmitThreads), 0, s>>>(cams, N, n, means2d, radii, depths,
+                                                                           b.order, b.offsets_sorted, M, f.tkeys, ids);
+    const int tile_bits = cams.total_tiles > 1 ? 32 - __builtin_clz((unsigned)(cams.total_tiles - 1)) : 1;
+    rc = radix_sort<uint32_t>(M, tile_bits, f.tkeys, ids, f.tkeys_alt, f.ids_alt, f.sort_ws, s);
+    if (rc != GSR_OK) return rc;
+    ranges_kernel<uint32_t><<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, f.tkeys, cams.total_tiles,
+                                                                                  ranges);
+    if (keys64)
+        keys64_kernel<<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, f.tkeys, ids, depths, n, keys64);
+    return launch_check("bin_finish");
 }
 
 }  // namespace gsr

@@ -1,12 +1,14 @@
 // Front-to-back alpha compositing of 16x16 tiles (Rasterization of Gaussians).
 //
 // One 256-thread block per tile; each of the four wave64s owns an 8x8 pixel
-// quad (compact quads keep a wave's lanes on the same side of a Gaussian's
-// support).  The tile's sorted list is walked in batches of 256 Gaussians
-// staged in LDS with one coalesced gather per batch; every lane then reads
-// the same LDS entry (broadcast).  A pixel stops when its next composite
-// would take T below T_min; the block leaves the list as soon as all its
-// pixels have stopped (counted at each batch boundary).
+// quad.  The tile's sorted list is walked in batches of 256 Gaussians staged
+// in LDS by one coalesced gather; while staging, each Gaussian also records
+// which quads its alpha >= alpha_min support box (precomputed per projected
+// Gaussian by pack_kernel) can reach, so a wave
+// skips, with a scalar branch, the entries that are below alpha_min at all
+// its pixels.  The per-pixel update is branch-free (selects), so the wave
+// never splits on skip/stop decisions.  The block leaves the list once every
+// pixel has stopped.
 #include "common.hpp"
 
 namespace gsr {
@@ -15,15 +17,27 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kBatch = 256;
 
+__global__ void __launch_bounds__(256) pack_kernel(int CN, int N, float alpha_min,
+        const float *__restrict__ means2d, const float *__restrict__ conics, const float *__restrict__ colors,
+        const float *__restrict__ opacities, const float *__restrict__ comps, PackedGauss *__restrict__ out) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= CN) return;
+    float o = opacities[g % N];
+    if (comps) o *= comps[g];
+    const float ca = conics[3 * g], cb = conics[3 * g + 1], cc = conics[3 * g + 2];
+    const float2 h = support_extent(ca, cb, cc, o, alpha_min);
+    PackedGauss r;
+    r.xyoh = make_float4(means2d[2 * g], means2d[2 * g + 1], o, h.x);
+    r.conh = make_float4(ca, cb, cc, h.y);
+    r.col = make_float4(colors[3 * g], colors[3 * g + 1], colors[3 * g + 2], 0.0f);
+    out[g] = r;
+}
+
 struct RasterArgs {
     gsr_params p;
     int N;
     int CN;
-    const float *__restrict__ means2d;
-    const float *__restrict__ conics;
-    const float *__restrict__ colors;
-    const float *__restrict__ opacities;
-    const float *__restrict__ comps;
+    const PackedGauss *__restrict__ gauss;
     const float *__restrict__ background;
     const int32_t *__restrict__ ranges;
     const int32_t *__restrict__ ids;
@@ -35,7 +49,7 @@ struct RasterArgs {
 };
 
 __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamTable cams) {
-    __shared__ float4 s_xyo[kBatch];   // mean x, mean y, opacity, -
+    __shared__ float4 s_xyo[kBatch];   // mean x, mean y, opacity, quad mask bits
     __shared__ float4 s_con[kBatch];   // conic a, b, c, -
     __shared__ float4 s_col[kBatch];   // colour r, g, b, -
 
@@ -44,16 +58,17 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     const CamInfo ci = cams.cam[c];
     const int lt = tile - ci.tile_base;
     const int ty = lt / ci.TX, tx = lt - ty * ci.TX;
-    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
     const int xi = tx * kTile + (w & 1) * 8 + (lane & 7);
     const int yi = ty * kTile + (w >> 1) * 8 + (lane >> 3);
     const bool inside = xi < ci.W && yi < ci.H;
     const float px = (float)xi + 0.5f, py = (float)yi + 0.5f;
+    const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
     const int start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const float amin = a.p.alpha_min, amax = a.p.alpha_max, tmin = a.p.T_min;
 
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    int last = -1, nev = 0, ncomp = 0;
+    int last = -1, ncomp = 0, stop_at = -1;
     bool done = !inside;
     for (int b0 = start; b0 < end; b0 += kBatch) {
         if (__syncthreads_count(done) == kThreads) break;
@@ -61,34 +76,36 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
         if (k < end) {
             int g = a.ids[k];
             if ((unsigned)g >= (unsigned)a.CN) g = 0;   // ids come from the sort; this only bounds a bad input
-            const int n = g % a.N;
-            float o = a.opacities[n];
-            if (a.comps) o *= a.comps[g];
-            s_xyo[threadIdx.x] = make_float4(a.means2d[2 * g], a.means2d[2 * g + 1], o, 0.0f);
-            s_con[threadIdx.x] = make_float4(a.conics[3 * g], a.conics[3 * g + 1], a.conics[3 * g + 2], 0.0f);
-            s_col[threadIdx.x] = make_float4(a.colors[3 * g], a.colors[3 * g + 1], a.colors[3 * g + 2], 0.0f);
+            const PackedGauss r = a.gauss[g];
+            const uint32_t qm = quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0);
+            s_xyo[threadIdx.x] = make_float4(r.xyoh.x, r.xyoh.y, r.xyoh.z, __uint_as_float(qm));
+            s_con[threadIdx.x] = r.conh;
+            s_col[threadIdx.x] = r.col;
         }
         __syncthreads();
         const int cnt = min(kBatch, end - b0);
-        if (!done) {
-            for (int j = 0; j < cnt; j++) {
-                const float4 xyo = s_xyo[j];
-                const float4 con = s_con[j];
-                const float dx = xyo.x - px, dy = xyo.y - py;
-                const float sigma = 0.5f * (con.x * dx * dx + con.z * dy * dy) + con.y * dx * dy;
-                nev++;
-                if (sigma < 0.0f) continue;
-                const float al = fminf(amax, xyo.z * __expf(-sigma));
-                if (al < amin) continue;
-                const float Tn = T * (1.0f - al);
-                if (Tn < tmin) { done = true; break; }
-                const float wgt = al * T;
-                const float4 col = s_col[j];
-                C0 += col.x * wgt; C1 += col.y * wgt; C2 += col.z * wgt;
-                T = Tn;
-                last = b0 + j;
-                ncomp++;
-            }
+        if (__all(done)) continue;
+        for (int j = 0; j < cnt; j++) {
+            const float4 xyo = s_xyo[j];
+            const uint32_t qm = __builtin_amdgcn_readfirstlane(__float_as_uint(xyo.w));
+            if (!((qm >> w) & 1u)) continue;            // below alpha_min at every pixel of this quad
+            const float4 con = s_con[j];
+            const float dx = xyo.x - px, dy = xyo.y - py;
+            const float sigma = 0.5f * (con.x * dx * dx + con.z * dy * dy) + con.y * dx * dy;
+            const float al = fminf(amax, xyo.z * __expf(-sigma));
+            const float Tn = T * (1.0f - al);
+            const bool use = !done && sigma >= 0.0f && al >= amin;
+            const bool stop = use && Tn < tmin;
+            const bool comp = use && !stop;
+            stop_at = stop ? b0 + j : stop_at;
+            done = done || stop;
+            const float wgt = comp ? al * T : 0.0f;
+            const float4 col = s_col[j];
+            C0 += col.x * wgt; C1 += col.y * wgt; C2 += col.z * wgt;
+            T = comp ? Tn : T;
+            last = comp ? b0 + j : last;
+            ncomp += comp ? 1 : 0;
+            if ((j & 15) == 15 && __all(done)) break;
         }
     }
     if (!inside) return;
@@ -102,21 +119,36 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     a.final_T[pix] = T;
     a.last_ids[pix] = last;
     if (a.n_eval) {
-        a.n_eval[2 * pix] = nev;
+        // entries evaluated: up to and including the one that stopped the pixel, else the whole list
+        a.n_eval[2 * pix] = stop_at >= 0 ? stop_at - start + 1 : end - start;
         a.n_eval[2 * pix + 1] = ncomp;
     }
 }
 
 }  // namespace
 
+size_t pack_workspace_bytes(int64_t cn) { return ((size_t)(cn > 0 ? cn : 1) * sizeof(PackedGauss) + 255) & ~(size_t)255; }
+
+int launch_pack(const gsr_params &p, int CN, int N, const float *means2d, const float *conics, const float *colors,
+                const float *opacities, const float *comps, PackedGauss *out, hipStream_t s) {
+    pack_kernel<<<dim3((unsigned)((CN + 255) / 256)), dim3(256), 0, s>>>(CN, N, p.alpha_min, means2d, conics, colors,
+                                                                        opacities, comps, out);
+    return launch_check("pack");
+}
+
 int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
                          const float *conics, const float *colors, const float *opacities,
                          const float *comps, const float *background, const int32_t *ranges,
                          const int32_t *ids, float *image, float *alpha, float *final_T, int32_t *last_ids,
-                         int32_t *n_eval, hipStream_t s) {
+                         int32_t *n_eval, void *ws, hipStream_t s) {
     if (cams.total_tiles == 0) return GSR_OK;
-    RasterArgs a{p, N, cams.C * N, means2d, conics, colors, opacities, p.antialiased ? comps : nullptr, background, ranges,
-                 ids, image, alpha, final_T, last_ids, n_eval};
+    const int CN = cams.C * N;
+    PackedGauss *gauss = (PackedGauss *)ws;
+    if (CN > 0) {
+        int rc = launch_pack(p, CN, N, means2d, conics, colors, opacities, p.antialiased ? comps : nullptr, gauss, s);
+        if (rc != GSR_OK) return rc;
+    }
+    RasterArgs a{p, N, CN, gauss, background, ranges, ids, image, alpha, final_T, last_ids, n_eval};
     raster_fwd_kernel<<<dim3((unsigned)cams.total_tiles), dim3(kThreads), 0, s>>>(a, cams);
     return launch_check("rasterize_fwd");
 }

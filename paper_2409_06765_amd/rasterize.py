@@ -54,16 +54,36 @@ def project(p, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H
     return out
 
 
-def intersect(p, proj, W, H, stream=None):
-    """Tile binning, key emission, stable radix sort, tile ranges.  Waits
-    once for the intersection count, which sizes the key buffers."""
+def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None):
+    """Per-tile depth-sorted lists.  Waits once for the intersection count,
+    which sizes the list buffers.
+
+    method="bin": depth order of the projected Gaussians, then a stable sort
+    of 32-bit tile keys (gsr_bin_prepare / gsr_bin_finish); method="keys64":
+    count, emit 64-bit keys, stable radix sort, ranges.  Both give the same
+    ids and ranges."""
     C, N = proj["radii"].shape
     d = proj["radii"].device
     _, tile_off = layout(W, H)
     total_tiles = tile_off[-1]
+    total = torch.empty(1, device=d, dtype=torch.int64)
+    ranges = torch.empty((max(total_tiles, 1), 2), device=d, dtype=torch.int32)
+    key_bits = 32 + max(total_tiles - 1, 0).bit_length()
+    if method == "bin":
+        wsp = torch.empty(max(L.workspace_bytes(L.GSR_OP_BIN_PREPARE, C, N, 0), 1), device=d, dtype=torch.uint8)
+        M = L.gsr_bin_prepare(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], total, wsp,
+                              sync=True, stream=stream)
+        ids = torch.empty(max(M, 1), device=d, dtype=torch.int32)
+        keys = torch.empty(max(M, 1), device=d, dtype=torch.uint64) if want_keys else None
+        wsf = torch.empty(max(L.workspace_bytes(L.GSR_OP_BIN_FINISH, C, N, M), 1), device=d, dtype=torch.uint8)
+        L.gsr_bin_finish(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], M, ids, ranges, keys,
+                         wsp, wsf, stream=stream)
+        out = dict(M=M, ids=ids[:M], ids_buf=ids, ranges=ranges, total_tiles=total_tiles, key_bits=key_bits)
+        if want_keys:
+            out.update(keys=keys[:M], keys_buf=keys)
+        return out
     counts = torch.empty((C, N), device=d, dtype=torch.int32)
     offsets = torch.empty((C, N), device=d, dtype=torch.int64)
-    total = torch.empty(1, device=d, dtype=torch.int64)
     ws = torch.empty(max(L.workspace_bytes(L.GSR_OP_INTERSECT_COUNT, C, N, 0), 1), device=d, dtype=torch.uint8)
     M = L.gsr_intersect_count(p, C, N, W, H, proj["means2d"], proj["radii"], counts, offsets, total, ws,
                               sync=True, stream=stream)
@@ -71,18 +91,20 @@ def intersect(p, proj, W, H, stream=None):
     ids = torch.empty(max(M, 1), device=d, dtype=torch.int32)
     L.gsr_intersect_emit(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], offsets, M, keys, ids,
                          stream=stream)
-    key_bits = 32 + max(total_tiles - 1, 0).bit_length()
     if M > 1:
         keys_alt = torch.empty_like(keys)
         ids_alt = torch.empty_like(ids)
         sws = torch.empty(max(L.workspace_bytes(L.GSR_OP_SORT, 0, 0, M), 1), device=d, dtype=torch.uint8)
         L.gsr_sort_pairs(M, key_bits, keys, ids, keys_alt, ids_alt, sws, stream=stream)
-    ranges = torch.empty((max(total_tiles, 1), 2), device=d, dtype=torch.int32)
     L.gsr_tile_ranges(M, keys, total_tiles, ranges, stream=stream)
     # keys/ids are views of length M; the *_buf tensors (length max(M, 1)) are
     # what the library is handed, so a pointer is never NULL when M == 0
     return dict(counts=counts, offsets=offsets, M=M, keys=keys[:M], ids=ids[:M], ids_buf=ids, keys_buf=keys,
                 ranges=ranges, total_tiles=total_tiles, key_bits=key_bits)
+
+
+def raster_workspace(C, N, device):
+    return torch.empty(max(L.workspace_bytes(L.GSR_OP_RASTERIZE, C, N, 0), 1), device=device, dtype=torch.uint8)
 
 
 def rasterize_forward(p, proj, opacities, isect, W, H, background=None, n_eval=False, stream=None):
@@ -96,7 +118,7 @@ def rasterize_forward(p, proj, opacities, isect, W, H, background=None, n_eval=F
                n_eval=torch.empty((P, 2), device=d, dtype=torch.int32) if n_eval else None)
     L.gsr_rasterize_fwd(p, C, N, W, H, proj["means2d"], proj["conics"], proj["colors"], opacities,
                         proj["comps"], background, isect["ranges"], isect["ids_buf"], out["image"], out["alpha"],
-                        out["final_T"], out["last_ids"], out["n_eval"], stream=stream)
+                        out["final_T"], out["last_ids"], out["n_eval"], ws=raster_workspace(C, N, d), stream=stream)
     return out
 
 
@@ -111,7 +133,7 @@ def rasterize_backward(p, proj, opacities, isect, W, H, fwd, v_image, v_alpha=No
     L.gsr_rasterize_bwd(p, C, N, W, H, proj["means2d"], proj["conics"], proj["colors"], opacities, proj["comps"],
                         background, isect["ranges"], isect["ids_buf"], fwd["final_T"], fwd["last_ids"], v_image,
                         v_alpha, g["v_means2d"], g["v_conics"], g["v_colors"], g["v_opacities"],
-                        g["v_means2d_abs"], stream=stream)
+                        g["v_means2d_abs"], ws=raster_workspace(C, N, d), stream=stream)
     return g
 
 
@@ -144,7 +166,7 @@ class RasterizeGaussians(torch.autograd.Function):
         ctx.save_for_backward(means, quats, scales, opacities, sh_or_colors, viewmats, Ks, background)
         ctx.meta = meta
         meta.update(radii=proj["radii"], means2d=proj["means2d"], depths=proj["depths"], conics=proj["conics"],
-                    colors=proj["colors"], tiles_per_gauss=isect["counts"], n_intersections=isect["M"],
+                    colors=proj["colors"], n_intersections=isect["M"],
                     last_ids=fwd["last_ids"], final_T=fwd["final_T"])
         return fwd["image"], fwd["alpha"]
 

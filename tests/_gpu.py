@@ -27,13 +27,13 @@ def np_(t):
     return None if t is None else t.detach().cpu().numpy()
 
 
-def gpu_forward(p, sc, cams, background=None, n_eval=True):
+def gpu_forward(p, sc, cams, background=None, n_eval=True, method="bin", want_keys=False):
     d = scene_to_dev(sc)
     vm, Ks = to_dev(cams["viewmats"]), to_dev(cams["Ks"])
     W, H = [int(w) for w in cams["W"]], [int(h) for h in cams["H"]]
     bg = None if background is None else to_dev(np.asarray(background, np.float32))
     proj = R.project(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, W, H)
-    isect = R.intersect(p, proj, W, H)
+    isect = R.intersect(p, proj, W, H, method=method, want_keys=want_keys)
     fwd = R.rasterize_forward(p, proj, d["opacities"], isect, W, H, bg, n_eval=n_eval)
     torch.cuda.synchronize()
     return dict(d=d, vm=vm, Ks=Ks, W=W, H=H, bg=bg, proj=proj, isect=isect, fwd=fwd)

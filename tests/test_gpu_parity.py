@@ -45,7 +45,7 @@ def _run(name):
     from _gpu import gpu_forward, params
     p = params(sh_degree=deg, antialiased=aa)
     _say(f"{name}: N={sc['means'].shape[0]} cams={len(cams['W'])} sizes={list(zip(cams['W'], cams['H']))}")
-    st = gpu_forward(p, sc, cams, background=bg)
+    st = gpu_forward(p, sc, cams, background=bg, want_keys=True)
     proj, isect, ras = O32.forward(P, sc, cams, background=bg)
     return sc, cams, bg, P, p, st, proj, isect, ras
 
@@ -70,9 +70,22 @@ def test_projection_bit_exact(case):
 
 
 def test_binning_and_sort_bit_exact(case):
+    """The pipeline's binning (depth order, then 32-bit tile keys)."""
     from _gpu import np_
     name, sc, cams, bg, P, p, st, proj, isect, ras = case
     gi = st["isect"]
+    assert gi["M"] == isect["M"], name
+    np.testing.assert_array_equal(np_(gi["ids"]), isect["ids"])
+    np.testing.assert_array_equal(np_(gi["keys"]), isect["keys"])
+    np.testing.assert_array_equal(np_(gi["ranges"])[:len(isect["ranges"])], isect["ranges"])
+
+
+def test_count_emit_sort_ranges_bit_exact(case):
+    """The general path: counts, offsets, emitted keys, 64-bit radix sort, ranges."""
+    from _gpu import np_, scene_to_dev, to_dev
+    from paper_2409_06765_amd import rasterize as R
+    name, sc, cams, bg, P, p, st, proj, isect, ras = case
+    gi = R.intersect(p, st["proj"], st["W"], st["H"], method="keys64")
     assert gi["M"] == isect["M"], name
     np.testing.assert_array_equal(np_(gi["counts"]), isect["counts"])
     np.testing.assert_array_equal(np_(gi["offsets"]), isect["offsets"])
