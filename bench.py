@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-tiles", type=int, default=96, help="tiles of view 0 the oracle rasterizes")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 256 MiB device copy (the reference for traffic counters)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of the one-view capacity")
     args = ap.parse_args()
@@ -82,13 +84,14 @@ def main():
     Kss = torch.from_numpy(cams["Ks"]).to(dev)
     W, H = int(cams["W"][0]), int(cams["H"][0])
     npix = W * H
+    N = int(sc["means"].shape[0])
     v_image_np, _ = scenes.upstream_grads(args.workload, npix, seed=0)
     v_image = torch.from_numpy(v_image_np).to(dev)
     p = R.make_params(sh_degree=wl["sh_degree"])
 
     def step(v, timing=None, n_eval=False):
         vm, Ks = vms[v:v + 1], Kss[v:v + 1]
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)] if timing is not None else None
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)] if timing is not None else None
         if ev: ev[0].record()
         proj = R.project(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, [W], [H])
         if ev: ev[1].record()
@@ -96,12 +99,15 @@ def main():
         if ev: ev[2].record()
         fwd = R.rasterize_forward(p, proj, d["opacities"], isect, [W], [H], None, n_eval=n_eval)
         if ev: ev[3].record()
-        g2 = R.rasterize_backward(p, proj, d["opacities"], isect, [W], [H], fwd, v_image)
+        grads = R.grad_buffers(1, N, dev)
         if ev: ev[4].record()
+        # the compositing backward alone: records reused from the forward, buffers already zero
+        g2 = R.rasterize_backward(p, proj, d["opacities"], isect, [W], [H], fwd, v_image, grads=grads)
+        if ev: ev[5].record()
         g3 = R.project_backward(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, [W], [H],
                                 proj, g2)
         if ev:
-            ev[5].record()
+            ev[6].record()
             timing.append((ev, isect["M"]))
         return proj, isect, fwd, g2, g3
 
@@ -123,6 +129,12 @@ def main():
     for i in range(args.warmup):
         step(views[i % len(views)])
     torch.cuda.synchronize()
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, device=dev, dtype=torch.float32)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     timing = []
     torch.cuda.synchronize()
@@ -132,7 +144,7 @@ def main():
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_start
 
-    stage_names = ["project_fwd", "intersect", "rasterize_fwd", "rasterize_bwd", "project_bwd"]
+    stage_names = ["project_fwd", "intersect", "rasterize_fwd", "zero_grads", "rasterize_bwd", "project_bwd"]
     stage_ms = {k: 0.0 for k in stage_names}
     for ev, _ in timing:
         for i, k in enumerate(stage_names):

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 1
+#define GSR_ABI_VERSION 2
 #define GSR_MAX_CAMERAS 64
 
 enum gsr_status {
@@ -78,6 +78,12 @@ enum gsr_op {
     GSR_OP_RASTERIZE = 3,         /* workspace of gsr_rasterize_fwd / _bwd, C*N       */
     GSR_OP_BIN_PREPARE = 4,       /* workspace kept from gsr_bin_prepare to _finish   */
     GSR_OP_BIN_FINISH = 5         /* workspace of gsr_bin_finish for M intersections  */
+};
+
+/* Flags of gsr_rasterize_bwd. */
+enum gsr_bwd_flags {
+    GSR_BWD_ACCUMULATE = 1,
+    GSR_BWD_PACKED = 2
 };
 
 int gsr_abi_version(void);
@@ -207,14 +213,22 @@ int gsr_rasterize_fwd(const gsr_params *p, int C, int N, const int32_t *W, const
  * v_means2d_abs [C,N,2] (nullable: per-pixel absolute values of the mu'
  * gradient summed, the absgrad statistic).  Sums use float atomics, so their
  * rounding order is not fixed.
- * ws: workspace of gsr_workspace_bytes(GSR_OP_RASTERIZE, C, N, 0). */
+ * ws: workspace of gsr_workspace_bytes(GSR_OP_RASTERIZE, C, N, 0).
+ * flags (bitwise or; 0 = overwrite the outputs and pack the records anew):
+ *   GSR_BWD_ACCUMULATE  add into the outputs instead of overwriting them
+ *                       (the caller zeroes them, or sums several calls);
+ *   GSR_BWD_PACKED      ws still holds the per-Gaussian records that
+ *                       gsr_rasterize_fwd wrote into it for these same
+ *                       means2d, conics, colors, opacities, compensations and
+ *                       params (not rewritten since), so they are not packed
+ *                       again; with other contents the gradients are wrong. */
 int gsr_rasterize_bwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
                       const float *means2d, const float *conics, const float *colors,
                       const float *opacities, const float *compensations, const float *background,
                       const int32_t *ranges, const int32_t *ids, const float *final_T,
                       const int32_t *last_ids, const float *v_image, const float *v_alpha,
                       float *v_means2d, float *v_conics, float *v_colors, float *v_opacities,
-                      float *v_means2d_abs, void *ws, size_t ws_bytes, gsr_stream_t stream);
+                      float *v_means2d_abs, void *ws, size_t ws_bytes, int flags, gsr_stream_t stream);
 
 /* Projection Gradients, Scale and rotation gradients, SH backward.  Per
  * Gaussian, summed over the C cameras (no atomics: one thread per Gaussian):

@@ -108,6 +108,20 @@ class Oracle:
         self.lib = _load("f32" if self.dtype == np.float32 else "f64")
 
     # -- helpers ---------------------------------------------------------
+    def _abs_buf(self, out, C, N, want):
+        if not want:
+            return None
+        out["_abs"] = np.zeros((C, N, 9), self.dtype)
+        return out["_abs"]
+
+    @staticmethod
+    def _split_abs(out, C, N):
+        a = out.pop("_abs", None)
+        if a is not None:
+            out.update(abs_v_means2d=a[..., 0:2], abs_v_conics=a[..., 2:5], abs_v_colors=a[..., 5:8],
+                       abs_v_opacities=a[..., 8])
+        return out
+
     def _r(self, a):
         return None if a is None else np.ascontiguousarray(np.asarray(a, dtype=self.dtype))
 
@@ -215,7 +229,9 @@ class Oracle:
         return out
 
     def rasterize_bwd(self, P, proj, opacities, ranges, ids, W, H, final_T, last_ids, v_image,
-                      v_alpha=None, background=None, tile_mask=None):
+                      v_alpha=None, background=None, tile_mask=None, abs_sums=False):
+        """abs_sums: also return "abs_<name>", per gradient element the sum of
+        the absolute values of its terms (the scale of float32 summation error)."""
         _p = _Keep()
         C, N = proj["radii"].shape
         Wa = _ints(np.broadcast_to(np.asarray(W), (C,)))
@@ -231,8 +247,9 @@ class Oracle:
                                    _p(np.ascontiguousarray(ranges, np.int32)), _p(np.ascontiguousarray(ids, np.int32)),
                                    _p(tm), _p(self._r(final_T)), _p(np.ascontiguousarray(last_ids, np.int32)),
                                    _p(self._r(v_image)), _p(self._r(v_alpha)), _p(out["v_means2d"]),
-                                   _p(out["v_conics"]), _p(out["v_colors"]), _p(out["v_opacities"]))
-        return out
+                                   _p(out["v_conics"]), _p(out["v_colors"]), _p(out["v_opacities"]),
+                                   _p(self._abs_buf(out, C, N, abs_sums)))
+        return self._split_abs(out, C, N)
 
     # -- the plain definition, tile by tile ---------------------------------
     def render_tiles_fwd(self, P, proj, opacities, tiles, W, H, background=None, untiled=False):
@@ -258,7 +275,8 @@ class Oracle:
                                       _p(out["flags"]), _p(out["trace"]), _p(out["list_len"]))
         return out
 
-    def render_tiles_bwd(self, P, proj, opacities, tiles, W, H, v_image, v_alpha=None, background=None):
+    def render_tiles_bwd(self, P, proj, opacities, tiles, W, H, v_image, v_alpha=None, background=None,
+                         abs_sums=False):
         _p = _Keep()
         C, N = proj["radii"].shape
         Wa = _ints(np.broadcast_to(np.asarray(W), (C,)))
@@ -275,8 +293,20 @@ class Oracle:
                                       _p(self._r(proj["depths"])), _p(self._r(background)),
                                       tiles.shape[0], _p(tiles), _p(self._r(v_image)), _p(self._r(v_alpha)),
                                       _p(out["v_means2d"]), _p(out["v_conics"]), _p(out["v_colors"]),
-                                      _p(out["v_opacities"]))
-        return out
+                                      _p(out["v_opacities"]), _p(self._abs_buf(out, C, N, abs_sums)))
+        return self._split_abs(out, C, N)
+
+    def tile_list(self, P, proj, W, H, c, tx, ty):
+        """The definition's per-tile list (ids in depth-bits, id order)."""
+        _p = _Keep()
+        C, N = proj["radii"].shape
+        Wa = _ints(np.broadcast_to(np.asarray(W), (C,)))
+        Ha = _ints(np.broadcast_to(np.asarray(H), (C,)))
+        out = np.zeros(max(N, 1), np.int32)
+        n = self.lib.orc_tile_list(self._cp(P), C, N, _p(Wa), _p(Ha), _p(self._r(proj["means2d"])),
+                                   _p(np.ascontiguousarray(proj["radii"], np.int32)), _p(self._r(proj["depths"])),
+                                   int(c), int(tx), int(ty), _p(out))
+        return out[:n].copy()
 
     # -- pins support --------------------------------------------------------
     def cov3d(self, q, s):

@@ -490,6 +490,14 @@ static REAL gauss_opacity(const scene2d_t *S, int g)
     return o;
 }
 
+/* alpha = o exp(-sigma) with sigma known to within tol: an accurate
+ * evaluation lies within a factor exp(+-tol) of v, so a decision against thr
+ * is open when thr is inside that interval. */
+static int within_factor(double v, double thr, double tol)
+{
+    return v >= thr * exp(-tol) && v <= thr * exp(tol);
+}
+
 static void composite_pixel(const scene2d_t *S, const int32_t *list, int len, REAL px, REAL py,
                             const REAL *bg, pix_out_t *out)
 {
@@ -506,15 +514,15 @@ static void composite_pixel(const scene2d_t *S, const int32_t *list, int len, RE
         REAL a = S->conics[3 * g], b = S->conics[3 * g + 1], c = S->conics[3 * g + 2];
         REAL sigma = K(0.5) * ((a * dx) * dx + (c * dy) * dy) + (b * dx) * dy;
         double smag = 0.5 * (fabs((double)a * dx * dx) + fabs((double)c * dy * dy)) + fabs((double)b * dx * dy);
-        double tol_s = 64.0 * ulp * smag + 1e-30;
+        double tol_s = 16.0 * ulp * smag + 1e-30;
         if (fabs((double)sigma) <= tol_s) flags |= FLAG_AMBIG;
         if (sigma < K(0)) continue;
         REAL o = gauss_opacity(S, g);
         REAL araw = o * r_exp(-sigma);
         REAL alpha = r_min((REAL)P->alpha_max, araw);
         double tol_a = tol_s + 8.0 * ulp;   /* relative error budget of alpha */
-        if (fabs((double)araw - P->alpha_min) <= tol_a * P->alpha_min) flags |= FLAG_AMBIG;
-        if (fabs((double)araw - P->alpha_max) <= tol_a * P->alpha_max) flags |= FLAG_AMBIG;
+        if (within_factor(araw, P->alpha_min, tol_a)) flags |= FLAG_AMBIG;
+        if (within_factor(araw, P->alpha_max, tol_a)) flags |= FLAG_AMBIG;
         if (alpha < (REAL)P->alpha_min) continue;
         REAL Tn = T * (K(1) - alpha);
         double eTn = eT + (alpha < (REAL)P->alpha_max ? tol_a * alpha / (1.0 - alpha) : 0.0) + 2.0 * ulp;
@@ -536,7 +544,39 @@ static void composite_pixel(const scene2d_t *S, const int32_t *list, int len, RE
 
 /* Reverse recursion (Depth Compositing Gradients) for one pixel.  Gradient
  * sums go to double accumulators indexed by the Gaussian's [C,N] id. */
-typedef struct { double *v_means2d, *v_conics, *v_colors, *v_opac; } grad2d_t;
+/* abs (nullable): per id 9 sums of the magnitudes of the terms that make up
+ * each gradient element (mean x, y; conic a, b, c; colour r, g, b; opacity),
+ * each term's magnitude taken over its parts before they cancel (for the
+ * alpha gradient: sum over channels of |colour T_k| + |S / (1 - alpha)|
+ * times |v_C|, plus |v_alpha final_T / (1 - alpha)|): the scale of the
+ * rounding error any float32 evaluation and summation of the terms makes. */
+typedef struct { double *v_means2d, *v_conics, *v_colors, *v_opac, *abs; } grad2d_t;
+
+static void add_term(grad2d_t *G, double *dst, size_t g, int slot, double x, double mag)
+{
+    *dst += x;
+    if (G->abs) G->abs[9 * g + (size_t)slot] += mag;
+}
+
+static void grad2d_alloc(grad2d_t *G, size_t CN, int want_abs)
+{
+    G->v_means2d = (double *)calloc(2 * CN + 1, sizeof(double));
+    G->v_conics = (double *)calloc(3 * CN + 1, sizeof(double));
+    G->v_colors = (double *)calloc(3 * CN + 1, sizeof(double));
+    G->v_opac = (double *)calloc(CN + 1, sizeof(double));
+    G->abs = want_abs ? (double *)calloc(9 * CN + 1, sizeof(double)) : NULL;
+}
+
+static void grad2d_store(grad2d_t *G, size_t CN, REAL *v_means2d, REAL *v_conics, REAL *v_colors,
+                         REAL *v_opacities, REAL *abs_sums)
+{
+    for (size_t i = 0; i < 2 * CN; i++) v_means2d[i] = (REAL)G->v_means2d[i];
+    for (size_t i = 0; i < 3 * CN; i++) { v_conics[i] = (REAL)G->v_conics[i]; v_colors[i] = (REAL)G->v_colors[i]; }
+    for (size_t i = 0; i < CN; i++) v_opacities[i] = (REAL)G->v_opac[i];
+    if (abs_sums && G->abs)
+        for (size_t i = 0; i < 9 * CN; i++) abs_sums[i] = (REAL)G->abs[i];
+    free(G->v_means2d); free(G->v_conics); free(G->v_colors); free(G->v_opac); free(G->abs);
+}
 
 static void composite_pixel_bwd(const scene2d_t *S, const int32_t *list, int last, REAL px, REAL py,
                                 const REAL *bg, REAL T_final, const REAL *vC, REAL vA, grad2d_t *G)
@@ -560,24 +600,34 @@ static void composite_pixel_bwd(const scene2d_t *S, const int32_t *list, int las
         REAL Tk = T / one_m;                 /* transmittance in front of entry k */
         const REAL *col = S->colors + 3 * (size_t)g;
         REAL v_alpha = K(0);
+        double m_alpha = 0.0;                /* magnitude of v_alpha's parts */
         for (int ch = 0; ch < 3; ch++) {
-            G->v_colors[3 * (size_t)g + ch] += (double)(alpha * Tk * vC[ch]);
+            double t = (double)(alpha * Tk * vC[ch]);
+            add_term(G, &G->v_colors[3 * (size_t)g + ch], (size_t)g, 5 + ch, t, fabs(t));
             v_alpha += (col[ch] * Tk - Sacc[ch] / one_m) * vC[ch];
+            m_alpha += (fabs((double)(col[ch] * Tk)) + fabs((double)(Sacc[ch] / one_m))) * fabs((double)vC[ch]);
         }
         v_alpha += vA * (T_final / one_m);
+        m_alpha += fabs((double)(vA * (T_final / one_m)));
         for (int ch = 0; ch < 3; ch++) Sacc[ch] += col[ch] * alpha * Tk;
         T = Tk;
         if (araw > (REAL)P->alpha_max) continue;    /* clamped: no gradient to o or sigma */
         /* d alpha / d o = exp(-sigma), o being the opacity the rasterizer
          * used (times the anti-aliasing compensation when that is on) */
-        G->v_opac[g] += (double)(e * v_alpha);
+        add_term(G, &G->v_opac[g], (size_t)g, 8, (double)(e * v_alpha), (double)e * m_alpha);
         REAL v_sigma = -araw * v_alpha;
+        double m_sigma = (double)araw * m_alpha;
         /* d sigma / d mu' = Y Delta with Delta = mu' - p; d sigma / d(a,b,c) */
-        G->v_means2d[2 * (size_t)g] += (double)(v_sigma * (a * dx + b * dy));
-        G->v_means2d[2 * (size_t)g + 1] += (double)(v_sigma * (b * dx + c * dy));
-        G->v_conics[3 * (size_t)g] += (double)(v_sigma * (K(0.5) * dx * dx));
-        G->v_conics[3 * (size_t)g + 1] += (double)(v_sigma * (dx * dy));
-        G->v_conics[3 * (size_t)g + 2] += (double)(v_sigma * (K(0.5) * dy * dy));
+        add_term(G, &G->v_means2d[2 * (size_t)g], (size_t)g, 0, (double)(v_sigma * (a * dx + b * dy)),
+                 m_sigma * (fabs((double)(a * dx)) + fabs((double)(b * dy))));
+        add_term(G, &G->v_means2d[2 * (size_t)g + 1], (size_t)g, 1, (double)(v_sigma * (b * dx + c * dy)),
+                 m_sigma * (fabs((double)(b * dx)) + fabs((double)(c * dy))));
+        add_term(G, &G->v_conics[3 * (size_t)g], (size_t)g, 2, (double)(v_sigma * (K(0.5) * dx * dx)),
+                 m_sigma * 0.5 * (double)(dx * dx));
+        add_term(G, &G->v_conics[3 * (size_t)g + 1], (size_t)g, 3, (double)(v_sigma * (dx * dy)),
+                 m_sigma * fabs((double)(dx * dy)));
+        add_term(G, &G->v_conics[3 * (size_t)g + 2], (size_t)g, 4, (double)(v_sigma * (K(0.5) * dy * dy)),
+                 m_sigma * 0.5 * (double)(dy * dy));
     }
 }
 
@@ -639,17 +689,14 @@ int orc_rasterize_bwd(const orc_params *P, int C, int N, const int *W, const int
                       const REAL *comps, const REAL *background, const int32_t *ranges, const int32_t *ids,
                       const uint8_t *tile_mask, const REAL *final_T, const int32_t *last_ids,
                       const REAL *v_image, const REAL *v_alpha,
-                      REAL *v_means2d, REAL *v_conics, REAL *v_colors, REAL *v_opacities)
+                      REAL *v_means2d, REAL *v_conics, REAL *v_colors, REAL *v_opacities, REAL *abs_sums)
 {
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     camera_offsets(P, C, W, H, pix_off, tile_off);
     size_t CN = (size_t)C * N;
     grad2d_t G;
-    G.v_means2d = (double *)calloc(2 * CN + 1, sizeof(double));
-    G.v_conics = (double *)calloc(3 * CN + 1, sizeof(double));
-    G.v_colors = (double *)calloc(3 * CN + 1, sizeof(double));
-    G.v_opac = (double *)calloc(CN + 1, sizeof(double));
+    grad2d_alloc(&G, CN, abs_sums != NULL);
     scene2d_t S = {P, N, means2d, conics, colors, opacities, comps};
     int ts = P->tile;
     for (int c = 0; c < C; c++) {
@@ -669,10 +716,7 @@ int orc_rasterize_bwd(const orc_params *P, int C, int N, const int *W, const int
                     }
             }
     }
-    for (size_t i = 0; i < 2 * CN; i++) v_means2d[i] = (REAL)G.v_means2d[i];
-    for (size_t i = 0; i < 3 * CN; i++) { v_conics[i] = (REAL)G.v_conics[i]; v_colors[i] = (REAL)G.v_colors[i]; }
-    for (size_t i = 0; i < CN; i++) v_opacities[i] = (REAL)G.v_opac[i];
-    free(G.v_means2d); free(G.v_conics); free(G.v_colors); free(G.v_opac);
+    grad2d_store(&G, CN, v_means2d, v_conics, v_colors, v_opacities, abs_sums);
     free(pix_off); free(tile_off);
     return 0;
 }
@@ -708,6 +752,19 @@ static int build_tile_list(const orc_params *P, int N, int c, int W, int H, int 
     }
     qsort(tmp, (size_t)len, sizeof(did_t), did_cmp);
     for (int i = 0; i < len; i++) list[i] = tmp[i].id;
+    return len;
+}
+
+/* The definition's list of one tile: ids c*N+n of the projected Gaussians
+ * whose rectangle holds tile (tx, ty) of camera c, in (depth bits, id) order.
+ * Returns its length; list must hold N entries. */
+int orc_tile_list(const orc_params *P, int C, int N, const int *W, const int *H, const REAL *means2d,
+                  const int32_t *radii, const REAL *depths, int c, int tx, int ty, int32_t *list)
+{
+    (void)C;
+    did_t *tmp = (did_t *)malloc(sizeof(did_t) * (N > 0 ? N : 1));
+    int len = build_tile_list(P, N, c, W[c], H[c], tx, ty, means2d, radii, depths, 0, list, tmp);
+    free(tmp);
     return len;
 }
 
@@ -760,7 +817,7 @@ int orc_render_tiles_bwd(const orc_params *P, int C, int N, const int *W, const 
                          const REAL *means2d, const REAL *conics, const REAL *colors, const REAL *opacities,
                          const REAL *comps, const int32_t *radii, const REAL *depths, const REAL *background,
                          int ntiles, const int32_t *tiles, const REAL *v_image, const REAL *v_alpha,
-                         REAL *v_means2d, REAL *v_conics, REAL *v_colors, REAL *v_opacities)
+                         REAL *v_means2d, REAL *v_conics, REAL *v_colors, REAL *v_opacities, REAL *abs_sums)
 {
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
@@ -769,10 +826,7 @@ int orc_render_tiles_bwd(const orc_params *P, int C, int N, const int *W, const 
     did_t *tmp = (did_t *)malloc(sizeof(did_t) * (N > 0 ? N : 1));
     size_t CN = (size_t)C * N;
     grad2d_t G;
-    G.v_means2d = (double *)calloc(2 * CN + 1, sizeof(double));
-    G.v_conics = (double *)calloc(3 * CN + 1, sizeof(double));
-    G.v_colors = (double *)calloc(3 * CN + 1, sizeof(double));
-    G.v_opac = (double *)calloc(CN + 1, sizeof(double));
+    grad2d_alloc(&G, CN, abs_sums != NULL);
     scene2d_t S = {P, N, means2d, conics, colors, opacities, comps};
     int ts = P->tile;
     for (int i = 0; i < ntiles; i++) {
@@ -790,10 +844,7 @@ int orc_render_tiles_bwd(const orc_params *P, int C, int N, const int *W, const 
                                     v_alpha ? v_alpha[p] : K(0), &G);
             }
     }
-    for (size_t i = 0; i < 2 * CN; i++) v_means2d[i] = (REAL)G.v_means2d[i];
-    for (size_t i = 0; i < 3 * CN; i++) { v_conics[i] = (REAL)G.v_conics[i]; v_colors[i] = (REAL)G.v_colors[i]; }
-    for (size_t i = 0; i < CN; i++) v_opacities[i] = (REAL)G.v_opac[i];
-    free(G.v_means2d); free(G.v_conics); free(G.v_colors); free(G.v_opac);
+    grad2d_store(&G, CN, v_means2d, v_conics, v_colors, v_opacities, abs_sums);
     free(list); free(tmp); free(pix_off); free(tile_off);
     return 0;
 }

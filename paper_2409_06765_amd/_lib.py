@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_PKG, "libgsraster.so")
 GSR_OK, GSR_EINVAL, GSR_EOVERFLOW, GSR_EWORKSPACE, GSR_EHIP = 0, 1, 2, 3, 4
 GSR_OP_INTERSECT_COUNT, GSR_OP_SORT, GSR_OP_RASTERIZE, GSR_OP_BIN_PREPARE, GSR_OP_BIN_FINISH = 1, 2, 3, 4, 5
 GSR_MAX_CAMERAS = 64
+GSR_BWD_ACCUMULATE, GSR_BWD_PACKED = 1, 2
+ABI_VERSION = 2                 # the signatures below
 _NAMES = {0: "GSR_OK", 1: "GSR_EINVAL", 2: "GSR_EOVERFLOW", 3: "GSR_EWORKSPACE", 4: "GSR_EHIP"}
 
 
@@ -48,7 +50,7 @@ _SIGS = {
     "gsr_bin_prepare": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
     "gsr_bin_finish": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp, _sz, _vp], _i),
     "gsr_rasterize_fwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 8 + [_vp] * 5 + [_vp, _sz, _vp], _i),
-    "gsr_rasterize_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 12 + [_vp] * 5 + [_vp, _sz, _vp], _i),
+    "gsr_rasterize_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 12 + [_vp] * 5 + [_vp, _sz, _i, _vp], _i),
     "gsr_project_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 9 + [_vp] * 5 + [_vp] * 5 + [_vp], _i),
 }
 
@@ -66,6 +68,9 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = res
+        if L.gsr_abi_version() != ABI_VERSION:
+            raise GsrError(GSR_EHIP, f"{LIB_PATH} has ABI version {L.gsr_abi_version()}, the binding expects "
+                                     f"{ABI_VERSION}: rebuild it")
         _lib = L
     return _lib
 
@@ -194,7 +199,7 @@ def gsr_rasterize_fwd(p, C, N, W, H, means2d, conics, colors, opacities, compens
 
 def gsr_rasterize_bwd(p, C, N, W, H, means2d, conics, colors, opacities, compensations, background, ranges, ids,
                       final_T, last_ids, v_image, v_alpha, v_means2d, v_conics, v_colors, v_opacities,
-                      v_means2d_abs=None, ws=None, stream=None):
+                      v_means2d_abs=None, ws=None, flags=0, stream=None):
     _check(lib().gsr_rasterize_bwd(
         ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(conics, F32, "conics"),
         _ptr(colors, F32, "colors"), _ptr(opacities, F32, "opacities"), _ptr(compensations, F32, "compensations"),
@@ -202,7 +207,7 @@ def gsr_rasterize_bwd(p, C, N, W, H, means2d, conics, colors, opacities, compens
         _ptr(final_T, F32, "final_T"), _ptr(last_ids, I32, "last_ids"), _ptr(v_image, F32, "v_image"),
         _ptr(v_alpha, F32, "v_alpha"), _ptr(v_means2d, F32, "v_means2d"), _ptr(v_conics, F32, "v_conics"),
         _ptr(v_colors, F32, "v_colors"), _ptr(v_opacities, F32, "v_opacities"),
-        _ptr(v_means2d_abs, F32, "v_means2d_abs"), *_ws(ws), _stream(stream)))
+        _ptr(v_means2d_abs, F32, "v_means2d_abs"), *_ws(ws), int(flags), _stream(stream)))
 
 
 def gsr_project_bwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, radii,

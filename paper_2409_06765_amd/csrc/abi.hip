@@ -276,8 +276,9 @@ int gsr_rasterize_bwd(const gsr_params *p, int C, int N, const int32_t *W, const
                       const int32_t *ranges, const int32_t *ids, const float *final_T,
                       const int32_t *last_ids, const float *v_image, const float *v_alpha,
                       float *v_means2d, float *v_conics, float *v_colors, float *v_opacities,
-                      float *v_means2d_abs, void *ws, size_t ws_bytes, gsr_stream_t stream) {
+                      float *v_means2d_abs, void *ws, size_t ws_bytes, int flags, gsr_stream_t stream) {
     static const char *fn = "gsr_rasterize_bwd";
+    if (flags & ~(GSR_BWD_ACCUMULATE | GSR_BWD_PACKED)) return fail(GSR_EINVAL, "%s: unknown flags 0x%x", fn, flags);
     int rc = check_params(p);
     CamTable cams;
     if (rc == GSR_OK) rc = make_cams(C, N, W, H, cams);
@@ -292,7 +293,7 @@ int gsr_rasterize_bwd(const gsr_params *p, int C, int N, const int32_t *W, const
         return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws ? ws_bytes : 0);
     return launch_rasterize_bwd(*p, cams, N, means2d, conics, colors, opacities, compensations, background, ranges,
                                 ids, final_T, last_ids, v_image, v_alpha, v_means2d, v_conics, v_colors,
-                                v_opacities, v_means2d_abs, ws, (hipStream_t)stream);
+                                v_opacities, v_means2d_abs, ws, flags, (hipStream_t)stream);
 }
 
 int gsr_project_bwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,

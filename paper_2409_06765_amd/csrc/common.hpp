@@ -78,7 +78,7 @@ int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, const
                          const float *comps, const float *background, const int32_t *ranges,
                          const int32_t *ids, const float *final_T, const int32_t *last_ids,
                          const float *v_image, const float *v_alpha, float *v_means2d, float *v_conics,
-                         float *v_colors, float *v_opac, float *v_means2d_abs, void *ws, hipStream_t s);
+                         float *v_colors, float *v_opac, float *v_means2d_abs, void *ws, int flags, hipStream_t s);
 
 int launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
 
@@ -147,7 +147,15 @@ __device__ __forceinline__ uint32_t quad_mask(float mx, float my, float hx, floa
 
 // Per projected Gaussian record read by the compositing kernels:
 // {mean x, mean y, opacity (times compensation), support half-width x},
-// {conic a, b, c, support half-width y}, {colour r, g, b, 0}.
+// {a/2, b, c/2 scaled by log2(e), support half-width y}, {colour r, g, b, 0},
+// with (a, b, c) the conic.  The scaling gives log2(e) sigma directly
+// (scaled_sigma), the argument of the hardware base-2 exponential.
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ __forceinline__ float scaled_sigma(float4 con, float dx, float dy) {
+    return fmaf(dx, fmaf(con.x, dx, con.y * dy), con.z * dy * dy);
+}
+
 struct PackedGauss {
     float4 xyoh;
     float4 conh;
@@ -157,5 +165,32 @@ struct PackedGauss {
 size_t pack_workspace_bytes(int64_t cn);
 int launch_pack(const gsr_params &p, int CN, int N, const float *means2d, const float *conics, const float *colors,
                 const float *opacities, const float *comps, PackedGauss *out, hipStream_t s);
+
+// Per-quad lists of a staged batch.  Thread t holds batch entry t with quad
+// mask m (0 when the entry is past the list end); afterwards list[q][0 ..
+// count[q]) holds, in increasing order, the entries whose mask has bit q.
+// Must be called by all kThreadsPerTile threads; ends with a barrier.
+constexpr int kThreadsPerTile = 256;
+__device__ __forceinline__ void compact_quads(uint32_t m, uint8_t (*list)[kThreadsPerTile], int32_t (*wcnt)[4],
+                                              int32_t *count) {
+    const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    int32_t pre[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint64_t bal = __ballot((m >> q) & 1u);
+        pre[q] = (int32_t)__popcll(bal & lt);
+        if (lane == 0) wcnt[q][w] = (int32_t)__popcll(bal);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        int32_t base = 0;
+        for (int v = 0; v < w; v++) base += wcnt[q][v];
+        if ((m >> q) & 1u) list[q][base + pre[q]] = (uint8_t)t;
+    }
+    if (t < 4) count[t] = wcnt[t][0] + wcnt[t][1] + wcnt[t][2] + wcnt[t][3];
+    __syncthreads();
+}
 
 }  // namespace gsr

@@ -138,13 +138,19 @@ __global__ void __launch_bounds__(kScanThreads) offsets_kernel(int64_t n_total, 
 }
 
 // ---- key emission ------------------------------------------------------------
-// One wave per 64 consecutive entries of the emission sequence (projected
-// Gaussians in id order, or in depth order when `order` is given): the wave's
-// output range is contiguous, so lanes stride over it and each finds the
-// entry owning its slot by binary search; writes are fully coalesced and a
-// Gaussian covering thousands of tiles is spread over the whole wave.  Keys
-// are tile << 32 | depth bits (uint64) or the tile id alone (uint32).
+// The output is cut into fixed slices of kEmitChunk entries, one slice per
+// wave, so the work per wave is bounded whatever the tile counts are (a few
+// Gaussians covering thousands of tiles, clustered in depth order, would
+// otherwise keep single waves busy long after the rest finished).  A wave
+// finds the entry owning its first slot with a 64-way search over the
+// exclusive offsets, then walks windows of 64 consecutive entries of the
+// emission sequence (projected Gaussians in id order, or in depth order when
+// `order` is given): each lane stages one entry's rectangle in LDS and, for
+// each slot it writes, finds the owning entry by binary search over the
+// window's offsets.  Writes are coalesced.  Keys are tile << 32 | depth bits
+// (uint64) or the tile id alone (uint32).
 constexpr int kEmitThreads = 256;
+constexpr int kEmitChunk = 512;
 
 template <typename K>
 __device__ __forceinline__ K make_key(uint32_t tile, uint32_t dbits);
@@ -155,75 +161,101 @@ __device__ __forceinline__ uint64_t make_key<uint64_t>(uint32_t tile, uint32_t d
 template <>
 __device__ __forceinline__ uint32_t make_key<uint32_t>(uint32_t tile, uint32_t) { return tile; }
 
+// Largest s in [0, n) with offsets[s] <= pos (offsets non-decreasing, offsets[0] = 0 <= pos);
+// wave-cooperative: every lane returns the same value.
+__device__ __forceinline__ int64_t owner_search(const int64_t *__restrict__ offsets, int64_t n, int64_t pos) {
+    const int lane = __lane_id();
+    int64_t lo = 0, hi = n;                    // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const int64_t step = (hi - lo + kWave - 1) / kWave;
+        const int64_t q = lo + (int64_t)lane * step;
+        const bool le = q < hi && offsets[q] <= pos;
+        const uint64_t m = __ballot(le);       // lane 0 is always set: offsets[lo] <= pos
+        const int L = 63 - __builtin_clzll(m);
+        lo = lo + (int64_t)L * step;
+        hi = min(lo + step, hi);
+    }
+    return lo;
+}
+
 template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N, int64_t n_total,
         const float *__restrict__ means2d, const int32_t *__restrict__ radii, const float *__restrict__ depths,
         const int32_t *__restrict__ order, const int64_t *__restrict__ offsets, int64_t cap, K *__restrict__ keys,
         int32_t *__restrict__ ids) {
-    __shared__ int32_t s_rel[kEmitThreads];   // slot of the lane's first entry, relative to the wave
-    __shared__ int32_t s_w[kEmitThreads];     // rectangle width in tiles
-    __shared__ int32_t s_row[kEmitThreads];   // tile_base + y0 * TX + x0 of the lane's camera
-    __shared__ int32_t s_TX[kEmitThreads];
-    __shared__ uint32_t s_dbits[kEmitThreads];
-    __shared__ int32_t s_g[kEmitThreads];
+    constexpr int kWaves = kEmitThreads / kWave;
+    __shared__ int64_t s_start[kWaves][kWave];   // first slot of each entry of the window
+    __shared__ int32_t s_w[kWaves][kWave];       // rectangle width in tiles
+    __shared__ int32_t s_row[kWaves][kWave];     // tile_base + y0 * TX + x0 of the entry's camera
+    __shared__ int32_t s_TX[kWaves][kWave];
+    __shared__ uint32_t s_dbits[kWaves][kWave];
+    __shared__ int32_t s_g[kWaves][kWave];
     const int lane = __lane_id(), w = threadIdx.x / kWave;
-    const int64_t s = (int64_t)blockIdx.x * kEmitThreads + threadIdx.x;
-    const int64_t s0 = (int64_t)blockIdx.x * kEmitThreads + (int64_t)w * kWave;
-    if (s0 >= n_total) return;                // whole wave past the end (wave-uniform)
-    int cnt = 0, x0 = 0, x1 = 0, y0 = 0, y1 = 0, TX = 0, row = 0;
-    int64_t off = 0, g = 0;
-    uint32_t dbits = 0;
-    if (s < n_total) {
-        g = order ? order[s] : s;
-        if (g < 0 || g >= n_total) g = 0;     // order comes from the depth sort; this only bounds a bad input
-        off = offsets[s];
-        const int r = radii[g];
-        if (r > 0) {
-            const int c = (int)(g / N);
-            TX = cams.cam[c].TX;
-            tile_rect(means2d[2 * g], means2d[2 * g + 1], r, TX, cams.cam[c].TY, x0, x1, y0, y1);
-            if (x1 > x0 && y1 > y0) cnt = (x1 - x0) * (y1 - y0);
-            row = cams.cam[c].tile_base + y0 * TX + x0;
-            dbits = __float_as_uint(depths[g]);
+    const int64_t c0 = ((int64_t)blockIdx.x * kWaves + w) * kEmitChunk;
+    if (c0 >= cap) return;                       // wave-uniform
+    const int64_t c1 = min(c0 + (int64_t)kEmitChunk, cap);
+    for (int64_t s = owner_search(offsets, n_total, c0); s < n_total; s += kWave) {
+        const int64_t q = s + lane;
+        int cnt = 0, x0 = 0, x1 = 0, y0 = 0, y1 = 0, TX = 0, row = 0;
+        int64_t start = INT64_MAX, g = 0;
+        uint32_t dbits = 0;
+        if (q < n_total) {
+            g = order ? order[q] : q;
+            if (g < 0 || g >= n_total) g = 0;    // order comes from the depth sort; this only bounds a bad input
+            start = offsets[q];
+            const int r = radii[g];
+            if (r > 0) {
+                const int c = (int)(g / N);
+                TX = cams.cam[c].TX;
+                tile_rect(means2d[2 * g], means2d[2 * g + 1], r, TX, cams.cam[c].TY, x0, x1, y0, y1);
+                if (x1 > x0 && y1 > y0) cnt = (x1 - x0) * (y1 - y0);
+                row = cams.cam[c].tile_base + y0 * TX + x0;
+                dbits = __float_as_uint(depths[g]);
+            }
         }
-    }
-    const int64_t wbase = __shfl(off, 0, kWave);
-    int64_t end = off + cnt;
+        // the window covers slots [start of lane 0, largest end)
+        int64_t wend = q < n_total ? start + cnt : INT64_MIN;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const int64_t o2 = __shfl_xor(end, d, kWave);
-        end = o2 > end ? o2 : end;
-    }
-    const int total = (int)(end - wbase);
-    s_rel[threadIdx.x] = (s < n_total) ? (int)(off - wbase) : 0x7fffffff;
-    s_w[threadIdx.x] = x1 - x0;
-    s_row[threadIdx.x] = row;
-    s_TX[threadIdx.x] = TX;
-    s_dbits[threadIdx.x] = dbits;
-    s_g[threadIdx.x] = (int32_t)g;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int wb = w * kWave;
-    for (int j = lane; j < total; j += kWave) {
-        // largest L with s_rel[L] <= j (always a lane with a non-empty rectangle)
-        int lo = 0, hi = kWave - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_rel[wb + mid] <= j) lo = mid; else hi = mid - 1;
+        for (int d = 32; d >= 1; d >>= 1) {
+            const int64_t o2 = __shfl_xor(wend, d, kWave);
+            wend = o2 > wend ? o2 : wend;
         }
-        const int k = wb + lo;
-        const int local = j - s_rel[k];
-        const int wdt = max(s_w[k], 1);
-        const int dy = local / wdt;
-        const int dx = local - dy * wdt;
-        const uint32_t tile = (uint32_t)(s_row[k] + dy * s_TX[k] + dx);
-        const int64_t pos = wbase + j;
-        if (pos < cap) {
-            keys[pos] = make_key<K>(tile, s_dbits[k]);
-            ids[pos] = s_g[k];
+        const int64_t wbeg = __shfl(start, 0, kWave);
+        s_start[w][lane] = start;
+        s_w[w][lane] = x1 - x0;
+        s_row[w][lane] = row;
+        s_TX[w][lane] = TX;
+        s_dbits[w][lane] = dbits;
+        s_g[w][lane] = (int32_t)g;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int64_t p0 = max(c0, wbeg), p1 = min(c1, wend);
+        for (int64_t pos = p0 + lane; pos < p1; pos += kWave) {
+            // largest L with s_start[L] <= pos: the entry owning the slot (zero-count entries
+            // share their successor's start and lose to it)
+            int lo = 0, hi = kWave - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_start[w][mid] <= pos) lo = mid; else hi = mid - 1;
+            }
+            const int local = (int)(pos - s_start[w][lo]);
+            const int wdt = max(s_w[w][lo], 1);
+            const int dy = local / wdt;
+            const int dx = local - dy * wdt;
+            keys[pos] = make_key<K>((uint32_t)(s_row[w][lo] + dy * s_TX[w][lo] + dx), s_dbits[w][lo]);
+            ids[pos] = s_g[w][lo];
         }
+        if (wend >= c1) break;
+        __builtin_amdgcn_wave_barrier();         // the window's LDS is rewritten next
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+}
+
+int64_t emit_blocks(int64_t cap) {
+    const int64_t per_block = (int64_t)kEmitChunk * (kEmitThreads / kWave);
+    return (cap + per_block - 1) / per_block;
 }
 
 __global__ void fill_zero_kernel(uint32_t *__restrict__ p, int64_t n_words) {
@@ -551,7 +583,7 @@ int launch_intersect_emit(const gsr_params &p, const CamTable &cams, int N, cons
     (void)p;
     const int64_t n = (int64_t)cams.C * N;
     if (n == 0 || cap == 0) return GSR_OK;
-    const int64_t nb = (n + kEmitThreads - 1) / kEmitThreads;
+    const int64_t nb = emit_blocks(cap);
     emit_kernel<uint64_t><<<dim3((unsigned)nb), dim3(kEmitThreads), 0, s>>>(cams, N, n, means2d, radii, depths,
                                                                            nullptr, offsets, cap, keys, ids);
     return launch_check("intersect_emit");
@@ -610,7 +642,7 @@ int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const fl
     BinFin f = carve_fin(ws_fin, M);
     int rc = launch_fill_zero(ranges, (size_t)cams.total_tiles * 2 * sizeof(int32_t), s);
     if (rc != GSR_OK || n == 0 || M == 0) return rc;
-    const int64_t ne = (n + kEmitThreads - 1) / kEmitThreads;
+    const int64_t ne = emit_blocks(M);
     emit_kernel<uint32_t><<<dim3((unsigned)ne), dim3(kEmitThreads), 0, s>>>(cams, N, n, means2d, radii, depths,
                                                                            b.order, b.offsets_sorted, M, f.tkeys, ids);
     const int tile_bits = cams.total_tiles > 1 ? 32 - __builtin_clz((unsigned)(cams.total_tiles - 1)) : 1;

@@ -1,8 +1,8 @@
 // Backward pass of the compositing (Depth Compositing Gradients).
 //
 // Same tiling as the forward: a 256-thread block per 16x16 tile, an 8x8
-// quad per wave, LDS-staged batches walked back to front, with the same
-// quad culling.  Each pixel restores T from final_T by T_k = T_{k+1} /
+// quad per wave, LDS-staged batches walked back to front over the same
+// per-quad lists.  Each pixel restores T from final_T by T_k = T_{k+1} /
 // (1 - alpha_k) and carries S, the colour accumulated behind the current
 // entry plus final_T times the background.  A wave starts at the largest
 // last_ids among its own pixels.
@@ -61,22 +61,42 @@ __device__ __forceinline__ float bfly(float a, float b, bool hi) {
     return keep + dpp<CTRL>(send);
 }
 
+// v plus the value of lane i ^ 16 (i ^ 32): v_permlane16_swap exchanges the
+// odd 16-lane rows of one register with the even rows of the other,
+// v_permlane32_swap the upper half of one with the lower half of the other;
+// given v twice, each lane ends with its own value in one register and its
+// partner's in the other, so their sum is the pair total, with no LDS trip.
+// Written as inline assembly because the compiler's builtin returns the
+// first register for both results; the leading s_nop gives the two wait
+// states a VALU write needs before these instructions read it.
+__device__ __forceinline__ float add_xor16(float v) {
+    float a = v, b = v;
+    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+    return a + b;
+}
+__device__ __forceinline__ float add_xor32(float v) {
+    float a = v, b = v;
+    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+    return a + b;
+}
+
 // Sum over all 64 lanes, result in every lane.
 __device__ __forceinline__ float wave_total(float v) {
     v += dpp<kDppXor1>(v);
     v += dpp<kDppXor2>(v);
     v += dpp<kDppRor4>(v);
     v += dpp<kDppRor8>(v);
-    v += __shfl_xor(v, 16, kWave);
-    v += __shfl_xor(v, 32, kWave);
-    return v;
+    return add_xor32(add_xor16(v));
 }
 
 __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, CamTable cams) {
-    __shared__ float4 s_xyo[kBatch];   // mean x, mean y, opacity, quad mask bits
+    __shared__ float4 s_xyo[kBatch];   // mean x, mean y, opacity, -
     __shared__ float4 s_con[kBatch];   // conic a, b, c, -
     __shared__ float4 s_col[kBatch];   // colour r, g, b, -
     __shared__ int32_t s_id[kBatch];
+    __shared__ uint8_t s_qlist[4][kBatch];
+    __shared__ int32_t s_wcnt[4][4];
+    __shared__ int32_t s_qcnt[4];
     __shared__ int32_t s_wmax[kThreads / kWave];
 
     const int tile = blockIdx.x;
@@ -91,7 +111,7 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
     const float px = (float)xi + 0.5f, py = (float)yi + 0.5f;
     const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
     const int start = a.ranges[2 * tile];
-    const float amin = a.p.alpha_min, amax = a.p.alpha_max;
+    const float amin = a.p.alpha_min, amax = __builtin_canonicalizef(a.p.alpha_max);
 
     int last = -1;
     float T = 1.0f, Tf = 1.0f, vC0 = 0.0f, vC1 = 0.0f, vC2 = 0.0f, vA = 0.0f;
@@ -119,39 +139,48 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
     const bool want_abs = a.v_means2d_abs != nullptr;
     const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
 
-    // destination of the value this lane holds after the reduction
-    const int slot = lane < 11 ? lane : -1;
+    // After the reduction lane i < 8 holds the total of value i; lane 8 the
+    // opacity gradient, lanes 9, 10 the absolute mean gradient.  Each of these
+    // lanes adds its total at dst_base + g * dst_mul.
+    const int nslots = want_abs ? 11 : 9;
+    float *dst_base = nullptr;
+    int dst_mul = 0;
+    if (lane < 2) { dst_base = a.v_means2d + lane; dst_mul = 2; }
+    else if (lane < 5) { dst_base = a.v_conics + (lane - 2); dst_mul = 3; }
+    else if (lane < 8) { dst_base = a.v_colors + (lane - 5); dst_mul = 3; }
+    else if (lane == 8) { dst_base = a.v_opac; dst_mul = 1; }
+    else if (lane < 11 && want_abs) { dst_base = a.v_means2d_abs + (lane - 9); dst_mul = 2; }
 
     for (int hi = stop + 1; hi > start; hi -= kBatch) {
         const int base = max(start, hi - kBatch);
         __syncthreads();
         const int k = base + (int)threadIdx.x;
+        uint32_t qm = 0u;
         if (k < hi) {
             int g = a.ids[k];
             if ((unsigned)g >= (unsigned)a.CN) g = 0;   // ids come from the sort; this only bounds a bad input
             const PackedGauss r = a.gauss[g];
-            const uint32_t qm = quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0);
-            s_xyo[threadIdx.x] = make_float4(r.xyoh.x, r.xyoh.y, r.xyoh.z, __uint_as_float(qm));
+            qm = quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0);
+            s_xyo[threadIdx.x] = r.xyoh;
             s_con[threadIdx.x] = r.conh;
             s_col[threadIdx.x] = r.col;
             s_id[threadIdx.x] = g;
         }
-        __syncthreads();
-        const int jtop = min(hi, wave_last + 1) - 1 - base;   // entries past the wave's last index carry nothing
-        for (int j = jtop; j >= 0; j--) {
-            const float4 xyo = s_xyo[j];
-            const uint32_t qm = __builtin_amdgcn_readfirstlane(__float_as_uint(xyo.w));
-            if (!((qm >> w) & 1u)) continue;            // below alpha_min at every pixel of this quad
-            const int kk = base + j;
-            const float4 con = s_con[j];
+        compact_quads(qm, s_qlist, s_wcnt, s_qcnt);
+        for (int j = s_qcnt[w] - 1; j >= 0; j--) {
+            const int e = __builtin_amdgcn_readfirstlane(s_qlist[w][j]);
+            const int kk = base + e;
+            if (kk > wave_last) continue;               // past every pixel's last composited entry
+            const float4 xyo = s_xyo[e];
+            const float4 con = s_con[e];
             const float dx = xyo.x - px, dy = xyo.y - py;
-            const float sigma = 0.5f * (con.x * dx * dx + con.z * dy * dy) + con.y * dx * dy;
-            const float e = __expf(-sigma);
-            const float araw = xyo.z * e;
+            const float sig = scaled_sigma(con, dx, dy);          // log2(e) sigma, as in the forward
+            const float ex = __builtin_amdgcn_exp2f(-sig);
+            const float araw = xyo.z * ex;
             const float al = fminf(amax, araw);
-            const bool use = kk <= last && sigma >= 0.0f && al >= amin;
+            const bool use = kk <= last && sig >= 0.0f && al >= amin;
             if (__ballot(use) == 0ull) continue;
-            const float4 col = s_col[j];
+            const float4 col = s_col[e];
             const float inv = __builtin_amdgcn_rcpf(1.0f - al);
             const float Tk = T * inv;
             const float wgt = use ? al * Tk : 0.0f;
@@ -161,31 +190,30 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
             T = use ? Tk : T;
             v_al = (use && araw <= amax) ? v_al : 0.0f;   // clamped alpha: no gradient to o or sigma
             const float v_sig = -araw * v_al;
-            const float g_mx = v_sig * (con.x * dx + con.y * dy);
-            const float g_my = v_sig * (con.y * dx + con.z * dy);
+            const float h = 0.5f * v_sig;
+            // d sigma / d mean = (a dx + b dy, b dx + c dy) = (2 con.x dx + con.y dy, con.y dx + 2 con.z dy) / log2(e)
+            const float u = v_sig * (1.0f / kLog2e);
+            const float g_mx = u * fmaf(2.0f * con.x, dx, con.y * dy);
+            const float g_my = u * fmaf(2.0f * con.z, dy, con.y * dx);
             // transposing butterfly: 8 values -> lane holds value (lane & 7)
             const float w0 = bfly<kDppXor1>(g_mx, g_my, b0);
-            const float w1 = bfly<kDppXor1>(v_sig * (0.5f * dx * dx), v_sig * (dx * dy), b0);
-            const float w2 = bfly<kDppXor1>(v_sig * (0.5f * dy * dy), wgt * vC0, b0);
+            const float w1 = bfly<kDppXor1>(h * dx * dx, v_sig * dx * dy, b0);
+            const float w2 = bfly<kDppXor1>(h * dy * dy, wgt * vC0, b0);
             const float w3 = bfly<kDppXor1>(wgt * vC1, wgt * vC2, b0);
             const float x0 = bfly<kDppXor2>(w0, w1, b1);
             const float x1 = bfly<kDppXor2>(w2, w3, b1);
             float y = bfly<kDppRor4>(x0, x1, b2);
             y += dpp<kDppRor8>(y);
-            y += __shfl_xor(y, 16, kWave);
-            y += __shfl_xor(y, 32, kWave);
-            const float zo = wave_total(e * v_al);
-            float zx = 0.0f, zy = 0.0f;
-            if (want_abs) { zx = wave_total(fabsf(g_mx)); zy = wave_total(fabsf(g_my)); }
-            if (slot >= 0 && (slot < 9 || want_abs)) {
-                const int g = s_id[j];
-                float *dst = slot < 2 ? a.v_means2d + 2 * g + slot
-                           : slot < 5 ? a.v_conics + 3 * g + (slot - 2)
-                           : slot < 8 ? a.v_colors + 3 * g + (slot - 5)
-                           : slot == 8 ? a.v_opac + g
-                                       : a.v_means2d_abs + 2 * g + (slot - 9);
-                const float val = slot < 8 ? y : slot == 8 ? zo : slot == 9 ? zx : zy;
-                unsafeAtomicAdd(dst, val);
+            y = add_xor32(add_xor16(y));
+            const float zo = wave_total(ex * v_al);
+            float val = lane < 8 ? y : zo;
+            if (want_abs) {
+                const float zx = wave_total(fabsf(g_mx)), zy = wave_total(fabsf(g_my));
+                val = lane == 9 ? zx : lane == 10 ? zy : val;
+            }
+            if (lane < nslots) {
+                const int g = s_id[e];
+                unsafeAtomicAdd(dst_base + (int64_t)g * dst_mul, val);
             }
         }
     }
@@ -198,18 +226,24 @@ int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, const
                          const float *comps, const float *background, const int32_t *ranges,
                          const int32_t *ids, const float *final_T, const int32_t *last_ids,
                          const float *v_image, const float *v_alpha, float *v_means2d, float *v_conics,
-                         float *v_colors, float *v_opac, float *v_means2d_abs, void *ws, hipStream_t s) {
+                         float *v_colors, float *v_opac, float *v_means2d_abs, void *ws, int flags,
+                         hipStream_t s) {
     const size_t CN = (size_t)cams.C * (size_t)N;
-    int rc = launch_fill_zero(v_means2d, CN * 2 * sizeof(float), s);
-    if (rc == GSR_OK) rc = launch_fill_zero(v_conics, CN * 3 * sizeof(float), s);
-    if (rc == GSR_OK) rc = launch_fill_zero(v_colors, CN * 3 * sizeof(float), s);
-    if (rc == GSR_OK) rc = launch_fill_zero(v_opac, CN * sizeof(float), s);
-    if (rc == GSR_OK && v_means2d_abs) rc = launch_fill_zero(v_means2d_abs, CN * 2 * sizeof(float), s);
+    int rc = GSR_OK;
+    if (!(flags & GSR_BWD_ACCUMULATE)) {
+        rc = launch_fill_zero(v_means2d, CN * 2 * sizeof(float), s);
+        if (rc == GSR_OK) rc = launch_fill_zero(v_conics, CN * 3 * sizeof(float), s);
+        if (rc == GSR_OK) rc = launch_fill_zero(v_colors, CN * 3 * sizeof(float), s);
+        if (rc == GSR_OK) rc = launch_fill_zero(v_opac, CN * sizeof(float), s);
+        if (rc == GSR_OK && v_means2d_abs) rc = launch_fill_zero(v_means2d_abs, CN * 2 * sizeof(float), s);
+    }
     if (rc != GSR_OK || cams.total_tiles == 0 || N == 0) return rc;
     const int cn = cams.C * N;
     PackedGauss *gauss = (PackedGauss *)ws;
-    rc = launch_pack(p, cn, N, means2d, conics, colors, opacities, p.antialiased ? comps : nullptr, gauss, s);
-    if (rc != GSR_OK) return rc;
+    if (!(flags & GSR_BWD_PACKED)) {
+        rc = launch_pack(p, cn, N, means2d, conics, colors, opacities, p.antialiased ? comps : nullptr, gauss, s);
+        if (rc != GSR_OK) return rc;
+    }
     RasterBwdArgs a{p, N, cn, gauss, background, ranges, ids, final_T, last_ids, v_image, v_alpha, v_means2d,
                     v_conics, v_colors, v_opac, v_means2d_abs};
     raster_bwd_kernel<<<dim3((unsigned)cams.total_tiles), dim3(kThreads), 0, s>>>(a, cams);

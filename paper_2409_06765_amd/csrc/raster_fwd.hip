@@ -2,13 +2,14 @@
 //
 // One 256-thread block per tile; each of the four wave64s owns an 8x8 pixel
 // quad.  The tile's sorted list is walked in batches of 256 Gaussians staged
-// in LDS by one coalesced gather; while staging, each Gaussian also records
-// which quads its alpha >= alpha_min support box (precomputed per projected
-// Gaussian by pack_kernel) can reach, so a wave
-// skips, with a scalar branch, the entries that are below alpha_min at all
-// its pixels.  The per-pixel update is branch-free (selects), so the wave
-// never splits on skip/stop decisions.  The block leaves the list once every
-// pixel has stopped.
+// in LDS by one coalesced gather.  While staging, the batch is also split
+// into four per-quad index lists (compact_quads) of the entries whose
+// alpha >= alpha_min support box (precomputed per projected Gaussian by
+// pack_kernel) reaches the quad, so a wave only visits entries that can
+// change one of its pixels; the rest are below alpha_min everywhere in the
+// quad and would be skipped by every pixel anyway.  The per-pixel update is
+// branch-free (selects), so the wave never splits on skip/stop decisions.
+// The block leaves the list once every pixel has stopped.
 #include "common.hpp"
 
 namespace gsr {
@@ -28,7 +29,7 @@ __global__ void __launch_bounds__(256) pack_kernel(int CN, int N, float alpha_mi
     const float2 h = support_extent(ca, cb, cc, o, alpha_min);
     PackedGauss r;
     r.xyoh = make_float4(means2d[2 * g], means2d[2 * g + 1], o, h.x);
-    r.conh = make_float4(ca, cb, cc, h.y);
+    r.conh = make_float4(0.5f * kLog2e * ca, kLog2e * cb, 0.5f * kLog2e * cc, h.y);
     r.col = make_float4(colors[3 * g], colors[3 * g + 1], colors[3 * g + 2], 0.0f);
     out[g] = r;
 }
@@ -48,10 +49,15 @@ struct RasterArgs {
     int32_t *__restrict__ n_eval;
 };
 
+// kCount: also count the entries each pixel evaluates and composites.
+template <bool kCount>
 __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamTable cams) {
-    __shared__ float4 s_xyo[kBatch];   // mean x, mean y, opacity, quad mask bits
+    __shared__ float4 s_xyo[kBatch];   // mean x, mean y, opacity, -
     __shared__ float4 s_con[kBatch];   // conic a, b, c, -
     __shared__ float4 s_col[kBatch];   // colour r, g, b, -
+    __shared__ uint8_t s_qlist[4][kBatch];
+    __shared__ int32_t s_wcnt[4][4];
+    __shared__ int32_t s_qcnt[4];
 
     const int tile = blockIdx.x;
     const int c = camera_of_tile(cams, tile);
@@ -65,7 +71,7 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     const float px = (float)xi + 0.5f, py = (float)yi + 0.5f;
     const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
     const int start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
-    const float amin = a.p.alpha_min, amax = a.p.alpha_max, tmin = a.p.T_min;
+    const float amin = a.p.alpha_min, amax = __builtin_canonicalizef(a.p.alpha_max), tmin = a.p.T_min;
 
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     int last = -1, ncomp = 0, stop_at = -1;
@@ -73,39 +79,39 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     for (int b0 = start; b0 < end; b0 += kBatch) {
         if (__syncthreads_count(done) == kThreads) break;
         const int k = b0 + (int)threadIdx.x;
+        uint32_t qm = 0u;
         if (k < end) {
             int g = a.ids[k];
             if ((unsigned)g >= (unsigned)a.CN) g = 0;   // ids come from the sort; this only bounds a bad input
             const PackedGauss r = a.gauss[g];
-            const uint32_t qm = quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0);
-            s_xyo[threadIdx.x] = make_float4(r.xyoh.x, r.xyoh.y, r.xyoh.z, __uint_as_float(qm));
+            qm = quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0);
+            s_xyo[threadIdx.x] = r.xyoh;
             s_con[threadIdx.x] = r.conh;
             s_col[threadIdx.x] = r.col;
         }
-        __syncthreads();
-        const int cnt = min(kBatch, end - b0);
+        compact_quads(qm, s_qlist, s_wcnt, s_qcnt);
+        const int cnt = s_qcnt[w];                  // entries that can reach this wave's quad
         if (__all(done)) continue;
         for (int j = 0; j < cnt; j++) {
-            const float4 xyo = s_xyo[j];
-            const uint32_t qm = __builtin_amdgcn_readfirstlane(__float_as_uint(xyo.w));
-            if (!((qm >> w) & 1u)) continue;            // below alpha_min at every pixel of this quad
-            const float4 con = s_con[j];
+            const int e = __builtin_amdgcn_readfirstlane(s_qlist[w][j]);
+            const float4 xyo = s_xyo[e];
+            const float4 con = s_con[e];
             const float dx = xyo.x - px, dy = xyo.y - py;
-            const float sigma = 0.5f * (con.x * dx * dx + con.z * dy * dy) + con.y * dx * dy;
-            const float al = fminf(amax, xyo.z * __expf(-sigma));
+            const float sig = scaled_sigma(con, dx, dy);          // log2(e) sigma
+            const float al = fminf(amax, xyo.z * __builtin_amdgcn_exp2f(-sig));
             const float Tn = T * (1.0f - al);
-            const bool use = !done && sigma >= 0.0f && al >= amin;
+            const bool use = !done && sig >= 0.0f && al >= amin;
             const bool stop = use && Tn < tmin;
             const bool comp = use && !stop;
-            stop_at = stop ? b0 + j : stop_at;
+            if (kCount) stop_at = stop ? b0 + e : stop_at;
             done = done || stop;
             const float wgt = comp ? al * T : 0.0f;
-            const float4 col = s_col[j];
+            const float4 col = s_col[e];
             C0 += col.x * wgt; C1 += col.y * wgt; C2 += col.z * wgt;
             T = comp ? Tn : T;
-            last = comp ? b0 + j : last;
-            ncomp += comp ? 1 : 0;
-            if ((j & 15) == 15 && __all(done)) break;
+            last = comp ? b0 + e : last;
+            if (kCount) ncomp += comp ? 1 : 0;
+            if ((j & 7) == 7 && __all(done)) break;
         }
     }
     if (!inside) return;
@@ -118,7 +124,7 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     a.alpha[pix] = 1.0f - T;
     a.final_T[pix] = T;
     a.last_ids[pix] = last;
-    if (a.n_eval) {
+    if (kCount) {
         // entries evaluated: up to and including the one that stopped the pixel, else the whole list
         a.n_eval[2 * pix] = stop_at >= 0 ? stop_at - start + 1 : end - start;
         a.n_eval[2 * pix + 1] = ncomp;
@@ -149,7 +155,10 @@ int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, const
         if (rc != GSR_OK) return rc;
     }
     RasterArgs a{p, N, CN, gauss, background, ranges, ids, image, alpha, final_T, last_ids, n_eval};
-    raster_fwd_kernel<<<dim3((unsigned)cams.total_tiles), dim3(kThreads), 0, s>>>(a, cams);
+    if (n_eval)
+        raster_fwd_kernel<true><<<dim3((unsigned)cams.total_tiles), dim3(kThreads), 0, s>>>(a, cams);
+    else
+        raster_fwd_kernel<false><<<dim3((unsigned)cams.total_tiles), dim3(kThreads), 0, s>>>(a, cams);
     return launch_check("rasterize_fwd");
 }
 

@@ -116,24 +116,44 @@ def rasterize_forward(p, proj, opacities, isect, W, H, background=None, n_eval=F
     out = dict(image=torch.empty((P, 3), **f), alpha=torch.empty(P, **f), final_T=torch.empty(P, **f),
                last_ids=torch.empty(P, device=d, dtype=torch.int32),
                n_eval=torch.empty((P, 2), device=d, dtype=torch.int32) if n_eval else None)
+    # the workspace keeps the packed per-Gaussian records for the backward
+    out["ws"] = raster_workspace(C, N, d)
     L.gsr_rasterize_fwd(p, C, N, W, H, proj["means2d"], proj["conics"], proj["colors"], opacities,
                         proj["comps"], background, isect["ranges"], isect["ids_buf"], out["image"], out["alpha"],
-                        out["final_T"], out["last_ids"], out["n_eval"], ws=raster_workspace(C, N, d), stream=stream)
+                        out["final_T"], out["last_ids"], out["n_eval"], ws=out["ws"], stream=stream)
     return out
 
 
+def grad_buffers(C, N, device, absgrad=False):
+    """Zeroed per-camera gradient buffers of the compositing backward, carved
+    from one allocation (one fill)."""
+    n = C * N
+    flat = torch.zeros(n * (11 if absgrad else 9), device=device, dtype=torch.float32)
+    return dict(v_means2d=flat[:2 * n].view(C, N, 2), v_conics=flat[2 * n:5 * n].view(C, N, 3),
+                v_colors=flat[5 * n:8 * n].view(C, N, 3), v_opacities=flat[8 * n:9 * n].view(C, N),
+                v_means2d_abs=flat[9 * n:11 * n].view(C, N, 2) if absgrad else None)
+
+
 def rasterize_backward(p, proj, opacities, isect, W, H, fwd, v_image, v_alpha=None, background=None,
-                       absgrad=False, stream=None):
+                       absgrad=False, grads=None, stream=None):
+    """Gradients of the compositing.  ``grads`` (from ``grad_buffers``) are
+    added to; by default fresh zeroed buffers are used.  The records the
+    forward packed into its workspace are reused."""
     C, N = proj["radii"].shape
     d = proj["radii"].device
-    f = dict(device=d, dtype=torch.float32)
-    g = dict(v_means2d=torch.empty((C, N, 2), **f), v_conics=torch.empty((C, N, 3), **f),
-             v_colors=torch.empty((C, N, 3), **f), v_opacities=torch.empty((C, N), **f),
-             v_means2d_abs=torch.empty((C, N, 2), **f) if absgrad else None)
+    g = grad_buffers(C, N, d, absgrad) if grads is None else grads
+    if absgrad and g["v_means2d_abs"] is None:
+        raise ValueError("absgrad needs grad buffers made with absgrad=True")
+    ws = fwd.get("ws")
+    flags = L.GSR_BWD_ACCUMULATE
+    if ws is None:
+        ws = raster_workspace(C, N, d)
+    else:
+        flags |= L.GSR_BWD_PACKED
     L.gsr_rasterize_bwd(p, C, N, W, H, proj["means2d"], proj["conics"], proj["colors"], opacities, proj["comps"],
                         background, isect["ranges"], isect["ids_buf"], fwd["final_T"], fwd["last_ids"], v_image,
                         v_alpha, g["v_means2d"], g["v_conics"], g["v_colors"], g["v_opacities"],
-                        g["v_means2d_abs"], ws=raster_workspace(C, N, d), stream=stream)
+                        g["v_means2d_abs"] if absgrad else None, ws=ws, flags=flags, stream=stream)
     return g
 
 

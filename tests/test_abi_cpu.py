@@ -36,7 +36,8 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_version_and_defaults(L):
-    assert L.abi_version() == 1
+    hdr = open(HEADER).read()
+    assert L.abi_version() == int(re.search(r"#define GSR_ABI_VERSION (\d+)", hdr).group(1)) == L.ABI_VERSION
     p = L.default_params()
     assert p.tile == 16 and p.sh_degree == -1 and p.antialiased == 0
     import numpy as np

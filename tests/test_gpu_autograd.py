@@ -1,0 +1,90 @@
+"""The torch.autograd.Function wrapper: gradients of a loss through
+``rasterization()`` against the oracle's analytic gradients (themselves
+pinned by float64 central differences on the CPU), plus a coarse central
+difference through the GPU forward itself."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import Oracle, OracleParams
+from paper_2409_06765_amd import scenes
+
+pytestmark = pytest.mark.gpu
+O32 = Oracle(np.float32)
+
+
+def _leaves(sc):
+    return {k: torch.from_numpy(sc[k]).cuda().requires_grad_(True)
+            for k in ("means", "quats", "scales", "opacities", "sh")}
+
+
+@pytest.mark.parametrize("deg,aa", [(3, False), (-1, False), (2, True)])
+def test_autograd_matches_oracle_gradients(deg, aa):
+    from _gpu import assert_grad_close
+    from paper_2409_06765_amd import rasterization
+    print(f"[gpu-autograd] deg={deg} aa={aa}", flush=True)
+    sc = scenes.scene_tiny(300, sh_degree=deg, seed=21 + deg, log_scale_mean=-2.4)
+    cams = scenes.cams_tiny(W=90, H=70, f=70.0, n_cams=2, seed=21)
+    P = OracleParams(sh_degree=deg, antialiased=int(aa))
+    proj, isect, ras = O32.forward(P, sc, cams)
+    ok = ras["flags"] == 0
+    v_image, v_alpha = scenes.upstream_grads("tiny", ok.size, seed=22, with_alpha=True)
+    v_image[~ok] = 0
+    v_alpha[~ok] = 0
+    t = _leaves(sc)
+    vm = torch.from_numpy(cams["viewmats"]).cuda()
+    Ks = torch.from_numpy(cams["Ks"]).cuda()
+    image, alpha, meta = rasterization(t["means"], t["quats"], t["scales"], t["opacities"], t["sh"], vm, Ks, 90, 70,
+                                       antialiased=aa)
+    assert image.shape == (2, 70, 90, 3) and alpha.shape == (2, 70, 90, 1)
+    loss = (image.reshape(-1, 3) * torch.from_numpy(v_image).cuda()).sum() + \
+           (alpha.reshape(-1) * torch.from_numpy(v_alpha).cuda()).sum()
+    loss.backward()
+    g2, g3 = O32.backward(P, sc, cams, proj, isect, ras, v_image, v_alpha)
+    for k, ko in (("means", "v_means"), ("quats", "v_quats"), ("scales", "v_scales"), ("opacities", "v_opacities"),
+                  ("sh", "v_sh")):
+        assert_grad_close(t[k].grad.cpu().numpy(), g3[ko], f"autograd:{k}", rtol=2e-3)
+
+
+def test_gpu_central_differences_on_smooth_parameters():
+    """With the skip and stop thresholds moved out of the way (alpha_min and
+    T_min of 1e-30; opacities below the 0.99 clamp) the image is smooth in the
+    colours and opacities (the tile lists do not depend on them), so a float32
+    central difference through the GPU forward agrees with the analytic
+    gradient to a few percent.  At the default thresholds a step in an
+    opacity moves pixels across alpha = 1/255, a jump the gradient leaves out
+    by definition."""
+    from paper_2409_06765_amd import rasterization
+    sc = scenes.scene_tiny(120, seed=31, log_scale_mean=-2.2)
+    sc["opacities"] = (0.2 + 0.5 * sc["opacities"]).astype(np.float32)
+    cams = scenes.cams_tiny(W=64, H=64, f=60.0)
+    vm = torch.from_numpy(cams["viewmats"]).cuda()
+    Ks = torch.from_numpy(cams["Ks"]).cuda()
+    v_image, _ = scenes.upstream_grads("tiny", 64 * 64, seed=32)
+    vi = torch.from_numpy(v_image).cuda()
+
+    def loss_of(t):
+        img, _, _ = rasterization(t["means"], t["quats"], t["scales"], t["opacities"], t["sh"], vm, Ks, 64, 64,
+                                  alpha_min=1e-30, T_min=1e-30)
+        return (img.reshape(-1, 3) * vi).sum()
+
+    t = _leaves(sc)
+    loss_of(t).backward()
+    g = np.random.default_rng(33)
+    checked = 0
+    for key in ("sh", "opacities"):
+        an_all = t[key].grad.cpu().numpy()
+        flat_idx = np.argsort(-np.abs(an_all).reshape(-1))[:6]     # the largest gradients: well above noise
+        for i in flat_idx:
+            eps = 2e-3
+            vals = []
+            for sgn in (1, -1):
+                tt = {k: v.detach().clone() for k, v in t.items()}
+                tt[key].view(-1)[i] += sgn * eps
+                with torch.no_grad():
+                    vals.append(float(loss_of(tt)))
+            fd = (vals[0] - vals[1]) / (2 * eps)
+            an = float(an_all.reshape(-1)[i])
+            assert abs(fd - an) <= 0.05 * abs(an) + 1e-3, (key, i, fd, an)
+            checked += 1
+    assert checked == 12

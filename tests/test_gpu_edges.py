@@ -95,3 +95,44 @@ def test_multiview_batch_equals_each_view_alone():
         np.testing.assert_array_equal(np_(s1["fwd"]["image"]), img_b)
         np.testing.assert_array_equal(np_(s1["fwd"]["final_T"]), np_(st["fwd"]["final_T"])[off:off + w * h])
         off += w * h
+
+
+def test_backward_flags_overwrite_repack_and_accumulate():
+    """gsr_rasterize_bwd with flags 0 (overwrite, pack anew) on buffers full of
+    garbage gives what the default path (records reused from the forward,
+    added into zeroed buffers) gives; accumulating a second call doubles it."""
+    from _gpu import gpu_backward, gpu_forward, np_, params, to_dev
+    from paper_2409_06765_amd import _lib as L
+    from paper_2409_06765_amd import rasterize as R
+    _say("backward flags")
+    sc = scenes.scene_tiny(400, sh_degree=2, seed=12, log_scale_mean=-2.6)
+    cams = scenes.cams_tiny(W=75, H=53, f=60.0, n_cams=2, seed=12)
+    p = params(sh_degree=2, antialiased=True)
+    st = gpu_forward(p, sc, cams)
+    v_image, v_alpha = scenes.upstream_grads("tiny", int(np.sum(cams["W"] * cams["H"])), seed=13, with_alpha=True)
+    ref, _ = gpu_backward(p, st, v_image, v_alpha, absgrad=True)
+    C, N = st["proj"]["radii"].shape
+    keys = ("v_means2d", "v_conics", "v_colors", "v_opacities", "v_means2d_abs")
+    junk = {k: torch.full_like(ref[k], 7.0) for k in keys}
+    vi, va = to_dev(v_image), to_dev(v_alpha)
+    d, pr, fw = st["d"], st["proj"], st["fwd"]
+    ws = R.raster_workspace(C, N, vi.device)      # fresh workspace: must be packed again
+
+    def call(g, ws, flags):
+        L.gsr_rasterize_bwd(p, C, N, st["W"], st["H"], pr["means2d"], pr["conics"], pr["colors"], d["opacities"],
+                            pr["comps"], None, st["isect"]["ranges"], st["isect"]["ids_buf"], fw["final_T"],
+                            fw["last_ids"], vi, va, g["v_means2d"], g["v_conics"], g["v_colors"], g["v_opacities"],
+                            g["v_means2d_abs"], ws=ws, flags=flags)
+
+    call(junk, ws, 0)
+    torch.cuda.synchronize()
+    for k in keys:
+        x, y = np_(junk[k]), np_(ref[k])
+        assert np.abs(x - y).max() <= 1e-5 * max(np.abs(y).max(), 1e-30), k
+    call(junk, fw["ws"], L.GSR_BWD_ACCUMULATE | L.GSR_BWD_PACKED)
+    torch.cuda.synchronize()
+    for k in keys:
+        x, y = np_(junk[k]), 2 * np_(ref[k])
+        assert np.abs(x - y).max() <= 1e-5 * max(np.abs(y).max(), 1e-30), k
+    with pytest.raises(L.GsrError):
+        call(junk, ws, 4)

@@ -1,0 +1,131 @@
+"""Parity at the benchmark's full size (1M Gaussians, 1920x1080, the launch
+configuration bench.py times) and on the 3M-Gaussian large scene: every
+projected quantity and every per-tile list bit for bit, and images and
+gradients on sampled tiles, which the oracle computes one by one with the
+per-tile definition (every projected Gaussian whose rectangle holds the tile,
+ordered by depth and id)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import Oracle, OracleParams
+from paper_2409_06765_amd import scenes
+
+pytestmark = pytest.mark.gpu
+O32 = Oracle(np.float32)
+O64 = Oracle(np.float64)
+
+
+def _say(msg):
+    print(f"[gpu-fullsize] {msg}", flush=True)
+
+
+def _sample_tiles(ranges, TX, n, seed):
+    lens = ranges[:, 1] - ranges[:, 0]
+    g = np.random.default_rng(seed)
+    busy = np.nonzero(lens > 0)[0]
+    heavy = busy[np.argsort(-lens[busy])[:n // 4]]          # the longest lists
+    rest = g.choice(np.setdiff1d(busy, heavy), size=n - heavy.size, replace=False)
+    pick = np.concatenate([heavy, rest])
+    return np.stack([np.zeros_like(pick), pick % TX, pick // TX], 1).astype(np.int32), pick
+
+
+def _pixels(tiles, W, H):
+    idx = []
+    for _, tx, ty in tiles:
+        for y in range(ty * 16, min(ty * 16 + 16, H)):
+            idx.extend(y * W + np.arange(tx * 16, min(tx * 16 + 16, W)))
+    return np.array(idx)
+
+
+# Share of sampled pixels the oracle may flag as undecidable at float32 (the
+# share grows with the entries a pixel evaluates: ~500 on the 1M scene, ~1,400
+# with many needle-shaped Gaussians on the 3M scene seen from inside).
+FLAG_BAR = {"cfg3": 0.01, "cfg4": 0.10}
+
+
+@pytest.mark.parametrize("wl", ["cfg3", "cfg4"])
+def test_full_size_view(wl):
+    from _gpu import assert_as_accurate_as_f32, assert_grad_close, gpu_backward, gpu_forward, np_, params
+    sc = getattr(scenes, f"scene_{wl}")()
+    cams_all = getattr(scenes, f"cams_{wl}")()
+    cams = {k: v[:1] for k, v in cams_all.items()}
+    W, H = int(cams["W"][0]), int(cams["H"][0])
+    TX = (W + 15) // 16
+    P = OracleParams(sh_degree=3)
+    p = params(sh_degree=3)
+    _say(f"{wl}: N={sc['means'].shape[0]} {W}x{H} gpu forward")
+    st = gpu_forward(p, sc, cams)
+    _say(f"{wl}: M={st['isect']['M']}; oracle projection")
+    proj = O32.project(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],
+                       cams["Ks"], cams["W"], cams["H"])
+    gp = st["proj"]
+    np.testing.assert_array_equal(np_(gp["radii"]), proj["radii"])
+    np.testing.assert_array_equal(np_(gp["means2d"]), proj["means2d"])
+    np.testing.assert_array_equal(np_(gp["depths"]), proj["depths"])
+    np.testing.assert_array_equal(np_(gp["conics"]), proj["conics"])
+    np.testing.assert_allclose(np_(gp["colors"]), proj["colors"], rtol=0, atol=2e-6)
+
+    ranges = np_(st["isect"]["ranges"])
+    ids = np_(st["isect"]["ids"])
+    tiles, pick = _sample_tiles(ranges, TX, 16, seed=1)
+    _say(f"{wl}: oracle per-tile definition on {len(tiles)} tiles (longest list {int((ranges[:, 1] - ranges[:, 0]).max())})")
+    ref = O32.render_tiles_fwd(P, proj, sc["opacities"], tiles, cams["W"], cams["H"])
+    # per-tile lists: bit-exact against the definition's (depth bits, id) order
+    for (c, tx, ty), t, ln in zip(tiles, pick, ref["list_len"]):
+        assert ranges[t, 1] - ranges[t, 0] == ln
+        np.testing.assert_array_equal(ids[ranges[t, 0]:ranges[t, 1]], O32.tile_list(P, proj, W, H, c, tx, ty))
+    pix = _pixels(tiles, W, H)
+    ok = ref["flags"][pix] == 0
+    _say(f"{wl}: {int((~ok).sum())} flagged of {pix.size} sampled pixels")
+    assert (~ok).mean() < FLAG_BAR[wl]
+    f = st["fwd"]
+    err = np.abs(np_(f["image"])[pix] - ref["image"][pix]).max(axis=1)
+    assert err[ok].max() <= 1e-4
+    lid = np_(f["last_ids"])[pix]
+    gid = np.where(lid >= 0, ids[np.maximum(lid, 0)], -1)
+    np.testing.assert_array_equal(gid[ok], ref["last_gid"][pix][ok])
+    np.testing.assert_array_equal(np_(f["n_eval"])[pix, 0][ok], ref["n_eval"][pix][ok])
+
+    # gradients from the sampled tiles only (upstream gradient zero elsewhere)
+    v_image = np.zeros((W * H, 3), np.float32)
+    vi, _ = scenes.upstream_grads(wl, pix.size, seed=2)
+    v_image[pix[ok]] = vi[ok]
+    _say(f"{wl}: backward")
+    g2, g3 = gpu_backward(p, st, v_image)
+    o2 = O32.render_tiles_bwd(P, proj, sc["opacities"], tiles, cams["W"], cams["H"], v_image, abs_sums=True)
+    # a Gaussian here sums thousands of per-pixel terms of both signs: the
+    # element-wise bar includes the float32 summation scale
+    for k in ("v_means2d", "v_conics", "v_colors", "v_opacities"):
+        assert_grad_close(np_(g2[k]), o2[k], f"{wl}:{k}", abs_ref=o2["abs_" + k])
+    o3 = O32.project_bwd(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],
+                         cams["Ks"], cams["W"], cams["H"], o2["v_means2d"], o2["v_conics"], o2["v_colors"],
+                         o2["v_opacities"])
+    # projection backward at full size from identical upstream gradients
+    from _gpu import to_dev
+    from paper_2409_06765_amd import rasterize as R
+    d = st["d"]
+    g2o = {k: to_dev(o2[k]) for k in ("v_means2d", "v_conics", "v_colors", "v_opacities")}
+    g3o = R.project_backward(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], st["vm"], st["Ks"],
+                             st["W"], st["H"], st["proj"], g2o)
+    # some elements cancel in float32 (large terms of both signs through J and
+    # the SH direction): judged against the float64 oracle fed the same input
+    o3x = O64.project_bwd(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],
+                          cams["Ks"], cams["W"], cams["H"], o2["v_means2d"], o2["v_conics"], o2["v_colors"],
+                          o2["v_opacities"])
+    ulp = np.random.default_rng(3)
+
+    def nudge(a):           # every element moved by about one float32 ulp
+        a = np.asarray(a, np.float32)
+        return (a * (1 + np.float32(2.0 ** -23) * ulp.choice([-1, 1], size=a.shape))).astype(np.float32)
+    o3p = O32.project_bwd(P, nudge(sc["means"]), nudge(sc["quats"]), nudge(sc["scales"]), sc["opacities"],
+                          nudge(sc["sh"]), cams["viewmats"], cams["Ks"], cams["W"], cams["H"], o2["v_means2d"],
+                          o2["v_conics"], o2["v_colors"], o2["v_opacities"])
+    for k in ("v_means", "v_quats", "v_scales", "v_opacities", "v_sh"):
+        assert_as_accurate_as_f32(np_(g3o[k]), [o3[k], o3p[k]], o3x[k], f"{wl}:{k}")
+    # end to end: norm-wise (the chain carries the summation error above)
+    for k in ("v_means", "v_quats", "v_scales", "v_opacities", "v_sh"):
+        x, y = np_(g3[k]).astype(np.float64), o3[k].astype(np.float64)
+        assert np.linalg.norm(x - y) <= 2e-3 * np.linalg.norm(y), f"{wl}:chain:{k}"
+    del st
+    torch.cuda.empty_cache()

@@ -287,3 +287,30 @@ def test_two_gaussian_alpha_gradients():
     # at the mean e^-sigma = 1, so dC/do = dC/dalpha
     np.testing.assert_allclose(g["v_opacities"][0, 0], np.dot(c1 - c2 * a2, v_image[p]), rtol=1e-12)
     np.testing.assert_allclose(g["v_opacities"][0, 1], np.dot(c2 * (1 - a1), v_image[p]), rtol=1e-12)
+
+
+def test_absolute_term_sums_bound_and_match_single_signed_terms():
+    """The per-element term magnitudes that the gradient tolerance uses: they
+    bound |gradient|, equal it when every term has one sign and no parts to
+    cancel (colour gradient under a non-negative upstream gradient: alpha T
+    v_C >= 0), are linear in the upstream gradients, and leave the gradients
+    themselves unchanged."""
+    P = OracleParams(sh_degree=1)
+    sc = scenes.scene_tiny(150, sh_degree=1, seed=41, log_scale_mean=-2.4)
+    cams = scenes.cams_tiny(W=48, H=40, f=50.0, n_cams=2, seed=41)
+    proj, isect, ras = O64.forward(P, sc, cams)
+    v_image, v_alpha = scenes.upstream_grads("tiny", ras["final_T"].shape[0], seed=42, with_alpha=True)
+    args = (P, proj, sc["opacities"], isect["ranges"], isect["ids"], cams["W"], cams["H"], ras["final_T"],
+            ras["last_ids"])
+    plain = O64.rasterize_bwd(*args, v_image, v_alpha)
+    g = O64.rasterize_bwd(*args, v_image, v_alpha, abs_sums=True)
+    for k in ("v_means2d", "v_conics", "v_colors", "v_opacities"):
+        np.testing.assert_array_equal(g[k], plain[k])
+        assert (g["abs_" + k] >= np.abs(g[k]) * (1 - 1e-12)).all(), k
+    assert g["abs_v_means2d"].max() > 0 and g["abs_v_opacities"].max() > 0
+    pos = O64.rasterize_bwd(*args, np.abs(v_image), None, abs_sums=True)
+    np.testing.assert_allclose(pos["abs_v_colors"], pos["v_colors"], rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(pos["abs_v_colors"], g["abs_v_colors"], rtol=1e-12, atol=1e-300)
+    two = O64.rasterize_bwd(*args, 2 * v_image, 2 * v_alpha, abs_sums=True)
+    for k in ("v_means2d", "v_conics", "v_colors", "v_opacities"):
+        np.testing.assert_allclose(two["abs_" + k], 2 * g["abs_" + k], rtol=1e-12, atol=1e-300)
