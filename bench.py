@@ -35,13 +35,16 @@ PEAK_HBM_GBS = 8000.0
 FLOPS_EVAL, FLOPS_FWD_COMP, FLOPS_BWD_COMP = 14, 9, 49
 
 WORKLOADS = {
-    "cfg3": dict(desc="1M Gaussians, 32 clusters, SH degree 3, 1920x1080, fx=fy=1500, 16 views on a radius-6 sphere",
-                 scene="scene_cfg3", cams="cams_cfg3", sh_degree=3),
-    "cfg2": dict(desc="100k Gaussians, SH degree 3, 800x800, fx=fy=1100, one view on a radius-4 sphere",
-                 scene="scene_cfg2", cams="cams_cfg2", sh_degree=3),
-    "cfg4": dict(desc="3M Gaussians (2.4M in a 20x20x5 box + 0.6M on a radius-50 shell), SH degree 3, 1920x1080, "
-                      "fx=fy=1200, 4 views from inside the box",
-                 scene="scene_cfg4", cams="cams_cfg4", sh_degree=3),
+    "clusters1m_sh3_1080p": dict(
+        desc="1M Gaussians, 32 clusters, SH degree 3, 1920x1080, fx=fy=1500, 16 views on a radius-6 sphere",
+        scene="scene_clusters1m_sh3_1080p", cams="cams_clusters1m_sh3_1080p", sh_degree=3),
+    "uniform100k_sh3_800": dict(
+        desc="100k Gaussians, SH degree 3, 800x800, fx=fy=1100, one view on a radius-4 sphere",
+        scene="scene_uniform100k_sh3_800", cams="cams_uniform100k_sh3_800", sh_degree=3),
+    "box3m_sh3_1080p": dict(
+        desc="3M Gaussians (2.4M in a 20x20x5 box + 0.6M on a radius-50 shell), SH degree 3, 1920x1080, "
+             "fx=fy=1200, 4 views from inside the box",
+        scene="scene_box3m_sh3_1080p", cams="cams_box3m_sh3_1080p", sh_degree=3),
 }
 
 
@@ -54,7 +57,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg3", choices=list(WORKLOADS))
+    ap.add_argument("--workload", default="clusters1m_sh3_1080p", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-tiles", type=int, default=96, help="tiles of view 0 the oracle rasterizes")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
@@ -185,7 +188,7 @@ def main():
         "raster_fwd_tflops": round(fwd_tflops, 3),
         "roofline": roofline,
     }
-    if not args.no_serve and args.workload == "cfg3":
+    if not args.no_serve and args.workload == "clusters1m_sh3_1080p":
         out["serving"] = serving(d, p, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, cams, wl, args, counts, views[0])

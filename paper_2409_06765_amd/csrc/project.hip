@@ -328,13 +328,17 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
         vt[2] += -(vmx * fx * tx + vmy * fy * ty) / (tz * tz);
         if (v_depths) vt[2] += v_depths[g];
 
-        // conic -> Sigma':  dL/dSigma' = -Y G Y,  G = [[ga, gb/2], [gb/2, gc]]
+        // conic -> Sigma':  dL/dSigma' = -Y G Y,  G = [[ga, gb/2], [gb/2, gc]].  The product is
+        // formed in full (S10 apart from S01, each row from the same row of Y G): for needle-like
+        // Gaussians Y is nearly singular and the later products with T and Sigma cancel, which
+        // amplifies errors that differ between rows; rows built consistently keep them small.
         const float ya = o.c / o.det, yb = -o.b / o.det, yc = o.a / o.det;
         const float ga = v_conics[3 * g], gb = 0.5f * v_conics[3 * g + 1], gc = v_conics[3 * g + 2];
         const float YG00 = ya * ga + yb * gb, YG01 = ya * gb + yb * gc;
         const float YG10 = yb * ga + yc * gb, YG11 = yb * gb + yc * gc;
         float S00 = -(YG00 * ya + YG01 * yb);
         float S01 = -(YG00 * yb + YG01 * yc);
+        float S10 = -(YG10 * ya + YG11 * yb);
         float S11 = -(YG10 * yb + YG11 * yc);
         if (p.antialiased) {
             const float det0 = o.cov[0] * o.cov[2] - o.cov[1] * o.cov[1];
@@ -344,6 +348,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
                 const float k0 = 0.5f * comp * vcomp;
                 S00 += k0 * (o.cov[2] / det0 - o.c / o.det);
                 S01 += k0 * (-o.cov[1] / det0 + o.b / o.det);
+                S10 += k0 * (-o.cov[1] / det0 + o.b / o.det);
                 S11 += k0 * (o.cov[0] / det0 - o.a / o.det);
             }
         }
@@ -351,7 +356,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
         float U[2][3];
         for (int j = 0; j < 3; j++) {
             U[0][j] = S00 * o.T[0][j] + S01 * o.T[1][j];
-            U[1][j] = S01 * o.T[0][j] + S11 * o.T[1][j];
+            U[1][j] = S10 * o.T[0][j] + S11 * o.T[1][j];
         }
         // dL/dSigma = T^T U ;  dL/dT = 2 U Sigma
         float vSig[3][3];

@@ -20,13 +20,14 @@ STREAM_SCENE, STREAM_CAMS, STREAM_GRADS, STREAM_FD, STREAM_TRACE = 0, 1, 2, 3, 4
 
 WORKLOADS = {
     "tiny": "Small parity case: N Gaussians in [-1,1]^3, one camera on the +z axis",
-    "cfg1": "Forward only: 10k Gaussians, direct RGB, 256x256, fx=fy=256, camera at (0,0,4)",
-    "cfg2": "Forward+backward: 100k Gaussians, SH degree 3, 800x800, fx=fy=1100, camera on a radius-4 sphere",
-    "cfg3": "Training-step shape: 1M Gaussians in 32 clusters, SH degree 3, 1920x1080, fx=fy=1500, "
+    "uniform10k_256": "Forward only: 10k Gaussians, direct RGB, 256x256, fx=fy=256, camera at (0,0,4)",
+    "uniform100k_sh3_800": "Forward+backward: 100k Gaussians, SH degree 3, 800x800, fx=fy=1100, camera on a "
+                           "radius-4 sphere",
+    "clusters1m_sh3_1080p": "Training-step shape: 1M Gaussians in 32 clusters, SH degree 3, 1920x1080, fx=fy=1500, "
             "16 viewpoints on a radius-6 sphere",
-    "cfg4": "Large scene: 3M Gaussians (2.4M in a 20x20x5 box + 0.6M on a radius-50 shell), SH degree 3, "
+    "box3m_sh3_1080p": "Large scene: 3M Gaussians (2.4M in a 20x20x5 box + 0.6M on a radius-50 shell), SH degree 3, "
             "1920x1080, fx=fy=1200, camera inside the box",
-    "cfg5": "Serving: the 1M-Gaussian cluster scene resident, 2000 Poisson requests over "
+    "serving_mix": "Serving: the 1M-Gaussian cluster scene resident, 2000 Poisson requests over "
             "{256^2, 512^2, 800^2, 1280x720, 1920x1080}, focal 1.2 W",
 }
 _WL_INDEX = {name: i for i, name in enumerate(WORKLOADS)}
@@ -125,8 +126,8 @@ def cams_tiny(W=64, H=48, f=60.0, n_cams=1, seed=0, radius=4.0):
     return cameras([look_at(e) for e in eyes], [intrinsics(f, w, h) for w, h in zip(Ws, Hs)], Ws, Hs)
 
 
-def scene_cfg1(seed=0, n=10_000):
-    g = rng("cfg1", STREAM_SCENE, seed)
+def scene_uniform10k_256(seed=0, n=10_000):
+    g = rng("uniform10k_256", STREAM_SCENE, seed)
     means = g.uniform(-1.0, 1.0, (n, 3))
     log_scales = g.normal(-4.0, 0.5, (n, 3))
     quats = _unit_quats(g, n)
@@ -135,12 +136,12 @@ def scene_cfg1(seed=0, n=10_000):
     return _pack(means, quats, log_scales, logits, rgb, -1)
 
 
-def cams_cfg1():
+def cams_uniform10k_256():
     return cameras([look_at((0.0, 0.0, 4.0))], [intrinsics(256.0, 256, 256)], 256, 256)
 
 
-def scene_cfg2(seed=0, n=100_000):
-    g = rng("cfg2", STREAM_SCENE, seed)
+def scene_uniform100k_sh3_800(seed=0, n=100_000):
+    g = rng("uniform100k_sh3_800", STREAM_SCENE, seed)
     means = g.uniform(-1.0, 1.0, (n, 3))
     log_scales = g.normal(-4.0, 0.5, (n, 3))
     quats = _unit_quats(g, n)
@@ -149,13 +150,13 @@ def scene_cfg2(seed=0, n=100_000):
     return _pack(means, quats, log_scales, logits, sh, 3)
 
 
-def cams_cfg2(seed=0):
-    eye = _sphere_eyes(rng("cfg2", STREAM_CAMS, seed), 1, 4.0)[0]
+def cams_uniform100k_sh3_800(seed=0):
+    eye = _sphere_eyes(rng("uniform100k_sh3_800", STREAM_CAMS, seed), 1, 4.0)[0]
     return cameras([look_at(eye)], [intrinsics(1100.0, 800, 800)], 800, 800)
 
 
-def scene_cfg3(seed=0, n=1_000_000, n_clusters=32):
-    g = rng("cfg3", STREAM_SCENE, seed)
+def scene_clusters1m_sh3_1080p(seed=0, n=1_000_000, n_clusters=32):
+    g = rng("clusters1m_sh3_1080p", STREAM_SCENE, seed)
     centres = g.uniform(-3.0, 3.0, (n_clusters, 3))
     which = g.integers(0, n_clusters, n)
     means = centres[which] + g.normal(0.0, 0.3, (n, 3))
@@ -166,13 +167,13 @@ def scene_cfg3(seed=0, n=1_000_000, n_clusters=32):
     return _pack(means, quats, log_scales, logits, sh, 3)
 
 
-def cams_cfg3(seed=0, n_views=16):
-    eyes = _sphere_eyes(rng("cfg3", STREAM_CAMS, seed), n_views, 6.0)
+def cams_clusters1m_sh3_1080p(seed=0, n_views=16):
+    eyes = _sphere_eyes(rng("clusters1m_sh3_1080p", STREAM_CAMS, seed), n_views, 6.0)
     return cameras([look_at(e) for e in eyes], [intrinsics(1500.0, 1920, 1080)] * n_views, 1920, 1080)
 
 
-def scene_cfg4(seed=0, n=3_000_000, far_fraction=0.2):
-    g = rng("cfg4", STREAM_SCENE, seed)
+def scene_box3m_sh3_1080p(seed=0, n=3_000_000, far_fraction=0.2):
+    g = rng("box3m_sh3_1080p", STREAM_SCENE, seed)
     n_far = int(round(n * far_fraction))
     n_box = n - n_far
     box = g.uniform([-10.0, -10.0, -2.5], [10.0, 10.0, 2.5], (n_box, 3))
@@ -186,8 +187,8 @@ def scene_cfg4(seed=0, n=3_000_000, far_fraction=0.2):
     return _pack(means, quats, log_scales, logits, sh, 3)
 
 
-def cams_cfg4(seed=0, n_views=4):
-    g = rng("cfg4", STREAM_CAMS, seed)
+def cams_box3m_sh3_1080p(seed=0, n_views=4):
+    g = rng("box3m_sh3_1080p", STREAM_CAMS, seed)
     eyes = g.uniform([-5.0, -5.0, -1.25], [5.0, 5.0, 1.25], (n_views, 3))
     th = g.uniform(0.0, 2.0 * np.pi, n_views)
     vms = [look_at(e, e + np.array([np.cos(t), np.sin(t), 0.0]), up=(0.0, 0.0, 1.0)) for e, t in zip(eyes, th)]
@@ -211,7 +212,7 @@ def serving_trace(rate_hz, n_requests=2000, seed=0, resolutions=None):
     """Poisson arrivals at ``rate_hz``, resolutions uniform over the set,
     focal 1.2 W, principal point at the image centre, poses on a radius-6
     sphere looking at the origin."""
-    g = rng("cfg5", STREAM_TRACE, seed)
+    g = rng("serving_mix", STREAM_TRACE, seed)
     res = resolutions or SERVE_RESOLUTIONS
     gaps = g.exponential(1.0 / rate_hz, n_requests)
     arrivals = np.cumsum(gaps) - gaps[0]

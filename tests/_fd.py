@@ -81,7 +81,7 @@ def fd_check(o, P, sc, cams, v_image, v_alpha=None, background=None, n_params=64
     proj, isect, ras = o.forward(P, sc, cams, background=background)
     g2, g3 = o.backward(P, sc, cams, proj, isect, ras, v_image, v_alpha, background)
     touched = np.nonzero(np.abs(g2["v_colors"]).sum(axis=(0, 2)) > 0)[0]
-    g = _sc.rng("cfg2", _sc.STREAM_FD, seed)
+    g = _sc.rng("uniform100k_sh3_800", _sc.STREAM_FD, seed)
     order = g.permutation(touched)
     rows, rejected = [], 0
     for n in order[:max_gauss]:

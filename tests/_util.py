@@ -39,3 +39,20 @@ def all_tiles(W, H, tile=16):
             for tx in range(TX):
                 out.append((c, tx, ty))
     return np.array(out, np.int32)
+
+
+def wide_cone_scene(n, seed, sh_degree=3, higher_band_std=0.6):
+    """Gaussians in front of a camera at z = 4 looking at -z (cams_tiny's
+    single camera), at depths 0.5 .. 3.5 and lateral offsets up to twice the
+    depth: with a 1.3 x half-field Jacobian clamp many means fall outside it
+    in x and in y.  Higher SH bands are strong so the view-direction gradient
+    matters."""
+    from paper_2409_06765_amd import scenes
+    sc = scenes.scene_tiny(n, sh_degree=sh_degree, seed=seed, log_scale_mean=-1.5, spread=1.0)
+    g = np.random.default_rng(seed)
+    depth = g.uniform(0.5, 3.5, n)
+    lat = g.uniform(-2.0, 2.0, (n, 2)) * depth[:, None]
+    sc["means"] = np.stack([lat[:, 0], lat[:, 1], 4.0 - depth], 1).astype(np.float32)
+    if sh_degree > 0:
+        sc["sh"][:, 1:, :] = g.normal(0.0, higher_band_std, sc["sh"][:, 1:, :].shape).astype(np.float32)
+    return sc

@@ -41,10 +41,10 @@ def _pixels(tiles, W, H):
 # Share of sampled pixels the oracle may flag as undecidable at float32 (the
 # share grows with the entries a pixel evaluates: ~500 on the 1M scene, ~1,400
 # with many needle-shaped Gaussians on the 3M scene seen from inside).
-FLAG_BAR = {"cfg3": 0.01, "cfg4": 0.10}
+FLAG_BAR = {"clusters1m_sh3_1080p": 0.01, "box3m_sh3_1080p": 0.10}
 
 
-@pytest.mark.parametrize("wl", ["cfg3", "cfg4"])
+@pytest.mark.parametrize("wl", ["clusters1m_sh3_1080p", "box3m_sh3_1080p"])
 def test_full_size_view(wl):
     from _gpu import assert_as_accurate_as_f32, assert_grad_close, gpu_backward, gpu_forward, np_, params
     sc = getattr(scenes, f"scene_{wl}")()

@@ -32,8 +32,8 @@ CASES = {
                     lambda: scenes.cams_tiny(W=97, H=61, f=70.0, n_cams=2, seed=2), 3, True, None),
     "tiny_sh1": (lambda: scenes.scene_tiny(200, sh_degree=1, seed=3, log_scale_mean=-2.0),
                  lambda: scenes.cams_tiny(W=48, H=48, f=40.0, seed=3), 1, False, None),
-    "cfg1": (scenes.scene_cfg1, scenes.cams_cfg1, -1, False, None),
-    "cfg2": (scenes.scene_cfg2, scenes.cams_cfg2, 3, False, None),
+    "uniform10k_256": (scenes.scene_uniform10k_256, scenes.cams_uniform10k_256, -1, False, None),
+    "uniform100k_sh3_800": (scenes.scene_uniform100k_sh3_800, scenes.cams_uniform100k_sh3_800, 3, False, None),
 }
 
 

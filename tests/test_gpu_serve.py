@@ -15,7 +15,7 @@ def test_served_images_equal_their_renders_alone():
     from paper_2409_06765_amd import rasterize as R
     from paper_2409_06765_amd.serve import GpuBackend, Server
     print("[gpu-serve] 40 requests against a 20k-Gaussian scene", flush=True)
-    sc = scenes.scene_cfg3(n=20_000)
+    sc = scenes.scene_clusters1m_sh3_1080p(n=20_000)
     d = scene_to_dev(sc)
     p = params(sh_degree=3)
     trace = scenes.serving_trace(3000.0, n_requests=40, seed=5,

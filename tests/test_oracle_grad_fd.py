@@ -32,13 +32,13 @@ def test_rendered_loss_gradients_match_fd(deg, aa, bg):
 
 
 @pytest.mark.slow
-def test_cfg2_fd_on_64_sampled_parameters():
-    """The CFG2 protocol: 100k Gaussians, SH3, 800x800, eps = 1e-3, 64 sampled
+def test_uniform100k_sh3_800_fd_on_64_sampled_parameters():
+    """The finite-difference protocol on the 100k scene: 100k Gaussians, SH3, 800x800, eps = 1e-3, 64 sampled
     parameters (eight per Gaussian; a sample whose decision trace changes
     within +-eps is redrawn), float64 oracle."""
     P = OracleParams(sh_degree=3)
-    sc = scenes.scene_cfg2()
-    cams = scenes.cams_cfg2()
-    v_image, _ = scenes.upstream_grads("cfg2", 800 * 800)
+    sc = scenes.scene_uniform100k_sh3_800()
+    cams = scenes.cams_uniform100k_sh3_800()
+    v_image, _ = scenes.upstream_grads("uniform100k_sh3_800", 800 * 800)
     rows, rejected = fd_check(O64, P, sc, cams, v_image.astype(np.float64), None, n_params=64, eps=1e-3)
     _check(rows, rejected, min_rows=64)

@@ -12,7 +12,7 @@ from scipy.special import sph_harm_y
 from oracle import Oracle, OracleParams
 from oracle import defs
 from paper_2409_06765_amd import scenes
-from _util import one_gaussian_scene, simple_cam
+from _util import one_gaussian_scene, simple_cam, wide_cone_scene
 
 O64 = Oracle(np.float64)
 O32 = Oracle(np.float32)
@@ -217,13 +217,25 @@ def _proj_loss(P, sc, cams, w):
     return L, p
 
 
-@pytest.mark.parametrize("deg,aa,jc", [(3, 0, 1.3), (-1, 0, 0.0), (2, 1, 1.3)])
-def test_projection_gradients_match_central_differences(deg, aa, jc):
+@pytest.mark.parametrize("deg,aa,jc,wide", [(3, 0, 1.3, False), (-1, 0, 0.0, False), (2, 1, 1.3, False),
+                                             (3, 0, 1.3, True), (2, 1, 1.3, True)])
+def test_projection_gradients_match_central_differences(deg, aa, jc, wide):
+    """wide: one camera and a wide cone of Gaussians, about half of them past
+    the Jacobian clamp in x or y (the clamped coordinate follows t_z)."""
     P = OracleParams(sh_degree=deg, antialiased=aa, jac_clamp=jc)
-    sc = scenes.scene_tiny(24, sh_degree=deg, seed=11, log_scale_mean=-2.0)
+    if wide:
+        sc = wide_cone_scene(48, seed=13, sh_degree=deg)
+        cams = scenes.cams_tiny(W=120, H=90, f=80.0)
+    else:
+        sc = scenes.scene_tiny(24, sh_degree=deg, seed=11, log_scale_mean=-2.0)
+        cams = scenes.cams_tiny(W=80, H=60, f=60.0, n_cams=2, seed=11)
     sc = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
-    cams = scenes.cams_tiny(W=80, H=60, f=60.0, n_cams=2, seed=11)
-    C, N = 2, 24
+    C, N = cams["viewmats"].shape[0], sc["means"].shape[0]
+    if wide:
+        p32 = O64.project(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],
+                          cams["Ks"], cams["W"], cams["H"])
+        u = p32["means2d"][p32["radii"] > 0]
+        assert (np.abs(u[:, 0] - 60) > 78).sum() >= 3 and (np.abs(u[:, 1] - 45) > 58.5).sum() >= 3
     g = np.random.default_rng(12)
     w = dict(m=g.standard_normal((C, N, 2)), c=g.standard_normal((C, N, 3)) * 10,
              col=g.standard_normal((C, N, 3)), d=g.standard_normal((C, N)), o=g.standard_normal((C, N)))
@@ -255,4 +267,4 @@ def test_projection_gradients_match_central_differences(deg, aa, jc):
             an = gr[gkey].reshape(-1)[i]
             assert abs(fd - an) <= 1e-5 * max(1.0, abs(fd)), (key, i, fd, an)
             checked += 1
-    assert checked > 60
+    assert checked > (40 if wide else 60)
