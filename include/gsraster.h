@@ -167,6 +167,12 @@ int gsr_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_
  * which must be passed unchanged to gsr_bin_finish.
  * gsr_bin_finish: ids [M] int32 and ranges [total_tiles, 2] int32 as above;
  * keys [M] uint64 (nullable) receives the 64-bit keys of the sorted lists.
+ * M is a capacity: the kernels read the true count from ws_prep on the
+ * device, so the host need not wait for gsr_bin_prepare.  When the true
+ * count exceeds M nothing is written past M and the lists are incomplete:
+ * the caller compares the count (total_dev of gsr_bin_prepare) with M after
+ * the fact and calls again with a larger M.  Unused capacity costs sort
+ * launches over empty blocks.
  * ws_fin: gsr_workspace_bytes(GSR_OP_BIN_FINISH, C, N, M). */
 int gsr_bin_prepare(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
                     const float *means2d, const int32_t *radii, const float *depths,

@@ -181,9 +181,10 @@ __device__ __forceinline__ int64_t owner_search(const int64_t *__restrict__ offs
 template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N, int64_t n_total,
         const float *__restrict__ means2d, const int32_t *__restrict__ radii, const float *__restrict__ depths,
-        const int32_t *__restrict__ order, const int64_t *__restrict__ offsets, int64_t cap, K *__restrict__ keys,
-        int32_t *__restrict__ ids) {
+        const int32_t *__restrict__ order, const int64_t *__restrict__ offsets, int64_t cap,
+        const int64_t *__restrict__ count_dev, K *__restrict__ keys, int32_t *__restrict__ ids) {
     constexpr int kWaves = kEmitThreads / kWave;
+    if (count_dev) cap = min(cap, *count_dev);   // capacity mode: the true count lives on the device
     __shared__ int64_t s_start[kWaves][kWave];   // first slot of each entry of the window
     __shared__ int32_t s_w[kWaves][kWave];       // rectangle width in tiles
     __shared__ int32_t s_row[kWaves][kWave];     // tile_base + y0 * TX + x0 of the entry's camera
@@ -267,7 +268,9 @@ template <typename K>
 __device__ __forceinline__ int32_t tile_of(K key) { return (int32_t)(sizeof(K) == 8 ? (uint64_t)key >> 32 : key); }
 
 template <typename K>
-__global__ void ranges_kernel(int64_t M, const K *__restrict__ keys, int32_t total_tiles, int32_t *__restrict__ ranges) {
+__global__ void ranges_kernel(int64_t M, const int64_t *__restrict__ count_dev, const K *__restrict__ keys,
+                              int32_t total_tiles, int32_t *__restrict__ ranges) {
+    if (count_dev) M = min(M, *count_dev);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     const int32_t t = tile_of<K>(keys[i]);
@@ -300,9 +303,11 @@ __global__ void __launch_bounds__(256) gather_counts_kernel(int64_t n_total, con
 }
 
 // 64-bit keys of the sorted lists (only when a caller asks for them).
-__global__ void __launch_bounds__(256) keys64_kernel(int64_t M, const uint32_t *__restrict__ tkeys,
+__global__ void __launch_bounds__(256) keys64_kernel(int64_t M, const int64_t *__restrict__ count_dev,
+                                                     const uint32_t *__restrict__ tkeys,
                                                      const int32_t *__restrict__ ids, const float *__restrict__ depths,
                                                      int64_t n_total, uint64_t *__restrict__ keys) {
+    if (count_dev) M = min(M, *count_dev);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     const int32_t g = ids[i];
@@ -336,8 +341,9 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, uint64_t a
 
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K *__restrict__ keys, int64_t M,
-        int shift, int bits, int nblocks, int32_t *__restrict__ hist) {
+        const int64_t *__restrict__ count_dev, int shift, int bits, int nblocks, int32_t *__restrict__ hist) {
     __shared__ int32_t cnt[kBins];
+    if (count_dev) M = min(M, *count_dev);      // blocks past the count write zero histograms
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t mask = (1u << bits) - 1u;
@@ -375,8 +381,9 @@ __global__ void __launch_bounds__(kScanThreads) radix_rowscan_kernel(int32_t *__
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__restrict__ keys_in,
         const int32_t *__restrict__ ids_in, K *__restrict__ keys_out, int32_t *__restrict__ ids_out,
-        int64_t M, int shift, int bits, int nblocks, const int32_t *__restrict__ hist,
-        const int32_t *__restrict__ digit_tot) {
+        int64_t M, const int64_t *__restrict__ count_dev, int shift, int bits, int nblocks,
+        const int32_t *__restrict__ hist, const int32_t *__restrict__ digit_tot) {
+    if (count_dev) M = min(M, *count_dev);
     __shared__ K s_keys[kSortTile];
     __shared__ int32_t s_ids[kSortTile];
     __shared__ int32_t s_wcnt[kSortWaves][kBins];
@@ -439,7 +446,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__
         }
     }
     __syncthreads();
-    const int n_valid = (int)((M - base) < kSortTile ? (M - base) : kSortTile);
+    const int n_valid = (int)((M - base) < kSortTile ? (M - base) : kSortTile);   // <= 0 past the count
     for (int j = t; j < n_valid; j += kSortThreads) {
         const K k = s_keys[j];
         const uint32_t d = (uint32_t)(k >> shift) & mask;
@@ -459,10 +466,11 @@ size_t radix_ws_bytes(int64_t M) {
 }
 
 // Sorts M pairs by the low key_bits bits; an even number of passes leaves
-// the result in keys/ids.
+// the result in keys/ids.  count_dev (nullable): the true number of pairs,
+// at most M, read on the device (the grids are sized for M).
 template <typename K>
 int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int32_t *ids_alt, void *ws,
-               hipStream_t s) {
+               hipStream_t s, const int64_t *count_dev = nullptr) {
     if (M <= 1) return GSR_OK;
     int passes = (key_bits + 7) / 8;
     if (passes % 2) passes++;
@@ -477,9 +485,10 @@ int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int3
         int bits = key_bits - shift;
         if (bits > width) bits = width;
         if (bits < 0) bits = 0;   // a padding pass: every digit 0, a stable copy
-        radix_hist_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, M, shift, bits, nb, hist);
+        radix_hist_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, M, count_dev, shift, bits, nb, hist);
         radix_rowscan_kernel<<<kBins, kScanThreads, 0, s>>>(hist, nb, dtot);
-        radix_scatter_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, iin, kout, iout, M, shift, bits, nb, hist, dtot);
+        radix_scatter_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, iin, kout, iout, M, count_dev, shift, bits, nb,
+                                                           hist, dtot);
         K *tk = kin; kin = kout; kout = tk;
         int32_t *ti = iin; iin = iout; iout = ti;
     }
@@ -585,7 +594,7 @@ int launch_intersect_emit(const gsr_params &p, const CamTable &cams, int N, cons
     if (n == 0 || cap == 0) return GSR_OK;
     const int64_t nb = emit_blocks(cap);
     emit_kernel<uint64_t><<<dim3((unsigned)nb), dim3(kEmitThreads), 0, s>>>(cams, N, n, means2d, radii, depths,
-                                                                           nullptr, offsets, cap, keys, ids);
+                                                                           nullptr, offsets, cap, nullptr, keys, ids);
     return launch_check("intersect_emit");
 }
 
@@ -601,7 +610,8 @@ int launch_fill_zero(void *ptr, size_t bytes, hipStream_t s) {
 int launch_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_t *ranges, hipStream_t s) {
     int rc = launch_fill_zero(ranges, (size_t)total_tiles * 2 * sizeof(int32_t), s);
     if (rc != GSR_OK || M == 0) return rc;
-    ranges_kernel<uint64_t><<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, keys, total_tiles, ranges);
+    ranges_kernel<uint64_t><<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, nullptr, keys, total_tiles,
+                                                                                  ranges);
     return launch_check("tile_ranges");
 }
 
@@ -643,15 +653,18 @@ int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const fl
     int rc = launch_fill_zero(ranges, (size_t)cams.total_tiles * 2 * sizeof(int32_t), s);
     if (rc != GSR_OK || n == 0 || M == 0) return rc;
     const int64_t ne = emit_blocks(M);
+    // M is the capacity; the true count (b.total, from the prepare step) is read on the device
     emit_kernel<uint32_t><<<dim3((unsigned)ne), dim3(kEmitThreads), 0, s>>>(cams, N, n, means2d, radii, depths,
-                                                                           b.order, b.offsets_sorted, M, f.tkeys, ids);
+                                                                           b.order, b.offsets_sorted, M, b.total,
+                                                                           f.tkeys, ids);
     const int tile_bits = cams.total_tiles > 1 ? 32 - __builtin_clz((unsigned)(cams.total_tiles - 1)) : 1;
-    rc = radix_sort<uint32_t>(M, tile_bits, f.tkeys, ids, f.tkeys_alt, f.ids_alt, f.sort_ws, s);
+    rc = radix_sort<uint32_t>(M, tile_bits, f.tkeys, ids, f.tkeys_alt, f.ids_alt, f.sort_ws, s, b.total);
     if (rc != GSR_OK) return rc;
-    ranges_kernel<uint32_t><<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, f.tkeys, cams.total_tiles,
-                                                                                  ranges);
+    ranges_kernel<uint32_t><<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, b.total, f.tkeys,
+                                                                                  cams.total_tiles, ranges);
     if (keys64)
-        keys64_kernel<<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, f.tkeys, ids, depths, n, keys64);
+        keys64_kernel<<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, b.total, f.tkeys, ids, depths, n,
+                                                                             keys64);
     return launch_check("bin_finish");
 }
 

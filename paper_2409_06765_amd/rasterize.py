@@ -54,14 +54,78 @@ def project(p, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H
     return out
 
 
-def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None):
-    """Per-tile depth-sorted lists.  Waits once for the intersection count,
-    which sizes the list buffers.
+class Intersections(dict):
+    """Result of ``intersect``.  With the binning route the intersection
+    count M stays on the device while the lists are built in a buffer of a
+    capacity chosen from earlier calls; reading ``M`` (or ``ids``/``keys``)
+    waits only for the count's copy to host memory, and a count above the
+    capacity rebuilds the lists (one extra synchronous pass, rare)."""
 
-    method="bin": depth order of the projected Gaussians, then a stable sort
-    of 32-bit tile keys (gsr_bin_prepare / gsr_bin_finish); method="keys64":
-    count, emit 64-bit keys, stable radix sort, ranges.  Both give the same
-    ids and ranges."""
+    def __init__(self, *a, **kw):
+        super().__init__(*a, **kw)
+        self._pending = None          # (event, pinned count, capacity, shape key, rebuild) until resolved
+        self.rebuilt = False
+
+    def _resolve(self):
+        if self._pending is None:
+            return
+        ev, pinned, cap, shape, rebuild = self._pending
+        self._pending = None
+        ev.synchronize()
+        M = int(pinned[0])
+        _CAPACITY.note(shape, M)
+        if M > cap:
+            dict.update(self, rebuild(M))
+            self.rebuilt = True
+        self._set_count(M)
+
+    def _set_count(self, M):
+        dict.__setitem__(self, "M", M)
+        dict.__setitem__(self, "ids", self["ids_buf"][:M])
+        if self.get("keys_buf") is not None:
+            dict.__setitem__(self, "keys", self["keys_buf"][:M])
+
+    def check(self):
+        """Resolves the count; True when the lists had to be rebuilt, in
+        which case work already launched on them must be launched again."""
+        self._resolve()
+        return self.rebuilt
+
+    def __getitem__(self, k):
+        if k in ("M", "ids", "keys"):
+            self._resolve()
+        return dict.__getitem__(self, k)
+
+
+class _Capacity:
+    """Intersection-buffer capacity per (device, cameras, Gaussians, image
+    sizes): 1.25 x the largest count seen, at least 2^16."""
+
+    def __init__(self):
+        self.cap = {}
+
+    def get(self, shape):
+        return self.cap.get(shape, 0)
+
+    def note(self, shape, M):
+        if shape is not None:
+            self.cap[shape] = max(self.cap.get(shape, 0), int(M * 1.25) + 1024, 1 << 16)
+
+
+_CAPACITY = _Capacity()
+
+
+def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None, capacity=None):
+    """Per-tile depth-sorted lists.
+
+    method="bin" (default): depth order of the projected Gaussians, then a
+    stable sort of 32-bit tile keys (gsr_bin_prepare / gsr_bin_finish).  The
+    host does not wait for the intersection count: the lists are built in a
+    buffer of ``capacity`` entries (default: from earlier calls of the same
+    shape; the first call of a shape waits for the count) and the count is
+    checked when M is read.  method="keys64": count (waits for it), emit
+    64-bit keys, stable radix sort, ranges.  Both give the same ids and
+    ranges."""
     C, N = proj["radii"].shape
     d = proj["radii"].device
     _, tile_off = layout(W, H)
@@ -70,17 +134,41 @@ def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None):
     ranges = torch.empty((max(total_tiles, 1), 2), device=d, dtype=torch.int32)
     key_bits = 32 + max(total_tiles - 1, 0).bit_length()
     if method == "bin":
+        shape = (str(d), C, N, tuple(int(w) for w in W), tuple(int(h) for h in H))
         wsp = torch.empty(max(L.workspace_bytes(L.GSR_OP_BIN_PREPARE, C, N, 0), 1), device=d, dtype=torch.uint8)
-        M = L.gsr_bin_prepare(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], total, wsp,
-                              sync=True, stream=stream)
-        ids = torch.empty(max(M, 1), device=d, dtype=torch.int32)
-        keys = torch.empty(max(M, 1), device=d, dtype=torch.uint64) if want_keys else None
-        wsf = torch.empty(max(L.workspace_bytes(L.GSR_OP_BIN_FINISH, C, N, M), 1), device=d, dtype=torch.uint8)
-        L.gsr_bin_finish(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], M, ids, ranges, keys,
-                         wsp, wsf, stream=stream)
-        out = dict(M=M, ids=ids[:M], ids_buf=ids, ranges=ranges, total_tiles=total_tiles, key_bits=key_bits)
-        if want_keys:
-            out.update(keys=keys[:M], keys_buf=keys)
+        cap = int(capacity) if capacity is not None else _CAPACITY.get(shape)
+        M_known = L.gsr_bin_prepare(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], total, wsp,
+                                    sync=cap == 0, stream=stream)
+        if M_known is not None:
+            _CAPACITY.note(shape, M_known)
+            cap = M_known
+
+        def build(cap):
+            ids = torch.empty(max(cap, 1), device=d, dtype=torch.int32)
+            keys = torch.empty(max(cap, 1), device=d, dtype=torch.uint64) if want_keys else None
+            wsf = torch.empty(max(L.workspace_bytes(L.GSR_OP_BIN_FINISH, C, N, cap), 1), device=d,
+                              dtype=torch.uint8)
+            L.gsr_bin_finish(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], cap, ids, ranges, keys,
+                             wsp, wsf, stream=stream)
+            return dict(ids_buf=ids, keys_buf=keys)
+
+        out = Intersections(ranges=ranges, total_tiles=total_tiles, key_bits=key_bits, total_dev=total,
+                            **build(cap))
+        if M_known is not None:
+            out._set_count(M_known)
+            return out
+        s = stream if stream is not None else torch.cuda.current_stream(d)
+        pinned = torch.empty(1, dtype=torch.int64, pin_memory=True)
+        with torch.cuda.stream(s):
+            pinned.copy_(total, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+
+        def rebuild(M):
+            # the capacity was too small: wait for the stream, rebuild with the true count
+            s.synchronize()
+            return build(M)
+        out._pending = (ev, pinned, cap, shape, rebuild)
         return out
     counts = torch.empty((C, N), device=d, dtype=torch.int32)
     offsets = torch.empty((C, N), device=d, dtype=torch.int64)
@@ -181,6 +269,8 @@ class RasterizeGaussians(torch.autograd.Function):
         proj = project(p, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H)
         isect = intersect(p, proj, W, H)
         fwd = rasterize_forward(p, proj, opacities, isect, W, H, background)
+        if isect.check():            # the list capacity was too small: composite the rebuilt lists
+            fwd = rasterize_forward(p, proj, opacities, isect, W, H, background)
         ctx.p, ctx.W, ctx.H, ctx.absgrad = p, W, H, absgrad
         ctx.proj, ctx.isect, ctx.fwd = proj, isect, fwd
         ctx.save_for_backward(means, quats, scales, opacities, sh_or_colors, viewmats, Ks, background)

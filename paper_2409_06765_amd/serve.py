@@ -210,13 +210,18 @@ class GpuBackend:
             h.proj = R.project(self.p, s["means"], s["quats"], s["scales"], s["opacities"], s["sh"], vm, Ks, h.W, h.H,
                                stream=self.stage_stream)
             h.isect = R.intersect(self.p, h.proj, h.W, h.H, stream=self.stage_stream)
-            h.M = h.isect["M"]
             h.ready = torch.cuda.Event()
             h.ready.record(self.stage_stream)
         return h
 
     def finish(self, h):
         torch, R = self.torch, self.R
+        # the count is long on the host by now; lists that overflowed their capacity are rebuilt on the
+        # staging stream, which the compositing then waits for
+        if h.isect.check():
+            h.ready = torch.cuda.Event()
+            h.ready.record(self.stage_stream)
+        h.M = h.isect["M"]
         self.raster_stream.wait_event(h.ready)
         with torch.cuda.stream(self.raster_stream):
             h.fwd = R.rasterize_forward(self.p, h.proj, self.scene["opacities"], h.isect, h.W, h.H,

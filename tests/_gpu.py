@@ -35,6 +35,8 @@ def gpu_forward(p, sc, cams, background=None, n_eval=True, method="bin", want_ke
     proj = R.project(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, W, H)
     isect = R.intersect(p, proj, W, H, method=method, want_keys=want_keys)
     fwd = R.rasterize_forward(p, proj, d["opacities"], isect, W, H, bg, n_eval=n_eval)
+    if method == "bin" and isect.check():
+        fwd = R.rasterize_forward(p, proj, d["opacities"], isect, W, H, bg, n_eval=n_eval)
     torch.cuda.synchronize()
     return dict(d=d, vm=vm, Ks=Ks, W=W, H=H, bg=bg, proj=proj, isect=isect, fwd=fwd)
 

@@ -136,3 +136,31 @@ def test_backward_flags_overwrite_repack_and_accumulate():
         assert np.abs(x - y).max() <= 1e-5 * max(np.abs(y).max(), 1e-30), k
     with pytest.raises(L.GsrError):
         call(junk, ws, 4)
+
+
+@pytest.mark.parametrize("capacity", [1, 37, 10 ** 6])
+def test_binning_capacity_below_and_above_the_count(capacity):
+    """gsr_bin_finish with a list capacity below the true count writes nothing
+    past it and the wrapper rebuilds the lists once the count is known; with
+    a capacity far above the count the extra sort blocks are empty.  Either
+    way ids and ranges equal those of the oracle, bit for bit."""
+    from _gpu import np_, params, scene_to_dev, to_dev
+    from paper_2409_06765_amd import rasterize as R
+    _say(f"binning capacity {capacity}")
+    sc = scenes.scene_tiny(300, seed=8, log_scale_mean=-2.5)
+    cams = scenes.cams_tiny(W=70, H=50, f=60.0, n_cams=2, seed=8)
+    P = OracleParams()
+    proj_o = O32.project(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],
+                         cams["Ks"], cams["W"], cams["H"])
+    ref = O32.intersect(P, proj_o, cams["W"], cams["H"])
+    assert ref["M"] > 37
+    p = params()
+    d = scene_to_dev(sc)
+    W, H = [int(w) for w in cams["W"]], [int(h) for h in cams["H"]]
+    proj = R.project(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], to_dev(cams["viewmats"]),
+                     to_dev(cams["Ks"]), W, H)
+    isect = R.intersect(p, proj, W, H, capacity=capacity)
+    assert isect.check() == (capacity < ref["M"])
+    assert isect["M"] == ref["M"]
+    np.testing.assert_array_equal(np_(isect["ids"]), ref["ids"])
+    np.testing.assert_array_equal(np_(isect["ranges"])[:len(ref["ranges"])], ref["ranges"])
