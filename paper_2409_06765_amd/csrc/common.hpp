@@ -147,13 +147,50 @@ __device__ __forceinline__ uint32_t quad_mask(float mx, float my, float hx, floa
 
 // Per projected Gaussian record read by the compositing kernels:
 // {mean x, mean y, opacity (times compensation), support half-width x},
-// {a/2, b, c/2 scaled by log2(e), support half-width y}, {colour r, g, b, 0},
-// with (a, b, c) the conic.  The scaling gives log2(e) sigma directly
-// (scaled_sigma), the argument of the hardware base-2 exponential.
+// {a/2, b, c/2 scaled by log2(e), support half-width y},
+// {colour r, g, b, log2(opacity / alpha_min)}, with (a, b, c) the conic.  The
+// scaling gives log2(e) sigma directly (scaled_sigma), the argument of the
+// hardware base-2 exponential; alpha >= alpha_min exactly where
+// log2(e) sigma <= log2(opacity / alpha_min).
 constexpr float kLog2e = 1.4426950408889634f;
 
 __device__ __forceinline__ float scaled_sigma(float4 con, float dx, float dy) {
     return fmaf(dx, fmaf(con.x, dx, con.y * dy), con.z * dy * dy);
+}
+
+// The quadratic q(u, v) = A u^2 + B u v + C v^2 (A, C > 0, 4AC > B^2) on the
+// segment u = u0, v in [v0, v1]: its minimum, at v = clamp(-B u0 / (2C)).
+__device__ __forceinline__ float edge_min(float A, float B, float C, float r, float u0, float v0, float v1) {
+    const float v = fminf(fmaxf(r * u0, v0), v1);
+    return fmaf(u0, fmaf(A, u0, B * v), C * v * v);
+}
+
+// Refines a quad mask with the exact support: quad q stays only if the
+// scaled sigma's minimum over the quad's rectangle of pixel centres reaches
+// the threshold Lq = log2(opacity / alpha_min) (plus a margin far above the
+// float32 error of this test and of the per-pixel evaluation); a bounding
+// box keeps many quads that an elongated, tilted ellipse misses.  In terms
+// of d = mean - pixel the rectangle is [u0, u1] x [v0, v1]; the minimum of
+// the convex quadratic is 0 if the rectangle holds d = 0, else on an edge.
+__device__ __forceinline__ uint32_t refine_quad_mask(uint32_t m, float4 xyoh, float4 conh, float Lq,
+                                                    float tile_x0, float tile_y0) {
+    const float A = conh.x, B = conh.y, C = conh.z;
+    if (m == 0u || !(A > 0.0f) || !(C > 0.0f) || !(4.0f * A * C > B * B)) return m;
+    const float ru = -B / (2.0f * C), rv = -B / (2.0f * A);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        if (!((m >> q) & 1u)) continue;
+        const float x0 = tile_x0 + (float)((q & 1) * 8) + 0.5f, y0 = tile_y0 + (float)((q >> 1) * 8) + 0.5f;
+        const float u0 = xyoh.x - (x0 + 7.0f), u1 = xyoh.x - x0;
+        const float v0 = xyoh.y - (y0 + 7.0f), v1 = xyoh.y - y0;
+        if (u0 <= 0.0f && u1 >= 0.0f && v0 <= 0.0f && v1 >= 0.0f) continue;
+        float smin = fminf(edge_min(A, B, C, ru, u0, v0, v1), edge_min(A, B, C, ru, u1, v0, v1));
+        smin = fminf(smin, fminf(edge_min(C, B, A, rv, v0, u0, u1), edge_min(C, B, A, rv, v1, u0, u1)));
+        const float U = fmaxf(fabsf(u0), fabsf(u1)), V = fmaxf(fabsf(v0), fabsf(v1));
+        const float smag = fmaf(A, U * U, fmaf(fabsf(B), U * V, C * V * V));
+        if (smin > Lq + 1e-5f * smag + 1e-4f * fabsf(Lq) + 1e-4f) m &= ~(1u << q);
+    }
+    return m;
 }
 
 struct PackedGauss {

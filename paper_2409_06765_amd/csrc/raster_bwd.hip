@@ -3,9 +3,10 @@
 // Same tiling as the forward: a 256-thread block per 16x16 tile, an 8x8
 // quad per wave, LDS-staged batches walked back to front over the same
 // per-quad lists.  Each pixel restores T from final_T by T_k = T_{k+1} /
-// (1 - alpha_k) and carries S, the colour accumulated behind the current
-// entry plus final_T times the background.  A wave starts at the largest
-// last_ids among its own pixels.
+// (1 - alpha_k) and carries the dot product of v_C with S, the colour
+// accumulated behind the current entry plus final_T times the background
+// (the alpha gradient needs S only through it).  A wave starts at the
+// largest last_ids among its own pixels.
 //
 // The nine per-pixel gradients of one Gaussian are summed over the 64 lanes
 // by a transposing butterfly on DPP lane swizzles: three exchange steps halve
@@ -113,19 +114,20 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
     const int start = a.ranges[2 * tile];
     const float amin = a.p.alpha_min, amax = __builtin_canonicalizef(a.p.alpha_max);
 
+    // Per pixel: T restored back to front, and SV = (S . v_C) with S the colour accumulated behind the
+    // current entry (plus final_T times the background): dL/dalpha only needs S through that dot
+    // product, and S . v_C advances by (colour . v_C) alpha T_k per composited entry.
     int last = -1;
-    float T = 1.0f, Tf = 1.0f, vC0 = 0.0f, vC1 = 0.0f, vC2 = 0.0f, vA = 0.0f;
-    float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
+    float T = 1.0f, vC0 = 0.0f, vC1 = 0.0f, vC2 = 0.0f, vATf = 0.0f, SV = 0.0f;
     if (inside) {
         const int64_t pix = ci.pix_off + (int64_t)yi * ci.W + xi;
         last = a.last_ids[pix];
-        Tf = a.final_T[pix];
+        const float Tf = a.final_T[pix];
         T = Tf;
         vC0 = a.v_image[3 * pix]; vC1 = a.v_image[3 * pix + 1]; vC2 = a.v_image[3 * pix + 2];
-        if (a.v_alpha) vA = a.v_alpha[pix];
-        if (a.background) {
-            S0 = Tf * a.background[3 * c]; S1 = Tf * a.background[3 * c + 1]; S2 = Tf * a.background[3 * c + 2];
-        }
+        if (a.v_alpha) vATf = a.v_alpha[pix] * Tf;
+        if (a.background)
+            SV = Tf * ((a.background[3 * c] * vC0 + a.background[3 * c + 1] * vC1) + a.background[3 * c + 2] * vC2);
     }
     // largest last index of the wave and of the block
     int m = last;
@@ -160,7 +162,8 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
             int g = a.ids[k];
             if ((unsigned)g >= (unsigned)a.CN) g = 0;   // ids come from the sort; this only bounds a bad input
             const PackedGauss r = a.gauss[g];
-            qm = quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0);
+            qm = refine_quad_mask(quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0), r.xyoh,
+                                  r.conh, r.col.w, tile_x0, tile_y0);
             s_xyo[threadIdx.x] = r.xyoh;
             s_con[threadIdx.x] = r.conh;
             s_col[threadIdx.x] = r.col;
@@ -184,9 +187,10 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
             const float inv = __builtin_amdgcn_rcpf(1.0f - al);
             const float Tk = T * inv;
             const float wgt = use ? al * Tk : 0.0f;
-            float v_al = (col.x * Tk - S0 * inv) * vC0 + (col.y * Tk - S1 * inv) * vC1 +
-                         (col.z * Tk - S2 * inv) * vC2 + vA * (Tf * inv);
-            S0 += col.x * wgt; S1 += col.y * wgt; S2 += col.z * wgt;
+            // dL/dalpha = (colour T_k - S / (1 - alpha)) . v_C + v_alpha final_T / (1 - alpha)
+            const float cv = (col.x * vC0 + col.y * vC1) + col.z * vC2;
+            float v_al = fmaf(Tk, cv, inv * (vATf - SV));
+            SV = fmaf(wgt, cv, SV);
             T = use ? Tk : T;
             v_al = (use && araw <= amax) ? v_al : 0.0f;   // clamped alpha: no gradient to o or sigma
             const float v_sig = -araw * v_al;

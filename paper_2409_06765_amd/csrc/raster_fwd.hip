@@ -30,7 +30,8 @@ __global__ void __launch_bounds__(256) pack_kernel(int CN, int N, float alpha_mi
     PackedGauss r;
     r.xyoh = make_float4(means2d[2 * g], means2d[2 * g + 1], o, h.x);
     r.conh = make_float4(0.5f * kLog2e * ca, kLog2e * cb, 0.5f * kLog2e * cc, h.y);
-    r.col = make_float4(colors[3 * g], colors[3 * g + 1], colors[3 * g + 2], 0.0f);
+    r.col = make_float4(colors[3 * g], colors[3 * g + 1], colors[3 * g + 2],
+                        o >= alpha_min ? log2f(o / alpha_min) : -1.0f);
     out[g] = r;
 }
 
@@ -84,7 +85,8 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
             int g = a.ids[k];
             if ((unsigned)g >= (unsigned)a.CN) g = 0;   // ids come from the sort; this only bounds a bad input
             const PackedGauss r = a.gauss[g];
-            qm = quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0);
+            qm = refine_quad_mask(quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0), r.xyoh,
+                                  r.conh, r.col.w, tile_x0, tile_y0);
             s_xyo[threadIdx.x] = r.xyoh;
             s_con[threadIdx.x] = r.conh;
             s_col[threadIdx.x] = r.col;
