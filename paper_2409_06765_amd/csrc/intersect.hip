@@ -191,6 +191,8 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
     __shared__ int32_t s_TX[kWaves][kWave];
     __shared__ uint32_t s_dbits[kWaves][kWave];
     __shared__ int32_t s_g[kWaves][kWave];
+    __shared__ K s_okey[kWaves][kEmitChunk];     // the wave's slice, written out coalesced at the end
+    __shared__ int32_t s_oid[kWaves][kEmitChunk];
     const int lane = __lane_id(), w = threadIdx.x / kWave;
     const int64_t c0 = ((int64_t)blockIdx.x * kWaves + w) * kEmitChunk;
     if (c0 >= cap) return;                       // wave-uniform
@@ -231,26 +233,49 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // Each lane writes a run of at most 8 consecutive slots of [p0, p1): it finds the owner of its
+        // first slot by binary search (the largest L with s_start[L] <= pos; zero-count entries share
+        // their successor's start and lose to it), then walks the owner's rectangle row by row and
+        // moves to the next owner where a rectangle ends.
         const int64_t p0 = max(c0, wbeg), p1 = min(c1, wend);
-        for (int64_t pos = p0 + lane; pos < p1; pos += kWave) {
-            // largest L with s_start[L] <= pos: the entry owning the slot (zero-count entries
-            // share their successor's start and lose to it)
+        const int run = (int)((p1 - p0 + kWave - 1) / kWave);
+        int64_t pos = p0 + (int64_t)lane * run;
+        const int64_t pend = min(pos + run, p1);
+        if (pos < pend) {
             int lo = 0, hi = kWave - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (s_start[w][mid] <= pos) lo = mid; else hi = mid - 1;
             }
-            const int local = (int)(pos - s_start[w][lo]);
-            const int wdt = max(s_w[w][lo], 1);
-            const int dy = local / wdt;
-            const int dx = local - dy * wdt;
-            keys[pos] = make_key<K>((uint32_t)(s_row[w][lo] + dy * s_TX[w][lo] + dx), s_dbits[w][lo]);
-            ids[pos] = s_g[w][lo];
+            int local = (int)(pos - s_start[w][lo]);
+            int wdt = max(s_w[w][lo], 1);
+            int dy = local / wdt;
+            int dx = local - dy * wdt;
+            for (; pos < pend; pos++) {
+                while (lo + 1 < kWave && s_start[w][lo + 1] <= pos) {   // next owner (its rectangle starts here)
+                    lo++;
+                    wdt = max(s_w[w][lo], 1);
+                    dx = 0;
+                    dy = 0;
+                }
+                const int slot = (int)(pos - c0);
+                s_okey[w][slot] = make_key<K>((uint32_t)(s_row[w][lo] + dy * s_TX[w][lo] + dx), s_dbits[w][lo]);
+                s_oid[w][slot] = s_g[w][lo];
+                if (++dx == wdt) { dx = 0; dy++; }
+            }
         }
         if (wend >= c1) break;
         __builtin_amdgcn_wave_barrier();         // the window's LDS is rewritten next
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int n_out = (int)(c1 - c0);             // every slot of [c0, c1) was written above
+    for (int i = lane; i < n_out; i += kWave) {
+        keys[c0 + i] = s_okey[w][i];
+        ids[c0 + i] = s_oid[w][i];
     }
 }
 
@@ -341,7 +366,8 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, uint64_t a
 
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K *__restrict__ keys, int64_t M,
-        const int64_t *__restrict__ count_dev, int shift, int bits, int nblocks, int32_t *__restrict__ hist) {
+        const int64_t *__restrict__ count_dev, int shift, int bits, int nblocks, int stride,
+        int32_t *__restrict__ hist) {
     __shared__ int32_t cnt[kBins];
     if (count_dev) M = min(M, *count_dev);      // blocks past the count write zero histograms
     cnt[threadIdx.x] = 0;
@@ -358,21 +384,45 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K *__res
         if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&cnt[d], (int32_t)__popcll(peers));
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+    if (threadIdx.x < (1 << bits)) hist[(int64_t)threadIdx.x * stride + blockIdx.x] = cnt[threadIdx.x];
 }
 
 // One block per digit: exclusive scan of hist[d][0..nblocks) in place; the
-// row total goes to digit_tot[d].
+// row total goes to digit_tot[d].  Rows are `stride` entries apart (a
+// multiple of 4, so they are read and written as int4), and each thread
+// takes kRowItems consecutive entries per round: a row of a few thousand
+// blocks takes one or two rounds of a block scan.
+constexpr int kRowItems = 16;
+
 __global__ void __launch_bounds__(kScanThreads) radix_rowscan_kernel(int32_t *__restrict__ hist, int nblocks,
-                                                                     int32_t *__restrict__ digit_tot) {
-    int32_t *row = hist + (int64_t)blockIdx.x * nblocks;
+                                                                     int stride, int32_t *__restrict__ digit_tot) {
+    int32_t *row = hist + (int64_t)blockIdx.x * stride;
     int32_t carry = 0;
-    for (int start = 0; start < nblocks; start += kScanThreads) {
-        const int i = start + threadIdx.x;
-        const int32_t v = i < nblocks ? row[i] : 0;
+    for (int start = 0; start < nblocks; start += kScanThreads * kRowItems) {
+        const int base = start + (int)threadIdx.x * kRowItems;
+        int32_t v[kRowItems];
+        int32_t local = 0;
+#pragma unroll
+        for (int i = 0; i < kRowItems; i += 4) {
+            int4 q = make_int4(0, 0, 0, 0);
+            if (base + i < stride) q = *reinterpret_cast<const int4 *>(row + base + i);
+            v[i] = base + i < nblocks ? q.x : 0;
+            v[i + 1] = base + i + 1 < nblocks ? q.y : 0;
+            v[i + 2] = base + i + 2 < nblocks ? q.z : 0;
+            v[i + 3] = base + i + 3 < nblocks ? q.w : 0;
+            local += (v[i] + v[i + 1]) + (v[i + 2] + v[i + 3]);
+        }
         int32_t tot;
-        const int32_t ex = block_exclusive_scan<int32_t>(v, tot);
-        if (i < nblocks) row[i] = carry + ex;
+        int32_t run = carry + block_exclusive_scan<int32_t>(local, tot);
+#pragma unroll
+        for (int i = 0; i < kRowItems; i += 4) {
+            int4 q;
+            q.x = run; run += v[i];
+            q.y = run; run += v[i + 1];
+            q.z = run; run += v[i + 2];
+            q.w = run; run += v[i + 3];
+            if (base + i < stride) *reinterpret_cast<int4 *>(row + base + i) = q;
+        }
         carry += tot;
     }
     if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
@@ -381,7 +431,7 @@ __global__ void __launch_bounds__(kScanThreads) radix_rowscan_kernel(int32_t *__
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__restrict__ keys_in,
         const int32_t *__restrict__ ids_in, K *__restrict__ keys_out, int32_t *__restrict__ ids_out,
-        int64_t M, const int64_t *__restrict__ count_dev, int shift, int bits, int nblocks,
+        int64_t M, const int64_t *__restrict__ count_dev, int shift, int bits, int nblocks, int stride,
         const int32_t *__restrict__ hist, const int32_t *__restrict__ digit_tot) {
     if (count_dev) M = min(M, *count_dev);
     __shared__ K s_keys[kSortTile];
@@ -393,11 +443,12 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__
     const uint32_t mask = (1u << bits) - 1u;
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
 
-    // global start of each digit's run for this block
+    // global start of each digit's run for this block (digits past 2^bits never occur)
     {
+        const bool used = t < (1 << bits);
         int32_t tot;
-        const int32_t before = block_exclusive_scan<int32_t>(digit_tot[t], tot);
-        s_gout[t] = before + hist[(int64_t)t * nblocks + blockIdx.x];
+        const int32_t before = block_exclusive_scan<int32_t>(used ? digit_tot[t] : 0, tot);
+        s_gout[t] = before + (used ? hist[(int64_t)t * stride + blockIdx.x] : 0);
     }
 #pragma unroll
     for (int k = 0; k < kSortWaves; k++) s_wcnt[k][t] = 0;
@@ -460,9 +511,12 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+int hist_stride(int64_t nb) { return (int)((nb + 3) & ~(int64_t)3); }
+
 size_t radix_ws_bytes(int64_t M) {
     const int64_t nb = (M + kSortTile - 1) / kSortTile;
-    return align256((size_t)kBins * (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)) + align256(kBins * sizeof(int32_t));
+    return align256((size_t)kBins * (size_t)hist_stride(nb > 0 ? nb : 1) * sizeof(int32_t)) +
+           align256(kBins * sizeof(int32_t));
 }
 
 // Sorts M pairs by the low key_bits bits; an even number of passes leaves
@@ -476,8 +530,9 @@ int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int3
     if (passes % 2) passes++;
     const int width = (key_bits + passes - 1) / passes;
     const int nb = (int)((M + kSortTile - 1) / kSortTile);
+    const int stride = hist_stride(nb);
     int32_t *hist = (int32_t *)ws;
-    int32_t *dtot = (int32_t *)((char *)ws + align256((size_t)kBins * nb * sizeof(int32_t)));
+    int32_t *dtot = (int32_t *)((char *)ws + align256((size_t)kBins * stride * sizeof(int32_t)));
     K *kin = keys, *kout = keys_alt;
     int32_t *iin = ids, *iout = ids_alt;
     for (int ps = 0; ps < passes; ps++) {
@@ -485,10 +540,10 @@ int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int3
         int bits = key_bits - shift;
         if (bits > width) bits = width;
         if (bits < 0) bits = 0;   // a padding pass: every digit 0, a stable copy
-        radix_hist_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, M, count_dev, shift, bits, nb, hist);
-        radix_rowscan_kernel<<<kBins, kScanThreads, 0, s>>>(hist, nb, dtot);
+        radix_hist_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, M, count_dev, shift, bits, nb, stride, hist);
+        radix_rowscan_kernel<<<1 << bits, kScanThreads, 0, s>>>(hist, nb, stride, dtot);
         radix_scatter_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, iin, kout, iout, M, count_dev, shift, bits, nb,
-                                                           hist, dtot);
+                                                           stride, hist, dtot);
         K *tk = kin; kin = kout; kout = tk;
         int32_t *ti = iin; iin = iout; iout = ti;
     }
