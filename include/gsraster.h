@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 2
+#define GSR_ABI_VERSION 3
 #define GSR_MAX_CAMERAS 64
 
 enum gsr_status {
@@ -77,7 +77,8 @@ enum gsr_op {
     GSR_OP_SORT = 2,              /* workspace of gsr_sort_pairs for M pairs          */
     GSR_OP_RASTERIZE = 3,         /* workspace of gsr_rasterize_fwd / _bwd, C*N       */
     GSR_OP_BIN_PREPARE = 4,       /* workspace kept from gsr_bin_prepare to _finish   */
-    GSR_OP_BIN_FINISH = 5         /* workspace of gsr_bin_finish for M intersections  */
+    GSR_OP_BIN_FINISH = 5,        /* workspace of gsr_bin_finish for M intersections  */
+    GSR_OP_PROJECT_BWD = 6        /* workspace of gsr_project_bwd with v_viewmats     */
 };
 
 /* Flags of gsr_rasterize_bwd. */
@@ -250,7 +251,15 @@ int gsr_rasterize_bwd(const gsr_params *p, int C, int N, const int32_t *W, const
  * v_conics, v_colors, v_opacities_cn [C,N] (from gsr_rasterize_bwd),
  * v_depths [C,N] (nullable).  Outputs, overwritten: v_means [N,3],
  * v_quats [N,4], v_scales [N,3], v_opacities [N], v_sh_or_colors (shape of
- * sh_or_colors). */
+ * sh_or_colors).
+ * v_viewmats [C,4,4] (nullable; pose gradient, the paper's view-matrix
+ * gradient read for world-to-camera matrices): with V = [R | t],
+ * t_cam = R mu + t, T = J R and camera centre -R^T t, per camera the sum
+ * over Gaussians of dL/dR = dL/dt_cam mu^T + J^T dL/dT + t g_dir^T and
+ * dL/dt = dL/dt_cam + R g_dir, g_dir being the mean gradient through the SH
+ * view direction; R is treated as a plain matrix; the last row is 0.  It
+ * needs ws of gsr_workspace_bytes(GSR_OP_PROJECT_BWD, C, N, 0) bytes
+ * (NULL and 0 when v_viewmats is NULL); its sums are deterministic. */
 int gsr_project_bwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
                     const float *means, const float *quats, const float *scales, const float *opacities,
                     const float *sh_or_colors, const float *viewmats, const float *Ks,
@@ -258,7 +267,8 @@ int gsr_project_bwd(const gsr_params *p, int C, int N, const int32_t *W, const i
                     const float *v_means2d, const float *v_conics, const float *v_colors,
                     const float *v_opacities_cn, const float *v_depths,
                     float *v_means, float *v_quats, float *v_scales, float *v_opacities,
-                    float *v_sh_or_colors, gsr_stream_t stream);
+                    float *v_sh_or_colors, float *v_viewmats, void *ws, size_t ws_bytes,
+                    gsr_stream_t stream);
 
 #ifdef __cplusplus
 }

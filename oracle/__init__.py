@@ -114,6 +114,12 @@ class Oracle:
         out["_abs"] = np.zeros((C, N, 9), self.dtype)
         return out["_abs"]
 
+    def _absgrad_buf(self, out, C, N, want):
+        if not want:
+            return None
+        out["v_means2d_abs"] = np.zeros((C, N, 2), self.dtype)
+        return out["v_means2d_abs"]
+
     @staticmethod
     def _split_abs(out, C, N):
         a = out.pop("_abs", None)
@@ -154,7 +160,9 @@ class Oracle:
         return out
 
     def project_bwd(self, P, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H,
-                    v_means2d, v_conics, v_colors, v_opacities_cn, v_depths=None):
+                    v_means2d, v_conics, v_colors, v_opacities_cn, v_depths=None, viewmat_grad=False):
+        """viewmat_grad: also return "v_viewmats" [C,4,4], the gradient with
+        respect to the world-to-camera matrices (last row zero)."""
         _p = _Keep()
         means, quats, scales, opacities = map(self._r, (means, quats, scales, opacities))
         shc, viewmats, Ks = map(self._r, (sh_or_colors, viewmats, Ks))
@@ -170,8 +178,14 @@ class Oracle:
                                  _p(opacities), _p(shc), _p(viewmats), _p(Ks), _p(v_means2d), _p(v_conics),
                                  _p(v_colors), _p(v_opacities_cn), _p(v_depths), _p(out["v_means"]),
                                  _p(out["v_quats"]), _p(out["v_scales"]), _p(out["v_opacities"]),
-                                 _p(out["v_sh"]))
+                                 _p(out["v_sh"]), _p(self._viewmat_buf(out, C, viewmat_grad)))
         return out
+
+    def _viewmat_buf(self, out, C, want):
+        if not want:
+            return None
+        out["v_viewmats"] = np.zeros((C, 4, 4), self.dtype)
+        return out["v_viewmats"]
 
     # -- tile binning and depth sort ---------------------------------------
     def intersect(self, P, proj, W, H, sort=True):
@@ -229,9 +243,11 @@ class Oracle:
         return out
 
     def rasterize_bwd(self, P, proj, opacities, ranges, ids, W, H, final_T, last_ids, v_image,
-                      v_alpha=None, background=None, tile_mask=None, abs_sums=False):
+                      v_alpha=None, background=None, tile_mask=None, abs_sums=False, absgrad=False):
         """abs_sums: also return "abs_<name>", per gradient element the sum of
-        the absolute values of its terms (the scale of float32 summation error)."""
+        the magnitudes of its terms (the scale of float32 summation error).
+        absgrad: also return "v_means2d_abs", per Gaussian the sum over
+        pixels of the absolute values of their mean-gradient contributions."""
         _p = _Keep()
         C, N = proj["radii"].shape
         Wa = _ints(np.broadcast_to(np.asarray(W), (C,)))
@@ -248,7 +264,7 @@ class Oracle:
                                    _p(tm), _p(self._r(final_T)), _p(np.ascontiguousarray(last_ids, np.int32)),
                                    _p(self._r(v_image)), _p(self._r(v_alpha)), _p(out["v_means2d"]),
                                    _p(out["v_conics"]), _p(out["v_colors"]), _p(out["v_opacities"]),
-                                   _p(self._abs_buf(out, C, N, abs_sums)))
+                                   _p(self._abs_buf(out, C, N, abs_sums)), _p(self._absgrad_buf(out, C, N, absgrad)))
         return self._split_abs(out, C, N)
 
     # -- the plain definition, tile by tile ---------------------------------
@@ -276,7 +292,7 @@ class Oracle:
         return out
 
     def render_tiles_bwd(self, P, proj, opacities, tiles, W, H, v_image, v_alpha=None, background=None,
-                         abs_sums=False):
+                         abs_sums=False, absgrad=False):
         _p = _Keep()
         C, N = proj["radii"].shape
         Wa = _ints(np.broadcast_to(np.asarray(W), (C,)))
@@ -293,7 +309,8 @@ class Oracle:
                                       _p(self._r(proj["depths"])), _p(self._r(background)),
                                       tiles.shape[0], _p(tiles), _p(self._r(v_image)), _p(self._r(v_alpha)),
                                       _p(out["v_means2d"]), _p(out["v_conics"]), _p(out["v_colors"]),
-                                      _p(out["v_opacities"]), _p(self._abs_buf(out, C, N, abs_sums)))
+                                      _p(out["v_opacities"]), _p(self._abs_buf(out, C, N, abs_sums)),
+                                      _p(self._absgrad_buf(out, C, N, absgrad)))
         return self._split_abs(out, C, N)
 
     def tile_list(self, P, proj, W, H, c, tx, ty):

@@ -550,7 +550,7 @@ static void composite_pixel(const scene2d_t *S, const int32_t *list, int len, RE
  * alpha gradient: sum over channels of |colour T_k| + |S / (1 - alpha)|
  * times |v_C|, plus |v_alpha final_T / (1 - alpha)|): the scale of the
  * rounding error any float32 evaluation and summation of the terms makes. */
-typedef struct { double *v_means2d, *v_conics, *v_colors, *v_opac, *abs; } grad2d_t;
+typedef struct { double *v_means2d, *v_conics, *v_colors, *v_opac, *abs, *v_means2d_abs; } grad2d_t;
 
 static void add_term(grad2d_t *G, double *dst, size_t g, int slot, double x, double mag)
 {
@@ -558,8 +558,9 @@ static void add_term(grad2d_t *G, double *dst, size_t g, int slot, double x, dou
     if (G->abs) G->abs[9 * g + (size_t)slot] += mag;
 }
 
-static void grad2d_alloc(grad2d_t *G, size_t CN, int want_abs)
+static void grad2d_alloc(grad2d_t *G, size_t CN, int want_abs, int want_absgrad)
 {
+    G->v_means2d_abs = want_absgrad ? (double *)calloc(2 * CN + 1, sizeof(double)) : NULL;
     G->v_means2d = (double *)calloc(2 * CN + 1, sizeof(double));
     G->v_conics = (double *)calloc(3 * CN + 1, sizeof(double));
     G->v_colors = (double *)calloc(3 * CN + 1, sizeof(double));
@@ -568,8 +569,11 @@ static void grad2d_alloc(grad2d_t *G, size_t CN, int want_abs)
 }
 
 static void grad2d_store(grad2d_t *G, size_t CN, REAL *v_means2d, REAL *v_conics, REAL *v_colors,
-                         REAL *v_opacities, REAL *abs_sums)
+                         REAL *v_opacities, REAL *abs_sums, REAL *v_means2d_abs)
 {
+    if (v_means2d_abs && G->v_means2d_abs)
+        for (size_t i = 0; i < 2 * CN; i++) v_means2d_abs[i] = (REAL)G->v_means2d_abs[i];
+    free(G->v_means2d_abs);
     for (size_t i = 0; i < 2 * CN; i++) v_means2d[i] = (REAL)G->v_means2d[i];
     for (size_t i = 0; i < 3 * CN; i++) { v_conics[i] = (REAL)G->v_conics[i]; v_colors[i] = (REAL)G->v_colors[i]; }
     for (size_t i = 0; i < CN; i++) v_opacities[i] = (REAL)G->v_opac[i];
@@ -618,10 +622,16 @@ static void composite_pixel_bwd(const scene2d_t *S, const int32_t *list, int las
         REAL v_sigma = -araw * v_alpha;
         double m_sigma = (double)araw * m_alpha;
         /* d sigma / d mu' = Y Delta with Delta = mu' - p; d sigma / d(a,b,c) */
-        add_term(G, &G->v_means2d[2 * (size_t)g], (size_t)g, 0, (double)(v_sigma * (a * dx + b * dy)),
+        REAL gx = v_sigma * (a * dx + b * dy), gy = v_sigma * (b * dx + c * dy);
+        add_term(G, &G->v_means2d[2 * (size_t)g], (size_t)g, 0, (double)gx,
                  m_sigma * (fabs((double)(a * dx)) + fabs((double)(b * dy))));
-        add_term(G, &G->v_means2d[2 * (size_t)g + 1], (size_t)g, 1, (double)(v_sigma * (b * dx + c * dy)),
+        add_term(G, &G->v_means2d[2 * (size_t)g + 1], (size_t)g, 1, (double)gy,
                  m_sigma * (fabs((double)(b * dx)) + fabs((double)(c * dy))));
+        /* absgrad (Absgrad): this pixel's contribution to the mean gradient, in absolute value */
+        if (G->v_means2d_abs) {
+            G->v_means2d_abs[2 * (size_t)g] += fabs((double)gx);
+            G->v_means2d_abs[2 * (size_t)g + 1] += fabs((double)gy);
+        }
         add_term(G, &G->v_conics[3 * (size_t)g], (size_t)g, 2, (double)(v_sigma * (K(0.5) * dx * dx)),
                  m_sigma * 0.5 * (double)(dx * dx));
         add_term(G, &G->v_conics[3 * (size_t)g + 1], (size_t)g, 3, (double)(v_sigma * (dx * dy)),
@@ -689,14 +699,15 @@ int orc_rasterize_bwd(const orc_params *P, int C, int N, const int *W, const int
                       const REAL *comps, const REAL *background, const int32_t *ranges, const int32_t *ids,
                       const uint8_t *tile_mask, const REAL *final_T, const int32_t *last_ids,
                       const REAL *v_image, const REAL *v_alpha,
-                      REAL *v_means2d, REAL *v_conics, REAL *v_colors, REAL *v_opacities, REAL *abs_sums)
+                      REAL *v_means2d, REAL *v_conics, REAL *v_colors, REAL *v_opacities, REAL *abs_sums,
+                      REAL *v_means2d_abs)
 {
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     camera_offsets(P, C, W, H, pix_off, tile_off);
     size_t CN = (size_t)C * N;
     grad2d_t G;
-    grad2d_alloc(&G, CN, abs_sums != NULL);
+    grad2d_alloc(&G, CN, abs_sums != NULL, v_means2d_abs != NULL);
     scene2d_t S = {P, N, means2d, conics, colors, opacities, comps};
     int ts = P->tile;
     for (int c = 0; c < C; c++) {
@@ -716,7 +727,7 @@ int orc_rasterize_bwd(const orc_params *P, int C, int N, const int *W, const int
                     }
             }
     }
-    grad2d_store(&G, CN, v_means2d, v_conics, v_colors, v_opacities, abs_sums);
+    grad2d_store(&G, CN, v_means2d, v_conics, v_colors, v_opacities, abs_sums, v_means2d_abs);
     free(pix_off); free(tile_off);
     return 0;
 }
@@ -817,7 +828,8 @@ int orc_render_tiles_bwd(const orc_params *P, int C, int N, const int *W, const 
                          const REAL *means2d, const REAL *conics, const REAL *colors, const REAL *opacities,
                          const REAL *comps, const int32_t *radii, const REAL *depths, const REAL *background,
                          int ntiles, const int32_t *tiles, const REAL *v_image, const REAL *v_alpha,
-                         REAL *v_means2d, REAL *v_conics, REAL *v_colors, REAL *v_opacities, REAL *abs_sums)
+                         REAL *v_means2d, REAL *v_conics, REAL *v_colors, REAL *v_opacities, REAL *abs_sums,
+                         REAL *v_means2d_abs)
 {
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
@@ -826,7 +838,7 @@ int orc_render_tiles_bwd(const orc_params *P, int C, int N, const int *W, const 
     did_t *tmp = (did_t *)malloc(sizeof(did_t) * (N > 0 ? N : 1));
     size_t CN = (size_t)C * N;
     grad2d_t G;
-    grad2d_alloc(&G, CN, abs_sums != NULL);
+    grad2d_alloc(&G, CN, abs_sums != NULL, v_means2d_abs != NULL);
     scene2d_t S = {P, N, means2d, conics, colors, opacities, comps};
     int ts = P->tile;
     for (int i = 0; i < ntiles; i++) {
@@ -844,7 +856,7 @@ int orc_render_tiles_bwd(const orc_params *P, int C, int N, const int *W, const 
                                     v_alpha ? v_alpha[p] : K(0), &G);
             }
     }
-    grad2d_store(&G, CN, v_means2d, v_conics, v_colors, v_opacities, abs_sums);
+    grad2d_store(&G, CN, v_means2d, v_conics, v_colors, v_opacities, abs_sums, v_means2d_abs);
     free(list); free(tmp); free(pix_off); free(tile_off);
     return 0;
 }
@@ -871,10 +883,13 @@ int orc_project_bwd(const orc_params *P, int C, int N, const int *W, const int *
                     const REAL *sh_or_colors, const REAL *viewmats, const REAL *Ks,
                     const REAL *v_means2d, const REAL *v_conics, const REAL *v_colors,
                     const REAL *v_opacities_cn, const REAL *v_depths,
-                    REAL *v_means, REAL *v_quats, REAL *v_scales, REAL *v_opacities, REAL *v_sh_or_colors)
+                    REAL *v_means, REAL *v_quats, REAL *v_scales, REAL *v_opacities, REAL *v_sh_or_colors,
+                    REAL *v_viewmats)
 {
     int nk = num_sh(P);
     int stride = nk > 0 ? 3 * nk : 3;
+    /* pose gradient: per camera, d L / d (R | t) of the world-to-camera matrix, summed over Gaussians */
+    double *vV = v_viewmats ? (double *)calloc((size_t)12 * (C > 0 ? C : 1), sizeof(double)) : NULL;
     for (int n = 0; n < N; n++) {
         double am[3] = {0, 0, 0}, aq[4] = {0, 0, 0, 0}, as[3] = {0, 0, 0}, ao = 0;
         double ash[48];
@@ -952,6 +967,7 @@ int orc_project_bwd(const orc_params *P, int C, int N, const int *W, const int *
             REAL vmu[3];
             matmul(3, 3, 1, RcwT, vt, vmu);
             (void)Rcw;
+            REAL gdir[3] = {K(0), K(0), K(0)};   /* dL/dmu through the SH view direction */
 
             /* Sigma = M M^T: dL/dM = 2 dL/dSigma M;  M = R S:
              * dL/dR = dL/dM S^T,  dL/ds_j = (R^T dL/dM)_jj */
@@ -998,16 +1014,43 @@ int orc_project_bwd(const orc_params *P, int C, int N, const int *W, const int *
                     }
                 /* dir = d / |d|, d = mu - campos */
                 REAL dd = (o.dir[0] * vdir[0] + o.dir[1] * vdir[1]) + o.dir[2] * vdir[2];
-                for (int j = 0; j < 3; j++) vmu[j] += (vdir[j] - o.dir[j] * dd) / o.dnorm;
+                for (int j = 0; j < 3; j++) {
+                    gdir[j] = (vdir[j] - o.dir[j] * dd) / o.dnorm;
+                    vmu[j] += gdir[j];
+                }
             } else {
                 for (int ch = 0; ch < 3; ch++) ash[ch] += (double)vc[ch];
             }
             for (int j = 0; j < 3; j++) am[j] += (double)vmu[j];
+            if (vV) {
+                /* t_cam = R mu + t:   dL/dR += vt mu^T,  dL/dt += vt;
+                 * T = J R:            dL/dR += J^T dL/dT;
+                 * centre = -R^T t (SH direction; dL/dcentre = -gdir):
+                 *                     dL/dR += t gdir^T,  dL/dt += R gdir. */
+                const REAL *mu = means + 3 * (size_t)n;
+                double *d = vV + 12 * (size_t)c;
+                for (int i = 0; i < 3; i++) {
+                    for (int j = 0; j < 3; j++) {
+                        double jt = 0.0;
+                        if (i == 0) jt = (double)o.J00 * vT[j];
+                        else if (i == 1) jt = (double)o.J11 * vT[3 + j];
+                        else jt = (double)o.J02 * vT[j] + (double)o.J12 * vT[3 + j];
+                        d[4 * i + j] += (double)vt[i] * mu[j] + jt + (double)V[4 * i + 3] * gdir[j];
+                    }
+                    d[4 * i + 3] += (double)vt[i] + ((double)V[4 * i] * gdir[0] + (double)V[4 * i + 1] * gdir[1]
+                                                     + (double)V[4 * i + 2] * gdir[2]);
+                }
+            }
         }
         for (int j = 0; j < 3; j++) { v_means[3 * (size_t)n + j] = (REAL)am[j]; v_scales[3 * (size_t)n + j] = (REAL)as[j]; }
         for (int j = 0; j < 4; j++) v_quats[4 * (size_t)n + j] = (REAL)aq[j];
         v_opacities[n] = (REAL)ao;
         for (int j = 0; j < stride; j++) v_sh_or_colors[(size_t)stride * n + j] = (REAL)ash[j];
+    }
+    if (vV) {
+        for (int c = 0; c < C; c++)
+            for (int e = 0; e < 16; e++) v_viewmats[16 * c + e] = e < 12 ? (REAL)vV[12 * c + e] : K(0);
+        free(vV);
     }
     return 0;
 }

@@ -16,9 +16,10 @@ LIB_PATH = os.path.join(_PKG, "libgsraster.so")
 
 GSR_OK, GSR_EINVAL, GSR_EOVERFLOW, GSR_EWORKSPACE, GSR_EHIP = 0, 1, 2, 3, 4
 GSR_OP_INTERSECT_COUNT, GSR_OP_SORT, GSR_OP_RASTERIZE, GSR_OP_BIN_PREPARE, GSR_OP_BIN_FINISH = 1, 2, 3, 4, 5
+GSR_OP_PROJECT_BWD = 6
 GSR_MAX_CAMERAS = 64
 GSR_BWD_ACCUMULATE, GSR_BWD_PACKED = 1, 2
-ABI_VERSION = 2                 # the signatures below
+ABI_VERSION = 3                 # the signatures below
 _NAMES = {0: "GSR_OK", 1: "GSR_EINVAL", 2: "GSR_EOVERFLOW", 3: "GSR_EWORKSPACE", 4: "GSR_EHIP"}
 
 
@@ -51,7 +52,7 @@ _SIGS = {
     "gsr_bin_finish": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp, _sz, _vp], _i),
     "gsr_rasterize_fwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 8 + [_vp] * 5 + [_vp, _sz, _vp], _i),
     "gsr_rasterize_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 12 + [_vp] * 5 + [_vp, _sz, _i, _vp], _i),
-    "gsr_project_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 9 + [_vp] * 5 + [_vp] * 5 + [_vp], _i),
+    "gsr_project_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 9 + [_vp] * 5 + [_vp] * 5 + [_vp, _vp, _sz, _vp], _i),
 }
 
 _lib = None
@@ -212,7 +213,7 @@ def gsr_rasterize_bwd(p, C, N, W, H, means2d, conics, colors, opacities, compens
 
 def gsr_project_bwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, radii,
                     compensations, v_means2d, v_conics, v_colors, v_opacities_cn, v_depths, v_means, v_quats,
-                    v_scales, v_opacities, v_sh_or_colors, stream=None):
+                    v_scales, v_opacities, v_sh_or_colors, v_viewmats=None, ws=None, stream=None):
     _check(lib().gsr_project_bwd(
         ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means, F32, "means"), _ptr(quats, F32, "quats"),
         _ptr(scales, F32, "scales"), _ptr(opacities, F32, "opacities"), _ptr(sh_or_colors, F32, "sh_or_colors"),
@@ -221,4 +222,5 @@ def gsr_project_bwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors
         _ptr(v_conics, F32, "v_conics"), _ptr(v_colors, F32, "v_colors"),
         _ptr(v_opacities_cn, F32, "v_opacities_cn"), _ptr(v_depths, F32, "v_depths"),
         _ptr(v_means, F32, "v_means"), _ptr(v_quats, F32, "v_quats"), _ptr(v_scales, F32, "v_scales"),
-        _ptr(v_opacities, F32, "v_opacities"), _ptr(v_sh_or_colors, F32, "v_sh_or_colors"), _stream(stream)))
+        _ptr(v_opacities, F32, "v_opacities"), _ptr(v_sh_or_colors, F32, "v_sh_or_colors"),
+        _ptr(v_viewmats, F32, "v_viewmats"), *_ws(ws), _stream(stream)))

@@ -109,6 +109,7 @@ size_t gsr_workspace_bytes(int op, int C, int N, int64_t M) {
         case GSR_OP_RASTERIZE: return pack_workspace_bytes((int64_t)(C > 0 ? C : 0) * (N > 0 ? N : 0));
         case GSR_OP_BIN_PREPARE: return bin_prepare_bytes((int64_t)(C > 0 ? C : 0) * (N > 0 ? N : 0));
         case GSR_OP_BIN_FINISH: return bin_finish_bytes(M > 0 ? M : 0);
+        case GSR_OP_PROJECT_BWD: return pose_workspace_bytes(C > 0 ? C : 0, N > 0 ? N : 0);
         default: return 0;
     }
 }
@@ -303,13 +304,15 @@ int gsr_project_bwd(const gsr_params *p, int C, int N, const int32_t *W, const i
                     const float *v_means2d, const float *v_conics, const float *v_colors,
                     const float *v_opacities_cn, const float *v_depths,
                     float *v_means, float *v_quats, float *v_scales, float *v_opacities,
-                    float *v_sh_or_colors, gsr_stream_t stream) {
+                    float *v_sh_or_colors, float *v_viewmats, void *ws, size_t ws_bytes, gsr_stream_t stream) {
     static const char *fn = "gsr_project_bwd";
     int rc = check_params(p);
     CamTable cams;
     if (rc == GSR_OK) rc = make_cams(C, N, W, H, cams);
     if (rc != GSR_OK) return rc;
-    if (N == 0) return GSR_OK;
+    if (N == 0)   // no Gaussians: the pose gradient is zero
+        return (v_viewmats && C > 0) ? launch_fill_zero(v_viewmats, (size_t)C * 16 * sizeof(float),
+                                                        (hipStream_t)stream) : GSR_OK;
     GSR_NEED(means); GSR_NEED(quats); GSR_NEED(scales); GSR_NEED(opacities); GSR_NEED(sh_or_colors);
     GSR_NEED(v_means); GSR_NEED(v_quats); GSR_NEED(v_scales); GSR_NEED(v_opacities); GSR_NEED(v_sh_or_colors);
     if (C > 0) {
@@ -317,9 +320,15 @@ int gsr_project_bwd(const gsr_params *p, int C, int N, const int32_t *W, const i
         GSR_NEED(v_means2d); GSR_NEED(v_conics); GSR_NEED(v_colors); GSR_NEED(v_opacities_cn);
         if (p->antialiased) GSR_NEED(compensations);
     }
+    if (v_viewmats && C > 0 && N > 0) {
+        const size_t need = pose_workspace_bytes(C, N);
+        if (!ws || ws_bytes < need)
+            return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed for v_viewmats, %zu given", fn, need,
+                        ws ? ws_bytes : 0);
+    }
     return launch_project_bwd(*p, cams, N, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, radii,
                               compensations, v_means2d, v_conics, v_colors, v_opacities_cn, v_depths, v_means,
-                              v_quats, v_scales, v_opacities, v_sh_or_colors, (hipStream_t)stream);
+                              v_quats, v_scales, v_opacities, v_sh_or_colors, v_viewmats, ws, (hipStream_t)stream);
 }
 
 }  // extern "C"

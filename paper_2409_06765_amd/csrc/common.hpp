@@ -43,7 +43,8 @@ int launch_project_bwd(const gsr_params &p, const CamTable &cams, int N, const f
                        const float *viewmats, const float *Ks, const int32_t *radii, const float *comps,
                        const float *v_means2d, const float *v_conics, const float *v_colors,
                        const float *v_opac_cn, const float *v_depths, float *v_means, float *v_quats,
-                       float *v_scales, float *v_opac, float *v_sh, hipStream_t s);
+                       float *v_scales, float *v_opac, float *v_sh, float *v_viewmats, void *ws, hipStream_t s);
+size_t pose_workspace_bytes(int C, int N);
 
 size_t count_workspace_bytes(int64_t n);
 int launch_intersect_count(const gsr_params &p, const CamTable &cams, int N, const float *means2d,

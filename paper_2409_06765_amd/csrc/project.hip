@@ -277,7 +277,11 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(gsr_params p, CamTable
     }
 }
 
-template <int NK>
+// kPose: also the gradient with respect to the world-to-camera matrices.  Per camera, each
+// (camera, Gaussian) contributes to the 12 entries of [R | t] (t_cam = R mu + t: vt mu^T and vt;
+// T = J R: J^T dL/dT; camera centre -R^T t of the SH direction: t gdir^T and R gdir, gdir being the
+// mean gradient through the direction); the sums over the block go to pose_part[block][c][12].
+template <int NK, bool kPose>
 __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable cams, int N,
         const float *__restrict__ means, const float *__restrict__ quats, const float *__restrict__ scales,
         const float *__restrict__ opacities, const float *__restrict__ shc, const float *__restrict__ viewmats,
@@ -285,9 +289,17 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
         const float *__restrict__ v_means2d, const float *__restrict__ v_conics,
         const float *__restrict__ v_colors, const float *__restrict__ v_opac_cn,
         const float *__restrict__ v_depths, float *__restrict__ v_means, float *__restrict__ v_quats,
-        float *__restrict__ v_scales, float *__restrict__ v_opac, float *__restrict__ v_sh) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+        float *__restrict__ v_scales, float *__restrict__ v_opac, float *__restrict__ v_sh,
+        float *__restrict__ pose_part) {
+    __shared__ float s_pose[kPose ? GSR_MAX_CAMERAS * 12 : 1];
+    const int n_raw = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = n_raw < N;
+    if (!kPose && !in) return;
+    const int n = in ? n_raw : 0;   // lanes past the end stay for the block's pose sums and add zero
+    if (kPose) {
+        for (int i = threadIdx.x; i < cams.C * 12; i += blockDim.x) s_pose[i] = 0.0f;
+        __syncthreads();
+    }
     const float mu[3] = {means[3 * n], means[3 * n + 1], means[3 * n + 2]};
     const float4 q4 = reinterpret_cast<const float4 *>(quats)[n];
     const float q[4] = {q4.x, q4.y, q4.z, q4.w};
@@ -300,14 +312,19 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
     float acc_o = 0.0f;
     bool have_coef = false;
     for (int c = 0; c < cams.C; c++) {
+        float pv[kPose ? 12 : 1];   // this Gaussian's share of dL/d[R | t] for camera c
+        if (kPose)
+            for (int k = 0; k < 12; k++) pv[k] = 0.0f;
+        do {
+        if (!in) break;
         const size_t g = (size_t)c * N + n;
-        if (radii[g] <= 0) continue;
+        if (radii[g] <= 0) break;
         const CamInfo ci = cams.cam[c];
         const float *V = viewmats + 16 * c;
         const float *Kc = Ks + 9 * c;
         Proj o;
         project_core(p, ci.W, ci.H, ci.TX, ci.TY, mu, q, s, V, Kc, o);
-        if (!o.valid) continue;
+        if (!o.valid) break;
         if (NK > 0 && !have_coef) {
             load_colour_coeffs<NK>(shc, n, coef);
             have_coef = true;
@@ -410,6 +427,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
         acc_q[3] += (gz - z * dq) / o.qnorm;
 
         // colour
+        float gdir[3] = {0.0f, 0.0f, 0.0f};   // mean gradient through the SH view direction
         const float vc[3] = {v_colors[3 * g], v_colors[3 * g + 1], v_colors[3 * g + 2]};
         if constexpr (NK > 0) {
             float cp[3], d[3];
@@ -437,18 +455,71 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
             float vdir[3] = {0.0f, 0.0f, 0.0f};
             sh_basis_grad<NK>(dir[0], dir[1], dir[2], wk, vdir);
             const float dd = (dir[0] * vdir[0] + dir[1] * vdir[1]) + dir[2] * vdir[2];
-            for (int j = 0; j < 3; j++) vmu[j] += (vdir[j] - dir[j] * dd) / dn;
+            for (int j = 0; j < 3; j++) {
+                gdir[j] = (vdir[j] - dir[j] * dd) / dn;
+                vmu[j] += gdir[j];
+            }
         } else {
             acc_sh[0] += vc[0]; acc_sh[1] += vc[1]; acc_sh[2] += vc[2];
         }
         for (int j = 0; j < 3; j++) acc_mu[j] += vmu[j];
-    }
-    for (int j = 0; j < 3; j++) { v_means[3 * n + j] = acc_mu[j]; v_scales[3 * n + j] = acc_s[j]; }
-    reinterpret_cast<float4 *>(v_quats)[n] = make_float4(acc_q[0], acc_q[1], acc_q[2], acc_q[3]);
-    v_opac[n] = acc_o;
-    float *dst = v_sh + (size_t)n * L;
+        if (kPose) {
+            for (int i = 0; i < 3; i++) {
+                for (int j = 0; j < 3; j++) {
+                    const float jt = i == 0 ? o.J00 * vT[0][j]
+                                   : i == 1 ? o.J11 * vT[1][j] : o.J02 * vT[0][j] + o.J12 * vT[1][j];
+                    pv[4 * i + j] = (vt[i] * mu[j] + jt) + V[4 * i + 3] * gdir[j];
+                }
+                pv[4 * i + 3] = vt[i] + ((V[4 * i] * gdir[0] + V[4 * i + 1] * gdir[1]) + V[4 * i + 2] * gdir[2]);
+            }
+        }
+        } while (0);
+        if (kPose) {
+            // wave sums with every lane active, then one LDS add per value and wave
 #pragma unroll
-    for (int i = 0; i < L; i++) dst[i] = acc_sh[i];
+            for (int k = 0; k < 12; k++) {
+                float v = pv[k];
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+                pv[k] = v;
+            }
+            if (__lane_id() == 0)
+                for (int k = 0; k < 12; k++) atomicAdd(&s_pose[c * 12 + k], pv[k]);
+        }
+    }
+    if (in) {
+        for (int j = 0; j < 3; j++) { v_means[3 * n + j] = acc_mu[j]; v_scales[3 * n + j] = acc_s[j]; }
+        reinterpret_cast<float4 *>(v_quats)[n] = make_float4(acc_q[0], acc_q[1], acc_q[2], acc_q[3]);
+        v_opac[n] = acc_o;
+        float *dst = v_sh + (size_t)n * L;
+#pragma unroll
+        for (int i = 0; i < L; i++) dst[i] = acc_sh[i];
+    }
+    if (kPose) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < cams.C * 12; i += blockDim.x)
+            pose_part[(size_t)blockIdx.x * cams.C * 12 + i] = s_pose[i];
+    }
+}
+
+// dL/dviewmats [C,4,4]: one block per (camera, entry of [R | t]) sums the per-block parts; the
+// last row is zero.
+__global__ void __launch_bounds__(256) pose_reduce_kernel(int nblocks, int C, const float *__restrict__ part,
+                                                         float *__restrict__ v_viewmats) {
+    __shared__ float red[256];
+    const int c = blockIdx.x / 12, k = blockIdx.x % 12;
+    float acc = 0.0f;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += part[((size_t)b * C + c) * 12 + k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        v_viewmats[16 * c + k] = red[0];
+        if (k < 4) v_viewmats[16 * c + 12 + k] = 0.0f;
+    }
 }
 
 int num_coeffs(int sh_degree) { return sh_degree < 0 ? 0 : (sh_degree + 1) * (sh_degree + 1); }
@@ -479,21 +550,31 @@ int launch_project_bwd(const gsr_params &p, const CamTable &cams, int N, const f
                        const float *viewmats, const float *Ks, const int32_t *radii, const float *comps,
                        const float *v_means2d, const float *v_conics, const float *v_colors,
                        const float *v_opac_cn, const float *v_depths, float *v_means, float *v_quats,
-                       float *v_scales, float *v_opac, float *v_sh, hipStream_t s) {
+                       float *v_scales, float *v_opac, float *v_sh, float *v_viewmats, void *ws, hipStream_t s) {
+    const int nb = (N + 255) / 256;
     if (N == 0) return GSR_OK;
-    dim3 block(256), grid((N + 255) / 256);
-#define GSR_PB(NK) project_bwd_kernel<NK><<<grid, block, 0, s>>>(p, cams, N, means, quats, scales, opacities, \
-        sh, viewmats, Ks, radii, comps, v_means2d, v_conics, v_colors, v_opac_cn, v_depths, v_means, v_quats, \
-        v_scales, v_opac, v_sh)
+    dim3 block(256), grid((unsigned)nb);
+    float *part = (float *)ws;
+#define GSR_PB(NK, POSE) project_bwd_kernel<NK, POSE><<<grid, block, 0, s>>>(p, cams, N, means, quats, scales, \
+        opacities, sh, viewmats, Ks, radii, comps, v_means2d, v_conics, v_colors, v_opac_cn, v_depths, v_means, \
+        v_quats, v_scales, v_opac, v_sh, part)
+#define GSR_PB2(NK) if (v_viewmats) GSR_PB(NK, true); else GSR_PB(NK, false)
     switch (num_coeffs(p.sh_degree)) {
-        case 0: GSR_PB(0); break;
-        case 1: GSR_PB(1); break;
-        case 4: GSR_PB(4); break;
-        case 9: GSR_PB(9); break;
-        default: GSR_PB(16); break;
+        case 0: GSR_PB2(0); break;
+        case 1: GSR_PB2(1); break;
+        case 4: GSR_PB2(4); break;
+        case 9: GSR_PB2(9); break;
+        default: GSR_PB2(16); break;
     }
+#undef GSR_PB2
 #undef GSR_PB
+    if (v_viewmats && cams.C > 0)
+        pose_reduce_kernel<<<dim3((unsigned)(cams.C * 12)), dim3(256), 0, s>>>(nb, cams.C, part, v_viewmats);
     return launch_check("project_bwd");
+}
+
+size_t pose_workspace_bytes(int C, int N) {
+    return (size_t)((N + 255) / 256) * (size_t)(C > 0 ? C : 1) * 12 * sizeof(float);
 }
 
 }  // namespace gsr

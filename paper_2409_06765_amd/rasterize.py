@@ -246,14 +246,20 @@ def rasterize_backward(p, proj, opacities, isect, W, H, fwd, v_image, v_alpha=No
 
 
 def project_backward(p, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H, proj, g2,
-                     v_depths=None, stream=None):
+                     v_depths=None, viewmat_grad=False, stream=None):
+    """Gradients of the projection; ``viewmat_grad`` adds "v_viewmats" [C,4,4]."""
     C, N = viewmats.shape[0], means.shape[0]
+    d = means.device
     out = dict(v_means=torch.empty_like(means), v_quats=torch.empty_like(quats), v_scales=torch.empty_like(scales),
-               v_opacities=torch.empty_like(opacities), v_sh=torch.empty_like(sh_or_colors))
+               v_opacities=torch.empty_like(opacities), v_sh=torch.empty_like(sh_or_colors),
+               v_viewmats=torch.empty((C, 4, 4), device=d, dtype=torch.float32) if viewmat_grad else None)
+    ws = None
+    if viewmat_grad:
+        ws = torch.empty(max(L.workspace_bytes(L.GSR_OP_PROJECT_BWD, C, N, 0), 1), device=d, dtype=torch.uint8)
     L.gsr_project_bwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, proj["radii"],
                       proj["comps"], g2["v_means2d"], g2["v_conics"], g2["v_colors"], g2["v_opacities"], v_depths,
                       out["v_means"], out["v_quats"], out["v_scales"], out["v_opacities"], out["v_sh"],
-                      stream=stream)
+                      v_viewmats=out["v_viewmats"], ws=ws, stream=stream)
     return out
 
 
@@ -264,8 +270,9 @@ class RasterizeGaussians(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, background, p, W, H, absgrad,
                 meta):
-        means, quats, scales, opacities, sh_or_colors = (t.contiguous() for t in
-                                                         (means, quats, scales, opacities, sh_or_colors))
+        means, quats, scales, opacities, sh_or_colors, viewmats = (t.contiguous() for t in
+                                                                   (means, quats, scales, opacities, sh_or_colors,
+                                                                    viewmats))
         proj = project(p, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H)
         isect = intersect(p, proj, W, H)
         fwd = rasterize_forward(p, proj, opacities, isect, W, H, background)
@@ -290,9 +297,11 @@ class RasterizeGaussians(torch.autograd.Function):
                                 absgrad=ctx.absgrad)
         if ctx.absgrad:
             ctx.meta["means2d_absgrad"] = g2["v_means2d_abs"]
-        g3 = project_backward(p, means, quats, scales, opacities, sh, viewmats, Ks, W, H, ctx.proj, g2)
+        want_vm = ctx.needs_input_grad[5]
+        g3 = project_backward(p, means, quats, scales, opacities, sh, viewmats, Ks, W, H, ctx.proj, g2,
+                              viewmat_grad=want_vm)
         return (g3["v_means"], g3["v_quats"], g3["v_scales"], g3["v_opacities"], g3["v_sh"],
-                None, None, None, None, None, None, None, None)
+                g3["v_viewmats"] if want_vm else None, None, None, None, None, None, None, None)
 
 
 def rasterization(means, quats, scales, opacities, colors, viewmats, Ks, width, height, sh_degree=None,

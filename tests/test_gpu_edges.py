@@ -17,6 +17,25 @@ def _say(msg):
     print(f"[gpu-edges] {msg}", flush=True)
 
 
+def test_pose_gradient_of_an_empty_scene_is_zero():
+    from _gpu import np_, params, scene_to_dev, to_dev
+    from paper_2409_06765_amd import rasterize as R
+    sc = scenes.scene_tiny(0)
+    cams = scenes.cams_tiny(W=40, H=30, n_cams=2, seed=3)
+    d = scene_to_dev(sc)
+    p = params()
+    W, H = [int(w) for w in cams["W"]], [int(h) for h in cams["H"]]
+    vm, Ks = to_dev(cams["viewmats"]), to_dev(cams["Ks"])
+    proj = R.project(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, W, H)
+    z = torch.zeros((2, 0, 3), device="cuda")
+    g2 = dict(v_means2d=torch.zeros((2, 0, 2), device="cuda"), v_conics=z, v_colors=z,
+              v_opacities=torch.zeros((2, 0), device="cuda"))
+    g3 = R.project_backward(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, W, H, proj, g2,
+                            viewmat_grad=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(np_(g3["v_viewmats"]), 0.0)
+
+
 def test_empty_scene_renders_background():
     from _gpu import gpu_forward, np_, params
     _say("empty scene")

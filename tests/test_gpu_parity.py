@@ -120,10 +120,10 @@ def test_rasterize_backward_and_projection_backward(case):
     # pixels whose decisions sit on a threshold get no upstream gradient on either side
     v_image[ras["flags"] != 0] = 0
     v_alpha[ras["flags"] != 0] = 0
-    g2, g3 = gpu_backward(p, st, v_image, v_alpha)
+    g2, g3 = gpu_backward(p, st, v_image, v_alpha, absgrad=True)
     o2 = O32.rasterize_bwd(P, proj, sc["opacities"], isect["ranges"], isect["ids"], cams["W"], cams["H"],
-                           ras["final_T"], ras["last_ids"], v_image, v_alpha, background=bg)
-    for k in ("v_means2d", "v_conics", "v_colors", "v_opacities"):
+                           ras["final_T"], ras["last_ids"], v_image, v_alpha, background=bg, absgrad=True)
+    for k in ("v_means2d", "v_conics", "v_colors", "v_opacities", "v_means2d_abs"):
         assert_grad_close(np_(g2[k]), o2[k], f"{name}:{k}")
     # projection backward: both sides from the same (oracle) upstream gradients
     o3 = O32.project_bwd(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],

@@ -1,7 +1,8 @@
 """Projection backward term by term: one upstream gradient at a time (2D
 means, conics, colours through the SH direction, opacities with the
 anti-aliasing compensation) on Gaussians near the camera, inside and outside
-the Jacobian clamp, with strong higher SH bands.  The GPU result is judged
+the Jacobian clamp, with strong higher SH bands; the pose (view-matrix)
+gradient with them.  The GPU result is judged
 against the float64 oracle fed the same upstream gradients, allowing a few
 times the float32 oracle's own distance from it."""
 import numpy as np
@@ -43,15 +44,18 @@ def test_projection_backward_one_term_at_a_time(which, aa):
         if which not in (k, "all"):
             up[k][:] = 0
         up[k] = (up[k] * vis.reshape(C, N, *([1] * (up[k].ndim - 2)))).astype(np.float32)
-    ref32 = O32.project_bwd(P, *args, up["v_means2d"], up["v_conics"], up["v_colors"], up["v_opacities"])
-    ref64 = O64.project_bwd(P, *args, up["v_means2d"], up["v_conics"], up["v_colors"], up["v_opacities"])
+    ref32 = O32.project_bwd(P, *args, up["v_means2d"], up["v_conics"], up["v_colors"], up["v_opacities"],
+                            viewmat_grad=True)
+    ref64 = O64.project_bwd(P, *args, up["v_means2d"], up["v_conics"], up["v_colors"], up["v_opacities"],
+                            viewmat_grad=True)
     d = scene_to_dev(sc)
     vm, Ks = to_dev(cams["viewmats"]), to_dev(cams["Ks"])
     W, H = [int(w) for w in cams["W"]], [int(h) for h in cams["H"]]
     gproj = R.project(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, W, H)
     np.testing.assert_array_equal(np_(gproj["radii"]), proj["radii"])
     g2 = {k: to_dev(v) for k, v in up.items()}
-    g3 = R.project_backward(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, W, H, gproj, g2)
+    g3 = R.project_backward(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, W, H, gproj, g2,
+                            viewmat_grad=True)
     torch.cuda.synchronize()
-    for k in ("v_means", "v_quats", "v_scales", "v_opacities", "v_sh"):
+    for k in ("v_means", "v_quats", "v_scales", "v_opacities", "v_sh", "v_viewmats"):
         assert_as_accurate_as_f32(np_(g3[k]), ref32[k], ref64[k], f"{which}:{k}")

@@ -268,3 +268,53 @@ def test_projection_gradients_match_central_differences(deg, aa, jc, wide):
             assert abs(fd - an) <= 1e-5 * max(1.0, abs(fd)), (key, i, fd, an)
             checked += 1
     assert checked > (40 if wide else 60)
+
+
+@pytest.mark.parametrize("deg,aa,wide", [(3, 0, False), (2, 1, True), (-1, 0, True)])
+def test_viewmat_gradient_matches_central_differences(deg, aa, wide):
+    """Pose gradient: dL/d(viewmat) for the world-to-camera matrices (the
+    3 x 4 block [R | t]; R taken as a plain matrix, as the projection uses it:
+    t_cam = R mu + t, T = J R, camera centre -R^T t) against float64 central
+    differences of the same projection loss, including Gaussians past the
+    Jacobian clamp (wide) and the SH view direction."""
+    P = OracleParams(sh_degree=deg, antialiased=aa)
+    if wide:
+        sc = wide_cone_scene(48, seed=17, sh_degree=deg)
+        cams = scenes.cams_tiny(W=120, H=90, f=80.0)
+    else:
+        sc = scenes.scene_tiny(30, sh_degree=deg, seed=15, log_scale_mean=-2.0)
+        cams = scenes.cams_tiny(W=80, H=60, f=60.0, n_cams=2, seed=15)
+    sc = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    cams = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) and v.dtype.kind == "f" else v)
+            for k, v in cams.items()}
+    C, N = cams["viewmats"].shape[0], sc["means"].shape[0]
+    g = np.random.default_rng(18)
+    w = dict(m=g.standard_normal((C, N, 2)), c=g.standard_normal((C, N, 3)) * 10,
+             col=g.standard_normal((C, N, 3)), d=g.standard_normal((C, N)), o=g.standard_normal((C, N)))
+    L0, p0 = _proj_loss(P, sc, cams, w)
+    gr = O64.project_bwd(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],
+                         cams["Ks"], cams["W"], cams["H"], w["m"], w["c"], w["col"], w["o"], v_depths=w["d"],
+                         viewmat_grad=True)
+    np.testing.assert_array_equal(gr["v_viewmats"][:, 3, :], 0.0)
+    checked = 0
+    for c in range(C):
+        for i in range(3):
+            for j in range(4):
+                V = cams["viewmats"]
+                orig = V[c, i, j]
+                eps = 1e-6 * max(1.0, abs(orig))
+                V[c, i, j] = orig + eps
+                Lp, pp = _proj_loss(P, sc, cams, w)
+                V[c, i, j] = orig - eps
+                Lm, pm = _proj_loss(P, sc, cams, w)
+                V[c, i, j] = orig
+                if not (np.array_equal(pp["radii"], p0["radii"]) and np.array_equal(pm["radii"], p0["radii"])):
+                    continue
+                if not (np.array_equal(pp["colors"] == 0, p0["colors"] == 0)
+                        and np.array_equal(pm["colors"] == 0, p0["colors"] == 0)):
+                    continue
+                fd = (Lp - Lm) / (2 * eps)
+                an = gr["v_viewmats"][c, i, j]
+                assert abs(fd - an) <= 2e-5 * max(1.0, abs(fd)), (c, i, j, fd, an)
+                checked += 1
+    assert checked >= 10 * C
