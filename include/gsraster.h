@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 3
+#define GSR_ABI_VERSION 4
 #define GSR_MAX_CAMERAS 64
 
 enum gsr_status {
@@ -68,7 +68,19 @@ typedef struct gsr_params {
     int32_t tile;       /* tile edge in pixels; must be 16                              */
     int32_t sh_degree;  /* -1: direct colours [N,3]; 0..3: SH coefficients [N,(d+1)^2,3] */
     int32_t antialiased;/* 1: opacity times sqrt(|Sigma'| / |Sigma' + eps2d I|)         */
+    int32_t render_depth;  /* gsr_depth_mode: composite the depth t_z as a last channel */
+    int32_t colors_shared; /* rasterizer colours [N,D] shared by all cameras, not [C,N,D] */
 } gsr_params;
+
+/* Depth rendering (Depth rendering appendix): the camera-space depth t_z of
+ * every Gaussian composited as one more channel after the D features, with
+ * no background; EXPECTED divides it by the sum of alpha T at the pixel
+ * (0 where that sum is 0). */
+enum gsr_depth_mode {
+    GSR_DEPTH_NONE = 0,
+    GSR_DEPTH_ACCUMULATED = 1,
+    GSR_DEPTH_EXPECTED = 2
+};
 
 typedef void *gsr_stream_t;   /* a hipStream_t */
 
@@ -110,7 +122,9 @@ size_t gsr_workspace_bytes(int op, int C, int N, int64_t M);
  * positive definite or its tile rectangle misses the image.
  * Outputs: means2d [C,N,2], conics [C,N,3], radii [C,N] int32, depths [C,N],
  * colors [C,N,3], compensations [C,N] (nullable; 1 unless antialiased).
- * opacities [N] is not read (kept for a uniform argument list). */
+ * With sh_degree = -1, colors may be NULL (and sh_or_colors then too): no
+ * colour is written, for callers that hand the rasterizer features of their
+ * own.  opacities [N] is not read (kept for a uniform argument list). */
 int gsr_project_fwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
                     const float *means, const float *quats, const float *scales, const float *opacities,
                     const float *sh_or_colors, const float *viewmats, const float *Ks,
@@ -190,15 +204,24 @@ int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const in
  *   alpha = min(alpha_max, o exp(-sigma)) with o = opacities[n] (times
  *   compensations[c*N+n] when antialiased); skipped if alpha < alpha_min;
  *   T' = T (1 - alpha); if T' < T_min the pixel stops here, without this one;
- *   otherwise C += colour alpha T, T = T'.
- * Finally C += T background[c] (background [C,3], NULL = black).
- * Outputs: image [P,3], alpha [P] = 1 - T, final_T [P] = T, last_ids [P] int32
+ *   otherwise C += f alpha T, T = T'.
+ * Finally C += T background[c] on the feature channels (background [C,D],
+ * NULL = zero).
+ * Channels: D (0 .. 32) features f from colors, [C,N,D] ([N,D] shared by
+ * all cameras when p->colors_shared; NULL when D = 0), then, when
+ * p->render_depth is set, the depth t_z from depths [C,N] as channel D (Depth
+ * rendering appendix; GSR_DEPTH_EXPECTED divides it by the sum of alpha T, 0
+ * where nothing was composited).  Dt = D (+1 with depth) is 1 .. 32.  Every
+ * channel takes the same alpha and T, so channels are independent.  Plain RGB
+ * (D = 3, no depth) is the fastest case: the colours travel in the
+ * per-Gaussian record; other channel sets are staged in LDS per batch.
+ * Outputs: image [P,Dt], alpha [P] = 1 - T, final_T [P] = T, last_ids [P] int32
  * (position in the sorted list of the last composited entry, -1 if none),
  * n_eval [P,2] int32 (nullable): per pixel, the entries evaluated (including
  * the one that stopped it) and the entries composited.
  * ws: workspace of gsr_workspace_bytes(GSR_OP_RASTERIZE, C, N, 0). */
-int gsr_rasterize_fwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
-                      const float *means2d, const float *conics, const float *colors,
+int gsr_rasterize_fwd(const gsr_params *p, int C, int N, int D, const int32_t *W, const int32_t *H,
+                      const float *means2d, const float *conics, const float *colors, const float *depths,
                       const float *opacities, const float *compensations, const float *background,
                       const int32_t *ranges, const int32_t *ids, float *image, float *alpha,
                       float *final_T, int32_t *last_ids, int32_t *n_eval, void *ws, size_t ws_bytes,
@@ -206,20 +229,25 @@ int gsr_rasterize_fwd(const gsr_params *p, int C, int N, const int32_t *W, const
 
 /* Depth Compositing Gradients.  Per pixel, from last_ids back to its tile's
  * start, recomputes alpha, restores T_k = T_{k+1} / (1 - alpha_k) from final_T,
- * keeps S = sum of colour alpha T behind entry k plus final_T background, and
+ * keeps S = sum of f alpha T behind entry k plus final_T background, and
  * accumulates
- *   dL/dcolour += alpha T v_C;
- *   dL/dalpha = sum_ch (colour T - S/(1 - alpha)) v_C + v_alpha final_T/(1 - alpha);
+ *   dL/df += alpha T v_C;
+ *   dL/dalpha = sum_ch (f T - S/(1 - alpha)) v_C + v_alpha final_T/(1 - alpha);
  *   unless alpha was clamped at alpha_max:
  *     dL/do += exp(-sigma) dL/dalpha,  dL/dsigma = -o exp(-sigma) dL/dalpha,
  *     dL/dmu' += dL/dsigma Sigma'^-1 Delta,
  *     dL/d(a, b, c) += dL/dsigma (Dx^2/2, Dx Dy, Dy^2/2).
- * v_image [P,3], v_alpha [P] (nullable).  Outputs, overwritten: v_means2d
- * [C,N,2], v_conics [C,N,3], v_colors [C,N,3], v_opacities [C,N] (gradient
- * with respect to the opacity the rasterizer used, o times compensation),
- * v_means2d_abs [C,N,2] (nullable: per-pixel absolute values of the mu'
- * gradient summed, the absgrad statistic).  Sums use float atomics, so their
- * rounding order is not fixed.
+ * Expected depth E = A / W (A the composited depth, W = sum alpha T = 1 -
+ * final_T) passes v_E / W on to A and -v_E E / W to the alpha output; image
+ * (the forward's output, [P,Dt]) supplies E and is read only in that mode.
+ * Channels, p, D, colors and depths as in gsr_rasterize_fwd.  v_image
+ * [P,Dt], v_alpha [P] (nullable).  Outputs, overwritten: v_means2d [C,N,2],
+ * v_conics [C,N,3], v_colors (shape of colors; NULL when D = 0), v_depths
+ * [C,N] (depth channel; NULL unless depth is rendered), v_opacities [C,N]
+ * (gradient with respect to the opacity the rasterizer used, o times
+ * compensation), v_means2d_abs [C,N,2] (nullable: per-pixel absolute values
+ * of the mu' gradient summed, the absgrad statistic).  Sums use float
+ * atomics, so their rounding order is not fixed.
  * ws: workspace of gsr_workspace_bytes(GSR_OP_RASTERIZE, C, N, 0).
  * flags (bitwise or; 0 = overwrite the outputs and pack the records anew):
  *   GSR_BWD_ACCUMULATE  add into the outputs instead of overwriting them
@@ -229,12 +257,12 @@ int gsr_rasterize_fwd(const gsr_params *p, int C, int N, const int32_t *W, const
  *                       means2d, conics, colors, opacities, compensations and
  *                       params (not rewritten since), so they are not packed
  *                       again; with other contents the gradients are wrong. */
-int gsr_rasterize_bwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
-                      const float *means2d, const float *conics, const float *colors,
+int gsr_rasterize_bwd(const gsr_params *p, int C, int N, int D, const int32_t *W, const int32_t *H,
+                      const float *means2d, const float *conics, const float *colors, const float *depths,
                       const float *opacities, const float *compensations, const float *background,
-                      const int32_t *ranges, const int32_t *ids, const float *final_T,
+                      const int32_t *ranges, const int32_t *ids, const float *image, const float *final_T,
                       const int32_t *last_ids, const float *v_image, const float *v_alpha,
-                      float *v_means2d, float *v_conics, float *v_colors, float *v_opacities,
+                      float *v_means2d, float *v_conics, float *v_colors, float *v_depths, float *v_opacities,
                       float *v_means2d_abs, void *ws, size_t ws_bytes, int flags, gsr_stream_t stream);
 
 /* Projection Gradients, Scale and rotation gradients, SH backward.  Per
@@ -251,7 +279,8 @@ int gsr_rasterize_bwd(const gsr_params *p, int C, int N, const int32_t *W, const
  * v_conics, v_colors, v_opacities_cn [C,N] (from gsr_rasterize_bwd),
  * v_depths [C,N] (nullable).  Outputs, overwritten: v_means [N,3],
  * v_quats [N,4], v_scales [N,3], v_opacities [N], v_sh_or_colors (shape of
- * sh_or_colors).
+ * sh_or_colors).  With sh_degree = -1, v_colors may be NULL (and
+ * sh_or_colors, v_sh_or_colors then too): the colours are not differentiated.
  * v_viewmats [C,4,4] (nullable; pose gradient, the paper's view-matrix
  * gradient read for world-to-camera matrices): with V = [R | t],
  * t_cam = R mu + t, T = J R and camera centre -R^T t, per camera the sum

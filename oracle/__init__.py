@@ -86,6 +86,11 @@ class _Keep:
         return ctypes.c_void_p(a.ctypes.data)
 
 
+def _nch(proj):
+    """Feature channels D of the projected colours [C, N, D]."""
+    return int(np.asarray(proj["colors"]).shape[-1])
+
+
 def _ints(xs):
     a = np.ascontiguousarray(np.asarray(xs, dtype=np.int32))
     return a
@@ -111,7 +116,7 @@ class Oracle:
     def _abs_buf(self, out, C, N, want):
         if not want:
             return None
-        out["_abs"] = np.zeros((C, N, 9), self.dtype)
+        out["_abs"] = np.zeros((C, N, 6 + out["v_colors"].shape[-1]), self.dtype)
         return out["_abs"]
 
     def _absgrad_buf(self, out, C, N, want):
@@ -124,8 +129,8 @@ class Oracle:
     def _split_abs(out, C, N):
         a = out.pop("_abs", None)
         if a is not None:
-            out.update(abs_v_means2d=a[..., 0:2], abs_v_conics=a[..., 2:5], abs_v_colors=a[..., 5:8],
-                       abs_v_opacities=a[..., 8])
+            out.update(abs_v_means2d=a[..., 0:2], abs_v_conics=a[..., 2:5], abs_v_opacities=a[..., 5],
+                       abs_v_colors=a[..., 6:])
         return out
 
     def _r(self, a):
@@ -216,10 +221,10 @@ class Oracle:
         return out
 
     # -- Rasterization of Gaussians ----------------------------------------
-    def _pixbufs(self, Wa, Ha):
+    def _pixbufs(self, Wa, Ha, D=3):
         npix = int(np.sum(Wa.astype(np.int64) * Ha))
         dt = self.dtype
-        return dict(image=np.zeros((npix, 3), dt), alpha=np.zeros(npix, dt), final_T=np.zeros(npix, dt),
+        return dict(image=np.zeros((npix, D), dt), alpha=np.zeros(npix, dt), final_T=np.zeros(npix, dt),
                     n_eval=np.zeros(npix, np.int32), n_comp=np.zeros(npix, np.int32),
                     flags=np.zeros(npix, np.uint8),
                     trace=np.zeros(npix, np.uint32))
@@ -229,11 +234,11 @@ class Oracle:
         C, N = proj["radii"].shape
         Wa = _ints(np.broadcast_to(np.asarray(W), (C,)))
         Ha = _ints(np.broadcast_to(np.asarray(H), (C,)))
-        out = self._pixbufs(Wa, Ha)
+        out = self._pixbufs(Wa, Ha, _nch(proj))
         out["last_ids"] = np.full(out["alpha"].shape, -1, np.int32)
         comps = self._r(proj["comps"]) if P.antialiased else None
         tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, dtype=np.uint8)
-        self.lib.orc_rasterize_fwd(self._cp(P), C, N, _p(Wa), _p(Ha), _p(self._r(proj["means2d"])),
+        self.lib.orc_rasterize_fwd(self._cp(P), C, N, _nch(proj), _p(Wa), _p(Ha), _p(self._r(proj["means2d"])),
                                    _p(self._r(proj["conics"])), _p(self._r(proj["colors"])),
                                    _p(self._r(opacities)), _p(comps), _p(self._r(background)),
                                    _p(np.ascontiguousarray(ranges, np.int32)), _p(np.ascontiguousarray(ids, np.int32)),
@@ -254,10 +259,10 @@ class Oracle:
         Ha = _ints(np.broadcast_to(np.asarray(H), (C,)))
         dt = self.dtype
         out = dict(v_means2d=np.zeros((C, N, 2), dt), v_conics=np.zeros((C, N, 3), dt),
-                   v_colors=np.zeros((C, N, 3), dt), v_opacities=np.zeros((C, N), dt))
+                   v_colors=np.zeros((C, N, _nch(proj)), dt), v_opacities=np.zeros((C, N), dt))
         comps = self._r(proj["comps"]) if P.antialiased else None
         tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, dtype=np.uint8)
-        self.lib.orc_rasterize_bwd(self._cp(P), C, N, _p(Wa), _p(Ha), _p(self._r(proj["means2d"])),
+        self.lib.orc_rasterize_bwd(self._cp(P), C, N, _nch(proj), _p(Wa), _p(Ha), _p(self._r(proj["means2d"])),
                                    _p(self._r(proj["conics"])), _p(self._r(proj["colors"])),
                                    _p(self._r(opacities)), _p(comps), _p(self._r(background)),
                                    _p(np.ascontiguousarray(ranges, np.int32)), _p(np.ascontiguousarray(ids, np.int32)),
@@ -267,6 +272,92 @@ class Oracle:
                                    _p(self._abs_buf(out, C, N, abs_sums)), _p(self._absgrad_buf(out, C, N, absgrad)))
         return self._split_abs(out, C, N)
 
+    # -- N-D features and depth rendering -----------------------------------
+    def _channels(self, proj, features, depth):
+        """The per-Gaussian channels the definitions composite: the features
+        ([C,N,D], or [N,D] shared by every camera; None = the projected
+        colours), then the depth z (accumulated or expected depth), then a
+        channel of ones for expected depth, whose composite is the sum of
+        alpha T (Depth rendering appendix).  Returns (channels [C,N,D+e], D,
+        shared, e)."""
+        C, N = proj["radii"].shape
+        F = proj["colors"] if features is None else features
+        F = np.asarray(F, dtype=self.dtype)
+        shared = F.ndim == 2
+        F = np.broadcast_to(F, (C, N, F.shape[-1])) if shared else F
+        D = F.shape[-1]
+        if depth not in ("none", "accumulated", "expected"):
+            raise ValueError(depth)
+        extra = []
+        if depth != "none":
+            extra.append(np.asarray(proj["depths"], self.dtype)[..., None])
+        if depth == "expected":
+            extra.append(np.ones((C, N, 1), self.dtype))
+        return np.ascontiguousarray(np.concatenate([F] + extra, axis=-1)), D, shared, len(extra)
+
+    @staticmethod
+    def _bg_channels(background, C, D, e):
+        if background is None:
+            return None
+        bg = np.asarray(background, dtype=np.float64).reshape(C, D)
+        return np.concatenate([bg, np.zeros((C, e))], axis=1)    # depth has no background
+
+    def channels_fwd(self, P, proj, opacities, ranges, ids, W, H, features=None, depth="none",
+                     background=None):
+        """Compositing of D feature channels, plus the depth channel:
+        "accumulated" is the sum of z alpha T; "expected" divides it by the
+        sum of alpha T (0 where nothing is composited).  Returns the
+        rasterize_fwd outputs with image [P, D (+1)], and "weight" (the sum of
+        alpha T, composited as a channel of ones) for expected depth."""
+        C, N = proj["radii"].shape
+        ch, D, shared, e = self._channels(proj, features, depth)
+        out = self.rasterize_fwd(P, dict(proj, colors=ch), opacities, ranges, ids, W, H,
+                                 background=self._bg_channels(background, C, D, e))
+        if depth == "expected":
+            A, Wt = out["image"][:, D], out["image"][:, D + 1]
+            pos = Wt > 0
+            E = np.zeros_like(A)
+            E[pos] = A[pos] / Wt[pos]
+            out["image"] = np.ascontiguousarray(np.concatenate([out["image"][:, :D], E[:, None]], axis=1))
+            out["weight"] = Wt
+        return out
+
+    def channels_bwd(self, P, proj, opacities, ranges, ids, W, H, fwd, v_image, v_alpha=None, features=None,
+                     depth="none", background=None, abs_sums=False, absgrad=False):
+        """Gradients of channels_fwd.  Expected depth E = A / Wt by the
+        quotient rule: dL/dA = v_E / Wt, dL/dWt = -v_E E / Wt (both 0 where
+        Wt = 0), composited back through the depth and ones channels.
+        v_colors has the features' shape (summed over cameras when they are
+        shared); "v_depths" [C,N] is the depth channel's gradient."""
+        C, N = proj["radii"].shape
+        ch, D, shared, e = self._channels(proj, features, depth)
+        v_image = np.asarray(v_image, dtype=np.float64).reshape(-1, D + (1 if depth != "none" else 0))
+        parts = [v_image[:, :D]]
+        if depth == "accumulated":
+            parts.append(v_image[:, D:D + 1])
+        elif depth == "expected":
+            Wt = np.asarray(fwd["weight"], np.float64)
+            E = np.asarray(fwd["image"], np.float64)[:, D]
+            vE = v_image[:, D]
+            pos = Wt > 0
+            vA, vW = np.zeros_like(vE), np.zeros_like(vE)
+            vA[pos] = vE[pos] / Wt[pos]
+            vW[pos] = -vE[pos] * E[pos] / Wt[pos]
+            parts += [vA[:, None], vW[:, None]]
+        g = self.rasterize_bwd(P, dict(proj, colors=ch), opacities, ranges, ids, W, H, fwd["final_T"],
+                               fwd["last_ids"], np.concatenate(parts, axis=1), v_alpha,
+                               background=self._bg_channels(background, C, D, e), abs_sums=abs_sums, absgrad=absgrad)
+        vc = g["v_colors"]
+        if depth != "none":
+            g["v_depths"] = np.ascontiguousarray(vc[..., D])
+        g["v_colors"] = vc[..., :D].sum(axis=0) if shared else np.ascontiguousarray(vc[..., :D])
+        if "abs_v_colors" in g:
+            a = g["abs_v_colors"]
+            if depth != "none":
+                g["abs_v_depths"] = np.ascontiguousarray(a[..., D])
+            g["abs_v_colors"] = a[..., :D].sum(axis=0) if shared else np.ascontiguousarray(a[..., :D])
+        return g
+
     # -- the plain definition, tile by tile ---------------------------------
     def render_tiles_fwd(self, P, proj, opacities, tiles, W, H, background=None, untiled=False):
         """``tiles``: int array [T, 3] of (camera, tile x, tile y)."""
@@ -275,12 +366,12 @@ class Oracle:
         Wa = _ints(np.broadcast_to(np.asarray(W), (C,)))
         Ha = _ints(np.broadcast_to(np.asarray(H), (C,)))
         tiles = np.ascontiguousarray(np.asarray(tiles, dtype=np.int32).reshape(-1, 3))
-        out = self._pixbufs(Wa, Ha)
+        out = self._pixbufs(Wa, Ha, _nch(proj))
         out["last_gid"] = np.full(out["alpha"].shape, -1, np.int32)
         out["last_pos"] = np.full(out["alpha"].shape, -1, np.int32)
         out["list_len"] = np.zeros(tiles.shape[0], np.int32)
         comps = self._r(proj["comps"]) if P.antialiased else None
-        self.lib.orc_render_tiles_fwd(self._cp(P), C, N, _p(Wa), _p(Ha), _p(self._r(proj["means2d"])),
+        self.lib.orc_render_tiles_fwd(self._cp(P), C, N, _nch(proj), _p(Wa), _p(Ha), _p(self._r(proj["means2d"])),
                                       _p(self._r(proj["conics"])), _p(self._r(proj["colors"])),
                                       _p(self._r(opacities)), _p(comps),
                                       _p(np.ascontiguousarray(proj["radii"], np.int32)),
@@ -300,9 +391,9 @@ class Oracle:
         tiles = np.ascontiguousarray(np.asarray(tiles, dtype=np.int32).reshape(-1, 3))
         dt = self.dtype
         out = dict(v_means2d=np.zeros((C, N, 2), dt), v_conics=np.zeros((C, N, 3), dt),
-                   v_colors=np.zeros((C, N, 3), dt), v_opacities=np.zeros((C, N), dt))
+                   v_colors=np.zeros((C, N, _nch(proj)), dt), v_opacities=np.zeros((C, N), dt))
         comps = self._r(proj["comps"]) if P.antialiased else None
-        self.lib.orc_render_tiles_bwd(self._cp(P), C, N, _p(Wa), _p(Ha), _p(self._r(proj["means2d"])),
+        self.lib.orc_render_tiles_bwd(self._cp(P), C, N, _nch(proj), _p(Wa), _p(Ha), _p(self._r(proj["means2d"])),
                                       _p(self._r(proj["conics"])), _p(self._r(proj["colors"])),
                                       _p(self._r(opacities)), _p(comps),
                                       _p(np.ascontiguousarray(proj["radii"], np.int32)),

@@ -463,10 +463,14 @@ int orc_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_
 /* ------------------------------------------------------------------------ */
 /* Front-to-back compositing of one pixel over a depth-ordered list.        */
 /* ------------------------------------------------------------------------ */
+/* colors [C,N,D]: D feature channels per projected Gaussian (N-dimensional
+ * rasterization; RGB is D = 3, RGB plus depth D = 4), at most ORC_MAX_D. */
+#define ORC_MAX_D 64
 typedef struct {
     const orc_params *P;
     int N;
     const REAL *means2d, *conics, *colors, *opacities, *comps;
+    int D;
 } scene2d_t;
 
 /* Per-pixel decision flags: set when a skip/stop/sign decision lies so close
@@ -475,7 +479,7 @@ typedef struct {
 #define FLAG_AMBIG 1u
 
 typedef struct {
-    REAL color[3], T;
+    REAL color[ORC_MAX_D], T;
     int last;            /* list position of the last composited entry, -1 if none */
     int n_eval;          /* entries evaluated, including the one that stopped it   */
     int n_comp;          /* entries composited                                     */
@@ -502,7 +506,9 @@ static void composite_pixel(const scene2d_t *S, const int32_t *list, int len, RE
                             const REAL *bg, pix_out_t *out)
 {
     const orc_params *P = S->P;
-    REAL T = K(1), C3[3] = {K(0), K(0), K(0)};
+    const int D = S->D;
+    REAL T = K(1), Cacc[ORC_MAX_D];
+    for (int ch = 0; ch < D; ch++) Cacc[ch] = K(0);
     int last = -1, n_eval = 0, n_comp = 0;
     uint32_t trace = 0, flags = 0;
     double eT = 0.0;               /* relative error budget of T (for flags) */
@@ -529,43 +535,45 @@ static void composite_pixel(const scene2d_t *S, const int32_t *list, int len, RE
         if (fabs((double)Tn - P->T_min) <= eTn * P->T_min) flags |= FLAG_AMBIG;
         if (Tn < (REAL)P->T_min) break;
         REAL w = alpha * T;
-        const REAL *col = S->colors + 3 * (size_t)g;
-        C3[0] += col[0] * w; C3[1] += col[1] * w; C3[2] += col[2] * w;
+        const REAL *col = S->colors + (size_t)D * g;
+        for (int ch = 0; ch < D; ch++) Cacc[ch] += col[ch] * w;
         T = Tn;
         eT = eTn;
         last = k;
         n_comp++;
         trace = trace * 2654435761u + (uint32_t)(2 * (k + 1) + (araw > (REAL)P->alpha_max));
     }
-    for (int ch = 0; ch < 3; ch++) out->color[ch] = C3[ch] + T * (bg ? bg[ch] : K(0));
+    for (int ch = 0; ch < D; ch++) out->color[ch] = Cacc[ch] + T * (bg ? bg[ch] : K(0));
     out->T = T; out->last = last; out->n_eval = n_eval; out->n_comp = n_comp;
     out->trace = trace; out->flags = flags;
 }
 
 /* Reverse recursion (Depth Compositing Gradients) for one pixel.  Gradient
  * sums go to double accumulators indexed by the Gaussian's [C,N] id. */
-/* abs (nullable): per id 9 sums of the magnitudes of the terms that make up
- * each gradient element (mean x, y; conic a, b, c; colour r, g, b; opacity),
+/* abs (nullable): per id 6 + D sums of the magnitudes of the terms that make
+ * up each gradient element (mean x, y; conic a, b, c; opacity; channels),
  * each term's magnitude taken over its parts before they cancel (for the
  * alpha gradient: sum over channels of |colour T_k| + |S / (1 - alpha)|
  * times |v_C|, plus |v_alpha final_T / (1 - alpha)|): the scale of the
  * rounding error any float32 evaluation and summation of the terms makes. */
-typedef struct { double *v_means2d, *v_conics, *v_colors, *v_opac, *abs, *v_means2d_abs; } grad2d_t;
+typedef struct { double *v_means2d, *v_conics, *v_colors, *v_opac, *abs, *v_means2d_abs; int D, nslot; } grad2d_t;
 
 static void add_term(grad2d_t *G, double *dst, size_t g, int slot, double x, double mag)
 {
     *dst += x;
-    if (G->abs) G->abs[9 * g + (size_t)slot] += mag;
+    if (G->abs) G->abs[(size_t)G->nslot * g + (size_t)slot] += mag;
 }
 
-static void grad2d_alloc(grad2d_t *G, size_t CN, int want_abs, int want_absgrad)
+static void grad2d_alloc(grad2d_t *G, size_t CN, int D, int want_abs, int want_absgrad)
 {
+    G->D = D;
+    G->nslot = 6 + D;
     G->v_means2d_abs = want_absgrad ? (double *)calloc(2 * CN + 1, sizeof(double)) : NULL;
     G->v_means2d = (double *)calloc(2 * CN + 1, sizeof(double));
     G->v_conics = (double *)calloc(3 * CN + 1, sizeof(double));
-    G->v_colors = (double *)calloc(3 * CN + 1, sizeof(double));
+    G->v_colors = (double *)calloc((size_t)D * CN + 1, sizeof(double));
     G->v_opac = (double *)calloc(CN + 1, sizeof(double));
-    G->abs = want_abs ? (double *)calloc(9 * CN + 1, sizeof(double)) : NULL;
+    G->abs = want_abs ? (double *)calloc((size_t)(6 + D) * CN + 1, sizeof(double)) : NULL;
 }
 
 static void grad2d_store(grad2d_t *G, size_t CN, REAL *v_means2d, REAL *v_conics, REAL *v_colors,
@@ -575,10 +583,11 @@ static void grad2d_store(grad2d_t *G, size_t CN, REAL *v_means2d, REAL *v_conics
         for (size_t i = 0; i < 2 * CN; i++) v_means2d_abs[i] = (REAL)G->v_means2d_abs[i];
     free(G->v_means2d_abs);
     for (size_t i = 0; i < 2 * CN; i++) v_means2d[i] = (REAL)G->v_means2d[i];
-    for (size_t i = 0; i < 3 * CN; i++) { v_conics[i] = (REAL)G->v_conics[i]; v_colors[i] = (REAL)G->v_colors[i]; }
+    for (size_t i = 0; i < 3 * CN; i++) v_conics[i] = (REAL)G->v_conics[i];
+    for (size_t i = 0; i < (size_t)G->D * CN; i++) v_colors[i] = (REAL)G->v_colors[i];
     for (size_t i = 0; i < CN; i++) v_opacities[i] = (REAL)G->v_opac[i];
     if (abs_sums && G->abs)
-        for (size_t i = 0; i < 9 * CN; i++) abs_sums[i] = (REAL)G->abs[i];
+        for (size_t i = 0; i < (size_t)(6 + G->D) * CN; i++) abs_sums[i] = (REAL)G->abs[i];
     free(G->v_means2d); free(G->v_conics); free(G->v_colors); free(G->v_opac); free(G->abs);
 }
 
@@ -586,9 +595,10 @@ static void composite_pixel_bwd(const scene2d_t *S, const int32_t *list, int las
                                 const REAL *bg, REAL T_final, const REAL *vC, REAL vA, grad2d_t *G)
 {
     const orc_params *P = S->P;
+    const int D = S->D;
     REAL T = T_final;
-    REAL Sacc[3];
-    for (int ch = 0; ch < 3; ch++) Sacc[ch] = T_final * (bg ? bg[ch] : K(0));
+    REAL Sacc[ORC_MAX_D];
+    for (int ch = 0; ch < D; ch++) Sacc[ch] = T_final * (bg ? bg[ch] : K(0));
     for (int k = last; k >= 0; k--) {
         int g = list[k];
         REAL dx = S->means2d[2 * g] - px, dy = S->means2d[2 * g + 1] - py;
@@ -602,23 +612,23 @@ static void composite_pixel_bwd(const scene2d_t *S, const int32_t *list, int las
         if (alpha < (REAL)P->alpha_min) continue;
         REAL one_m = K(1) - alpha;
         REAL Tk = T / one_m;                 /* transmittance in front of entry k */
-        const REAL *col = S->colors + 3 * (size_t)g;
+        const REAL *col = S->colors + (size_t)D * g;
         REAL v_alpha = K(0);
         double m_alpha = 0.0;                /* magnitude of v_alpha's parts */
-        for (int ch = 0; ch < 3; ch++) {
+        for (int ch = 0; ch < D; ch++) {
             double t = (double)(alpha * Tk * vC[ch]);
-            add_term(G, &G->v_colors[3 * (size_t)g + ch], (size_t)g, 5 + ch, t, fabs(t));
+            add_term(G, &G->v_colors[(size_t)D * g + ch], (size_t)g, 6 + ch, t, fabs(t));
             v_alpha += (col[ch] * Tk - Sacc[ch] / one_m) * vC[ch];
             m_alpha += (fabs((double)(col[ch] * Tk)) + fabs((double)(Sacc[ch] / one_m))) * fabs((double)vC[ch]);
         }
         v_alpha += vA * (T_final / one_m);
         m_alpha += fabs((double)(vA * (T_final / one_m)));
-        for (int ch = 0; ch < 3; ch++) Sacc[ch] += col[ch] * alpha * Tk;
+        for (int ch = 0; ch < D; ch++) Sacc[ch] += col[ch] * alpha * Tk;
         T = Tk;
         if (araw > (REAL)P->alpha_max) continue;    /* clamped: no gradient to o or sigma */
         /* d alpha / d o = exp(-sigma), o being the opacity the rasterizer
          * used (times the anti-aliasing compensation when that is on) */
-        add_term(G, &G->v_opac[g], (size_t)g, 8, (double)(e * v_alpha), (double)e * m_alpha);
+        add_term(G, &G->v_opac[g], (size_t)g, 5, (double)(e * v_alpha), (double)e * m_alpha);
         REAL v_sigma = -araw * v_alpha;
         double m_sigma = (double)araw * m_alpha;
         /* d sigma / d mu' = Y Delta with Delta = mu' - p; d sigma / d(a,b,c) */
@@ -655,20 +665,21 @@ static void camera_offsets(const orc_params *P, int C, const int *W, const int *
 /* Render every pixel of every (selected) tile from the sorted list.
  * Images are packed per camera: pixel (c, y, x) at pix_off[c] + y W_c + x.
  * last_ids holds the global position in the sorted list (-1: none). */
-int orc_rasterize_fwd(const orc_params *P, int C, int N, const int *W, const int *H,
+int orc_rasterize_fwd(const orc_params *P, int C, int N, int D, const int *W, const int *H,
                       const REAL *means2d, const REAL *conics, const REAL *colors, const REAL *opacities,
                       const REAL *comps, const REAL *background, const int32_t *ranges, const int32_t *ids,
                       const uint8_t *tile_mask, REAL *image, REAL *alpha, REAL *final_T, int32_t *last_ids,
                       int32_t *n_eval, int32_t *n_comp, uint8_t *flags, uint32_t *trace)
 {
+    if (D < 1 || D > ORC_MAX_D) return -1;
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     camera_offsets(P, C, W, H, pix_off, tile_off);
-    scene2d_t S = {P, N, means2d, conics, colors, opacities, comps};
+    scene2d_t S = {P, N, means2d, conics, colors, opacities, comps, D};
     int ts = P->tile;
     for (int c = 0; c < C; c++) {
         int TX = (W[c] + ts - 1) / ts, TY = (H[c] + ts - 1) / ts;
-        const REAL *bg = background ? background + 3 * c : NULL;
+        const REAL *bg = background ? background + (size_t)D * c : NULL;
         for (int ty = 0; ty < TY; ty++)
             for (int tx = 0; tx < TX; tx++) {
                 int64_t t = tile_off[c] + (int64_t)ty * TX + tx;
@@ -679,7 +690,7 @@ int orc_rasterize_fwd(const orc_params *P, int C, int N, const int *W, const int
                         pix_out_t po;
                         composite_pixel(&S, ids + start, end - start, (REAL)x + K(0.5), (REAL)y + K(0.5), bg, &po);
                         int64_t p = pix_off[c] + (int64_t)y * W[c] + x;
-                        for (int ch = 0; ch < 3; ch++) image[3 * p + ch] = po.color[ch];
+                        for (int ch = 0; ch < D; ch++) image[(size_t)D * p + ch] = po.color[ch];
                         alpha[p] = K(1) - po.T;
                         final_T[p] = po.T;
                         last_ids[p] = po.last >= 0 ? start + po.last : -1;
@@ -694,7 +705,7 @@ int orc_rasterize_fwd(const orc_params *P, int C, int N, const int *W, const int
     return 0;
 }
 
-int orc_rasterize_bwd(const orc_params *P, int C, int N, const int *W, const int *H,
+int orc_rasterize_bwd(const orc_params *P, int C, int N, int D, const int *W, const int *H,
                       const REAL *means2d, const REAL *conics, const REAL *colors, const REAL *opacities,
                       const REAL *comps, const REAL *background, const int32_t *ranges, const int32_t *ids,
                       const uint8_t *tile_mask, const REAL *final_T, const int32_t *last_ids,
@@ -702,17 +713,18 @@ int orc_rasterize_bwd(const orc_params *P, int C, int N, const int *W, const int
                       REAL *v_means2d, REAL *v_conics, REAL *v_colors, REAL *v_opacities, REAL *abs_sums,
                       REAL *v_means2d_abs)
 {
+    if (D < 1 || D > ORC_MAX_D) return -1;
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     camera_offsets(P, C, W, H, pix_off, tile_off);
     size_t CN = (size_t)C * N;
     grad2d_t G;
-    grad2d_alloc(&G, CN, abs_sums != NULL, v_means2d_abs != NULL);
-    scene2d_t S = {P, N, means2d, conics, colors, opacities, comps};
+    grad2d_alloc(&G, CN, D, abs_sums != NULL, v_means2d_abs != NULL);
+    scene2d_t S = {P, N, means2d, conics, colors, opacities, comps, D};
     int ts = P->tile;
     for (int c = 0; c < C; c++) {
         int TX = (W[c] + ts - 1) / ts, TY = (H[c] + ts - 1) / ts;
-        const REAL *bg = background ? background + 3 * c : NULL;
+        const REAL *bg = background ? background + (size_t)D * c : NULL;
         for (int ty = 0; ty < TY; ty++)
             for (int tx = 0; tx < TX; tx++) {
                 int64_t t = tile_off[c] + (int64_t)ty * TX + tx;
@@ -723,7 +735,7 @@ int orc_rasterize_bwd(const orc_params *P, int C, int N, const int *W, const int
                         int64_t p = pix_off[c] + (int64_t)y * W[c] + x;
                         if (last_ids[p] < 0) continue;
                         composite_pixel_bwd(&S, ids + start, last_ids[p] - start, (REAL)x + K(0.5), (REAL)y + K(0.5),
-                                            bg, final_T[p], v_image + 3 * p, v_alpha ? v_alpha[p] : K(0), &G);
+                                            bg, final_T[p], v_image + (size_t)D * p, v_alpha ? v_alpha[p] : K(0), &G);
                     }
             }
     }
@@ -783,23 +795,24 @@ int orc_tile_list(const orc_params *P, int C, int N, const int *W, const int *H,
  * Outputs are written into full packed images (only listed tiles touched).
  * last_gid: [C,N] id of the last composited Gaussian (-1); last_pos: its
  * position in the tile's list (-1). */
-int orc_render_tiles_fwd(const orc_params *P, int C, int N, const int *W, const int *H,
+int orc_render_tiles_fwd(const orc_params *P, int C, int N, int D, const int *W, const int *H,
                          const REAL *means2d, const REAL *conics, const REAL *colors, const REAL *opacities,
                          const REAL *comps, const int32_t *radii, const REAL *depths, const REAL *background,
                          int ntiles, const int32_t *tiles, int untiled,
                          REAL *image, REAL *alpha, REAL *final_T, int32_t *last_gid, int32_t *last_pos,
                          int32_t *n_eval, int32_t *n_comp, uint8_t *flags, uint32_t *trace, int32_t *list_len)
 {
+    if (D < 1 || D > ORC_MAX_D) return -1;
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     camera_offsets(P, C, W, H, pix_off, tile_off);
     int32_t *list = (int32_t *)malloc(sizeof(int32_t) * (N > 0 ? N : 1));
     did_t *tmp = (did_t *)malloc(sizeof(did_t) * (N > 0 ? N : 1));
-    scene2d_t S = {P, N, means2d, conics, colors, opacities, comps};
+    scene2d_t S = {P, N, means2d, conics, colors, opacities, comps, D};
     int ts = P->tile;
     for (int i = 0; i < ntiles; i++) {
         int c = tiles[3 * i], tx = tiles[3 * i + 1], ty = tiles[3 * i + 2];
-        const REAL *bg = background ? background + 3 * c : NULL;
+        const REAL *bg = background ? background + (size_t)D * c : NULL;
         int len = build_tile_list(P, N, c, W[c], H[c], tx, ty, means2d, radii, depths, untiled, list, tmp);
         if (list_len) list_len[i] = len;
         for (int y = ty * ts; y < (ty + 1) * ts && y < H[c]; y++)
@@ -807,7 +820,7 @@ int orc_render_tiles_fwd(const orc_params *P, int C, int N, const int *W, const 
                 pix_out_t po;
                 composite_pixel(&S, list, len, (REAL)x + K(0.5), (REAL)y + K(0.5), bg, &po);
                 int64_t p = pix_off[c] + (int64_t)y * W[c] + x;
-                for (int ch = 0; ch < 3; ch++) image[3 * p + ch] = po.color[ch];
+                for (int ch = 0; ch < D; ch++) image[(size_t)D * p + ch] = po.color[ch];
                 alpha[p] = K(1) - po.T;
                 final_T[p] = po.T;
                 if (last_gid) last_gid[p] = po.last >= 0 ? list[po.last] : -1;
@@ -824,13 +837,14 @@ int orc_render_tiles_fwd(const orc_params *P, int C, int N, const int *W, const 
 
 /* Gradients of sum(v_image * image) + sum(v_alpha * alpha) over the listed
  * tiles only, by the definition lists.  Outputs are [C,N]-indexed sums. */
-int orc_render_tiles_bwd(const orc_params *P, int C, int N, const int *W, const int *H,
+int orc_render_tiles_bwd(const orc_params *P, int C, int N, int D, const int *W, const int *H,
                          const REAL *means2d, const REAL *conics, const REAL *colors, const REAL *opacities,
                          const REAL *comps, const int32_t *radii, const REAL *depths, const REAL *background,
                          int ntiles, const int32_t *tiles, const REAL *v_image, const REAL *v_alpha,
                          REAL *v_means2d, REAL *v_conics, REAL *v_colors, REAL *v_opacities, REAL *abs_sums,
                          REAL *v_means2d_abs)
 {
+    if (D < 1 || D > ORC_MAX_D) return -1;
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     camera_offsets(P, C, W, H, pix_off, tile_off);
@@ -838,12 +852,12 @@ int orc_render_tiles_bwd(const orc_params *P, int C, int N, const int *W, const 
     did_t *tmp = (did_t *)malloc(sizeof(did_t) * (N > 0 ? N : 1));
     size_t CN = (size_t)C * N;
     grad2d_t G;
-    grad2d_alloc(&G, CN, abs_sums != NULL, v_means2d_abs != NULL);
-    scene2d_t S = {P, N, means2d, conics, colors, opacities, comps};
+    grad2d_alloc(&G, CN, D, abs_sums != NULL, v_means2d_abs != NULL);
+    scene2d_t S = {P, N, means2d, conics, colors, opacities, comps, D};
     int ts = P->tile;
     for (int i = 0; i < ntiles; i++) {
         int c = tiles[3 * i], tx = tiles[3 * i + 1], ty = tiles[3 * i + 2];
-        const REAL *bg = background ? background + 3 * c : NULL;
+        const REAL *bg = background ? background + (size_t)D * c : NULL;
         int len = build_tile_list(P, N, c, W[c], H[c], tx, ty, means2d, radii, depths, 0, list, tmp);
         for (int y = ty * ts; y < (ty + 1) * ts && y < H[c]; y++)
             for (int x = tx * ts; x < (tx + 1) * ts && x < W[c]; x++) {
@@ -852,7 +866,7 @@ int orc_render_tiles_bwd(const orc_params *P, int C, int N, const int *W, const 
                 composite_pixel(&S, list, len, px, py, bg, &po);
                 if (po.last < 0) continue;
                 int64_t p = pix_off[c] + (int64_t)y * W[c] + x;
-                composite_pixel_bwd(&S, list, po.last, px, py, bg, po.T, v_image + 3 * p,
+                composite_pixel_bwd(&S, list, po.last, px, py, bg, po.T, v_image + (size_t)D * p,
                                     v_alpha ? v_alpha[p] : K(0), &G);
             }
     }

@@ -44,6 +44,9 @@ int check_params(const gsr_params *p) {
     if (!(p->alpha_min > 0.0f) || !(p->alpha_max < 1.0f) || !(p->alpha_min < p->alpha_max))
         return fail(GSR_EINVAL, "need 0 < alpha_min < alpha_max < 1");
     if (!(p->T_min > 0.0f) || !(p->T_min < 1.0f)) return fail(GSR_EINVAL, "need 0 < T_min < 1");
+    if (p->render_depth < GSR_DEPTH_NONE || p->render_depth > GSR_DEPTH_EXPECTED)
+        return fail(GSR_EINVAL, "render_depth must be 0, 1 or 2 (got %d)", p->render_depth);
+    if (p->colors_shared != 0 && p->colors_shared != 1) return fail(GSR_EINVAL, "colors_shared must be 0 or 1");
     return GSR_OK;
 }
 
@@ -100,6 +103,8 @@ void gsr_default_params(gsr_params *p) {
     p->tile = kTile;
     p->sh_degree = -1;
     p->antialiased = 0;
+    p->render_depth = GSR_DEPTH_NONE;
+    p->colors_shared = 0;
 }
 
 size_t gsr_workspace_bytes(int op, int C, int N, int64_t M) {
@@ -126,8 +131,9 @@ int gsr_project_fwd(const gsr_params *p, int C, int N, const int32_t *W, const i
     if (rc == GSR_OK) rc = make_cams(C, N, W, H, cams);
     if (rc != GSR_OK) return rc;
     if ((int64_t)C * N == 0) return GSR_OK;
-    GSR_NEED(means); GSR_NEED(quats); GSR_NEED(scales); GSR_NEED(sh_or_colors); GSR_NEED(viewmats); GSR_NEED(Ks);
-    GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(radii); GSR_NEED(depths); GSR_NEED(colors);
+    GSR_NEED(means); GSR_NEED(quats); GSR_NEED(scales); GSR_NEED(viewmats); GSR_NEED(Ks);
+    GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(radii); GSR_NEED(depths);
+    if (p->sh_degree >= 0 || colors) { GSR_NEED(sh_or_colors); GSR_NEED(colors); }
     if (p->antialiased) GSR_NEED(compensations);
     return launch_project_fwd(*p, cams, N, means, quats, scales, sh_or_colors, viewmats, Ks, means2d, conics, radii,
                               depths, colors, compensations, (hipStream_t)stream);
@@ -247,54 +253,71 @@ int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const in
                              (hipStream_t)stream);
 }
 
-int gsr_rasterize_fwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
-                      const float *means2d, const float *conics, const float *colors,
+// The channel count: D features (0 .. 32) plus the depth channel, 1 .. 32 in all.
+static int check_channels(const char *fn, const gsr_params *p, int D) {
+    const int Dt = D + (p->render_depth != GSR_DEPTH_NONE ? 1 : 0);
+    if (D < 0 || Dt < 1 || Dt > kMaxChannels)
+        return fail(GSR_EINVAL, "%s: D = %d features%s: 1 .. %d channels supported", fn, D,
+                    p->render_depth != GSR_DEPTH_NONE ? " plus depth" : "", kMaxChannels);
+    return GSR_OK;
+}
+
+int gsr_rasterize_fwd(const gsr_params *p, int C, int N, int D, const int32_t *W, const int32_t *H,
+                      const float *means2d, const float *conics, const float *colors, const float *depths,
                       const float *opacities, const float *compensations, const float *background,
                       const int32_t *ranges, const int32_t *ids, float *image, float *alpha,
                       float *final_T, int32_t *last_ids, int32_t *n_eval, void *ws, size_t ws_bytes,
                       gsr_stream_t stream) {
     static const char *fn = "gsr_rasterize_fwd";
     int rc = check_params(p);
+    if (rc == GSR_OK) rc = check_channels(fn, p, D);
     CamTable cams;
     if (rc == GSR_OK) rc = make_cams(C, N, W, H, cams);
     if (rc != GSR_OK) return rc;
     if (cams.total_pix == 0) return GSR_OK;
     GSR_NEED(ranges); GSR_NEED(image); GSR_NEED(alpha); GSR_NEED(final_T); GSR_NEED(last_ids);
-    if (N > 0) { GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(colors); GSR_NEED(opacities); GSR_NEED(ids); }
+    if (N > 0) { GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(ids); }
+    if (N > 0 && D > 0) GSR_NEED(colors);
+    if (N > 0 && p->render_depth != GSR_DEPTH_NONE) GSR_NEED(depths);
     if (p->antialiased && N > 0) GSR_NEED(compensations);
     if (N > 0) {
         const size_t need = pack_workspace_bytes((int64_t)C * N);
         if (!ws || ws_bytes < need)
             return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws ? ws_bytes : 0);
     }
-    return launch_rasterize_fwd(*p, cams, N, means2d, conics, colors, opacities, compensations, background, ranges,
+    return launch_rasterize_fwd(*p, cams, N, D, means2d, conics, colors, depths, opacities, compensations, background, ranges,
                                 ids, image, alpha, final_T, last_ids, n_eval, ws, (hipStream_t)stream);
 }
 
-int gsr_rasterize_bwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
-                      const float *means2d, const float *conics, const float *colors,
+int gsr_rasterize_bwd(const gsr_params *p, int C, int N, int D, const int32_t *W, const int32_t *H,
+                      const float *means2d, const float *conics, const float *colors, const float *depths,
                       const float *opacities, const float *compensations, const float *background,
-                      const int32_t *ranges, const int32_t *ids, const float *final_T,
+                      const int32_t *ranges, const int32_t *ids, const float *image, const float *final_T,
                       const int32_t *last_ids, const float *v_image, const float *v_alpha,
-                      float *v_means2d, float *v_conics, float *v_colors, float *v_opacities,
+                      float *v_means2d, float *v_conics, float *v_colors, float *v_depths, float *v_opacities,
                       float *v_means2d_abs, void *ws, size_t ws_bytes, int flags, gsr_stream_t stream) {
     static const char *fn = "gsr_rasterize_bwd";
     if (flags & ~(GSR_BWD_ACCUMULATE | GSR_BWD_PACKED)) return fail(GSR_EINVAL, "%s: unknown flags 0x%x", fn, flags);
     int rc = check_params(p);
+    if (rc == GSR_OK) rc = check_channels(fn, p, D);
     CamTable cams;
     if (rc == GSR_OK) rc = make_cams(C, N, W, H, cams);
     if (rc != GSR_OK) return rc;
     if ((int64_t)C * N == 0) return GSR_OK;
-    GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(colors); GSR_NEED(opacities); GSR_NEED(ranges); GSR_NEED(ids);
+    GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(ranges); GSR_NEED(ids);
     GSR_NEED(final_T); GSR_NEED(last_ids); GSR_NEED(v_image);
-    GSR_NEED(v_means2d); GSR_NEED(v_conics); GSR_NEED(v_colors); GSR_NEED(v_opacities);
+    GSR_NEED(v_means2d); GSR_NEED(v_conics); GSR_NEED(v_opacities);
+    if (D > 0) { GSR_NEED(colors); GSR_NEED(v_colors); }
+    if (p->render_depth != GSR_DEPTH_NONE) { GSR_NEED(depths); GSR_NEED(v_depths); }
+    if (p->render_depth == GSR_DEPTH_EXPECTED) GSR_NEED(image);
     if (p->antialiased) GSR_NEED(compensations);
     const size_t need = pack_workspace_bytes((int64_t)C * N);
     if (!ws || ws_bytes < need)
         return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws ? ws_bytes : 0);
-    return launch_rasterize_bwd(*p, cams, N, means2d, conics, colors, opacities, compensations, background, ranges,
-                                ids, final_T, last_ids, v_image, v_alpha, v_means2d, v_conics, v_colors,
-                                v_opacities, v_means2d_abs, ws, flags, (hipStream_t)stream);
+    return launch_rasterize_bwd(*p, cams, N, D, means2d, conics, colors, depths, opacities, compensations,
+                                background, ranges, ids, image, final_T, last_ids, v_image, v_alpha, v_means2d,
+                                v_conics, v_colors, v_depths, v_opacities, v_means2d_abs, ws, flags,
+                                (hipStream_t)stream);
 }
 
 int gsr_project_bwd(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
@@ -313,11 +336,14 @@ int gsr_project_bwd(const gsr_params *p, int C, int N, const int32_t *W, const i
     if (N == 0)   // no Gaussians: the pose gradient is zero
         return (v_viewmats && C > 0) ? launch_fill_zero(v_viewmats, (size_t)C * 16 * sizeof(float),
                                                         (hipStream_t)stream) : GSR_OK;
-    GSR_NEED(means); GSR_NEED(quats); GSR_NEED(scales); GSR_NEED(opacities); GSR_NEED(sh_or_colors);
-    GSR_NEED(v_means); GSR_NEED(v_quats); GSR_NEED(v_scales); GSR_NEED(v_opacities); GSR_NEED(v_sh_or_colors);
+    GSR_NEED(means); GSR_NEED(quats); GSR_NEED(scales); GSR_NEED(opacities);
+    GSR_NEED(v_means); GSR_NEED(v_quats); GSR_NEED(v_scales); GSR_NEED(v_opacities);
+    const bool colour_grad = p->sh_degree >= 0 || v_colors;   // direct colours may be left out
+    if (colour_grad) { GSR_NEED(sh_or_colors); GSR_NEED(v_sh_or_colors); }
     if (C > 0) {
         GSR_NEED(viewmats); GSR_NEED(Ks); GSR_NEED(radii);
-        GSR_NEED(v_means2d); GSR_NEED(v_conics); GSR_NEED(v_colors); GSR_NEED(v_opacities_cn);
+        GSR_NEED(v_means2d); GSR_NEED(v_conics); GSR_NEED(v_opacities_cn);
+        if (colour_grad) GSR_NEED(v_colors);
         if (p->antialiased) GSR_NEED(compensations);
     }
     if (v_viewmats && C > 0 && N > 0) {

@@ -68,18 +68,19 @@ int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const fl
                       const int32_t *radii, const float *depths, int64_t M, void *ws_prep, void *ws_fin,
                       int32_t *ids, int32_t *ranges, uint64_t *keys64, hipStream_t s);
 
-int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
-                         const float *conics, const float *colors, const float *opacities,
+int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, int D, const float *means2d,
+                         const float *conics, const float *colors, const float *depths, const float *opacities,
                          const float *comps, const float *background, const int32_t *ranges,
                          const int32_t *ids, float *image, float *alpha, float *final_T, int32_t *last_ids,
                          int32_t *n_eval, void *ws, hipStream_t s);
 
-int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
-                         const float *conics, const float *colors, const float *opacities,
+int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D, const float *means2d,
+                         const float *conics, const float *colors, const float *depths, const float *opacities,
                          const float *comps, const float *background, const int32_t *ranges,
-                         const int32_t *ids, const float *final_T, const int32_t *last_ids,
+                         const int32_t *ids, const float *image, const float *final_T, const int32_t *last_ids,
                          const float *v_image, const float *v_alpha, float *v_means2d, float *v_conics,
-                         float *v_colors, float *v_opac, float *v_means2d_abs, void *ws, int flags, hipStream_t s);
+                         float *v_colors, float *v_depths, float *v_opac, float *v_means2d_abs, void *ws, int flags,
+                         hipStream_t s);
 
 int launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
 
@@ -201,8 +202,30 @@ struct PackedGauss {
 };
 
 size_t pack_workspace_bytes(int64_t cn);
-int launch_pack(const gsr_params &p, int CN, int N, const float *means2d, const float *conics, const float *colors,
-                const float *opacities, const float *comps, PackedGauss *out, hipStream_t s);
+int launch_pack(const gsr_params &p, int CN, int N, int D, const float *means2d, const float *conics,
+                const float *colors, const float *opacities, const float *comps, PackedGauss *out, hipStream_t s);
+// Channel capacity of the compositing kernels for D channels: 3 (RGB in the
+// packed records), 4, 8, 16 or 32 (channels staged in LDS).
+// Channels composited (D features plus the depth channel when rendered) and
+// the capacity of the kernel instance that composites them: 3 for plain RGB
+// (colours ride in the packed records), else the next of 4, 8, 16, 32.
+int composited_channels(const gsr_params &p, int D);
+int channel_capacity(const gsr_params &p, int D);
+constexpr int kMaxChannels = 32;
+
+// Stages the a.Dt channels of list entry g (a Gaussian of camera c) into
+// column t of s_feat, laid out [DM][B] (conflict-free stores, broadcast
+// reads): features from a.feat ([C,N,D], or [N,D] when colors_shared), then
+// the camera-space depth as channel a.D when depth is rendered, zeros up to DM.
+template <int DM, int B, typename Args>
+__device__ __forceinline__ void stage_features(const Args &a, int c, int g, int t, float *s_feat) {
+    int n = g - c * a.N;
+    if ((unsigned)n >= (unsigned)a.N) n = 0;      // only a bad id can leave the tile's camera
+    const float *f = a.feat + (size_t)(a.p.colors_shared ? n : g) * a.D;
+#pragma unroll
+    for (int d = 0; d < DM; d++)
+        s_feat[d * B + t] = d < a.D ? f[d] : (d < a.Dt ? a.depths[g] : 0.0f);
+}
 
 // Per-quad lists of a staged batch.  Thread t holds batch entry t with quad
 // mask m (0 when the entry is past the list end); afterwards list[q][0 ..

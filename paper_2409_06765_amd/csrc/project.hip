@@ -233,13 +233,13 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(gsr_params p, CamTable
         if (!o.valid) {
             means2d[2 * g] = 0.0f; means2d[2 * g + 1] = 0.0f;
             conics[3 * g] = 0.0f; conics[3 * g + 1] = 0.0f; conics[3 * g + 2] = 0.0f;
-            colors[3 * g] = 0.0f; colors[3 * g + 1] = 0.0f; colors[3 * g + 2] = 0.0f;
+            if (colors) { colors[3 * g] = 0.0f; colors[3 * g + 1] = 0.0f; colors[3 * g + 2] = 0.0f; }
             radii[g] = 0;
             depths[g] = 0.0f;
             if (comps) comps[g] = 0.0f;
             continue;
         }
-        if (!have_coef) {   // culled Gaussians never read their colour coefficients
+        if (colors && !have_coef) {   // culled Gaussians never read their colour coefficients
             load_colour_coeffs<NK>(shc, n, coef);
             have_coef = true;
         }
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(gsr_params p, CamTable
                 for (int k = 0; k < NK; k++) acc += Y[k] * coef[3 * k + ch];
                 colors[3 * g + ch] = fmaxf(acc + 0.5f, 0.0f);
             }
-        } else {
+        } else if (colors) {   // direct colours; none when the rasterizer takes features of its own
             colors[3 * g] = coef[0]; colors[3 * g + 1] = coef[1]; colors[3 * g + 2] = coef[2];
         }
     }
@@ -428,7 +428,8 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
 
         // colour
         float gdir[3] = {0.0f, 0.0f, 0.0f};   // mean gradient through the SH view direction
-        const float vc[3] = {v_colors[3 * g], v_colors[3 * g + 1], v_colors[3 * g + 2]};
+        float vc[3] = {0.0f, 0.0f, 0.0f};   // no v_colors: direct colours are not differentiated here
+        if (v_colors) { vc[0] = v_colors[3 * g]; vc[1] = v_colors[3 * g + 1]; vc[2] = v_colors[3 * g + 2]; }
         if constexpr (NK > 0) {
             float cp[3], d[3];
             for (int j = 0; j < 3; j++) cp[j] = -((V[j] * V[3] + V[4 + j] * V[7]) + V[8 + j] * V[11]);
@@ -491,9 +492,11 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
         for (int j = 0; j < 3; j++) { v_means[3 * n + j] = acc_mu[j]; v_scales[3 * n + j] = acc_s[j]; }
         reinterpret_cast<float4 *>(v_quats)[n] = make_float4(acc_q[0], acc_q[1], acc_q[2], acc_q[3]);
         v_opac[n] = acc_o;
-        float *dst = v_sh + (size_t)n * L;
+        if (v_sh) {
+            float *dst = v_sh + (size_t)n * L;
 #pragma unroll
-        for (int i = 0; i < L; i++) dst[i] = acc_sh[i];
+            for (int i = 0; i < L; i++) dst[i] = acc_sh[i];
+        }
     }
     if (kPose) {
         __syncthreads();

@@ -33,17 +33,23 @@ struct RasterBwdArgs {
     gsr_params p;
     int N;
     int CN;
+    int D;                                // feature channels of colors
+    int Dt;                               // channels composited: D, plus one for depth; at most the kernel's DM
+    const float *__restrict__ feat;       // colors [C,N,D] or [N,D] (read here unless plain RGB)
+    const float *__restrict__ depths;     // [C,N], channel D when a depth mode is set
     const PackedGauss *__restrict__ gauss;
     const float *__restrict__ background;
     const int32_t *__restrict__ ranges;
     const int32_t *__restrict__ ids;
+    const float *__restrict__ image;      // the forward's image (expected depth reads its depth channel)
     const float *__restrict__ final_T;
     const int32_t *__restrict__ last_ids;
     const float *__restrict__ v_image;
     const float *__restrict__ v_alpha;
     float *__restrict__ v_means2d;
     float *__restrict__ v_conics;
-    float *__restrict__ v_colors;
+    float *__restrict__ v_colors;         // [C,N,D] or [N,D] as colors
+    float *__restrict__ v_depths;         // [C,N], gradient of the depth channel
     float *__restrict__ v_opac;
     float *__restrict__ v_means2d_abs;
 };
@@ -90,10 +96,26 @@ __device__ __forceinline__ float wave_total(float v) {
     return add_xor32(add_xor16(v));
 }
 
+// Where the gradient of composited channel d of Gaussian g (id n within its
+// camera) goes: a feature channel of v_colors, or v_depths for the depth
+// channel.
+template <typename Args>
+__device__ __forceinline__ float *channel_dst(const Args &a, int d, int &mul, bool &by_n) {
+    if (d < a.D) { mul = a.D; by_n = a.p.colors_shared != 0; return a.v_colors + d; }
+    mul = 1; by_n = false;
+    return a.v_depths;
+}
+
+// DM: channel capacity as in the forward (3: RGB from the packed records;
+// otherwise a.Dt <= DM channels staged into LDS).  Channels 0..2 ride in the
+// transposing butterfly, further channels get a wave sum each.
+template <int DM>
 __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, CamTable cams) {
+    constexpr bool kRGB = DM == 3;
     __shared__ float4 s_xyo[kBatch];   // mean x, mean y, opacity, -
     __shared__ float4 s_con[kBatch];   // conic a, b, c, -
-    __shared__ float4 s_col[kBatch];   // colour r, g, b, -
+    __shared__ float4 s_col[kBatch];   // colour r, g, b, log2(opacity / alpha_min)
+    __shared__ float s_feat[kRGB ? 1 : DM * kBatch];
     __shared__ int32_t s_id[kBatch];
     __shared__ uint8_t s_qlist[4][kBatch];
     __shared__ int32_t s_wcnt[4][4];
@@ -117,17 +139,38 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
     // Per pixel: T restored back to front, and SV = (S . v_C) with S the colour accumulated behind the
     // current entry (plus final_T times the background): dL/dalpha only needs S through that dot
     // product, and S . v_C advances by (colour . v_C) alpha T_k per composited entry.
+    const int D = kRGB ? 3 : a.D, Dt = kRGB ? 3 : a.Dt;
     int last = -1;
-    float T = 1.0f, vC0 = 0.0f, vC1 = 0.0f, vC2 = 0.0f, vATf = 0.0f, SV = 0.0f;
+    float T = 1.0f, vC[DM], vATf = 0.0f, SV = 0.0f;
+#pragma unroll
+    for (int d = 0; d < DM; d++) vC[d] = 0.0f;
     if (inside) {
         const int64_t pix = ci.pix_off + (int64_t)yi * ci.W + xi;
         last = a.last_ids[pix];
         const float Tf = a.final_T[pix];
         T = Tf;
-        vC0 = a.v_image[3 * pix]; vC1 = a.v_image[3 * pix + 1]; vC2 = a.v_image[3 * pix + 2];
-        if (a.v_alpha) vATf = a.v_alpha[pix] * Tf;
-        if (a.background)
-            SV = Tf * ((a.background[3 * c] * vC0 + a.background[3 * c + 1] * vC1) + a.background[3 * c + 2] * vC2);
+#pragma unroll
+        for (int d = 0; d < DM; d++) vC[d] = d < Dt ? a.v_image[(int64_t)Dt * pix + d] : 0.0f;
+        float v_alpha = a.v_alpha ? a.v_alpha[pix] : 0.0f;
+        if (!kRGB && Dt > D && a.p.render_depth == GSR_DEPTH_EXPECTED) {
+            // E = A / W with A the composited depth and W = sum alpha T = 1 - final_T: the gradient
+            // reaches A as v_E / W and W as -v_E E / W, which is an alpha-output gradient
+            const float Wn = 1.0f - Tf;
+            float vE = 0.0f;
+#pragma unroll
+            for (int d = 0; d < DM; d++) vE = d == D ? vC[d] : vE;
+            const float gA = Wn > 0.0f ? vE / Wn : 0.0f;
+#pragma unroll
+            for (int d = 0; d < DM; d++) vC[d] = d == D ? gA : vC[d];
+            v_alpha -= gA * a.image[(int64_t)Dt * pix + D];
+        }
+        vATf = v_alpha * Tf;
+        if (a.background) {
+            float bv = 0.0f;
+#pragma unroll
+            for (int d = 0; d < DM; d++) bv += d < D ? a.background[D * c + d] * vC[d] : 0.0f;
+            SV = Tf * bv;
+        }
     }
     // largest last index of the wave and of the block
     int m = last;
@@ -141,17 +184,24 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
     const bool want_abs = a.v_means2d_abs != nullptr;
     const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
 
-    // After the reduction lane i < 8 holds the total of value i; lane 8 the
-    // opacity gradient, lanes 9, 10 the absolute mean gradient.  Each of these
-    // lanes adds its total at dst_base + g * dst_mul.
-    const int nslots = want_abs ? 11 : 9;
+    // After the reduction lane i < 8 holds the total of value i (mean x, y;
+    // conic a, b, c; channels 0..2), lane 8 the opacity gradient, lanes
+    // 9 .. 8 + extra channels 3 .. Dt - 1, the next two the absolute mean
+    // gradient.  Each of these lanes adds its total at dst_base + i * dst_mul
+    // with i the Gaussian's list id g, or its id n within the camera for
+    // features shared by all cameras.
+    const int extra = Dt > 3 ? Dt - 3 : 0;
+    const int nslots = 9 + extra + (want_abs ? 2 : 0);
     float *dst_base = nullptr;
     int dst_mul = 0;
+    bool dst_by_n = false;
     if (lane < 2) { dst_base = a.v_means2d + lane; dst_mul = 2; }
     else if (lane < 5) { dst_base = a.v_conics + (lane - 2); dst_mul = 3; }
-    else if (lane < 8) { dst_base = a.v_colors + (lane - 5); dst_mul = 3; }
+    else if (lane < 8) { if (lane - 5 < Dt) dst_base = channel_dst(a, lane - 5, dst_mul, dst_by_n); }
     else if (lane == 8) { dst_base = a.v_opac; dst_mul = 1; }
-    else if (lane < 11 && want_abs) { dst_base = a.v_means2d_abs + (lane - 9); dst_mul = 2; }
+    else if (lane < 9 + extra) { dst_base = channel_dst(a, lane - 6, dst_mul, dst_by_n); }
+    else if (lane < 11 + extra && want_abs) { dst_base = a.v_means2d_abs + (lane - 9 - extra); dst_mul = 2; }
+    const int cam_base = c * a.N;
 
     for (int hi = stop + 1; hi > start; hi -= kBatch) {
         const int base = max(start, hi - kBatch);
@@ -168,6 +218,7 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
             s_con[threadIdx.x] = r.conh;
             s_col[threadIdx.x] = r.col;
             s_id[threadIdx.x] = g;
+            if (!kRGB) stage_features<DM, kBatch>(a, c, g, threadIdx.x, s_feat);
         }
         compact_quads(qm, s_qlist, s_wcnt, s_qcnt);
         for (int j = s_qcnt[w] - 1; j >= 0; j--) {
@@ -183,12 +234,19 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
             const float al = fminf(amax, araw);
             const bool use = kk <= last && sig >= 0.0f && al >= amin;
             if (__ballot(use) == 0ull) continue;
-            const float4 col = s_col[e];
             const float inv = __builtin_amdgcn_rcpf(1.0f - al);
             const float Tk = T * inv;
             const float wgt = use ? al * Tk : 0.0f;
             // dL/dalpha = (colour T_k - S / (1 - alpha)) . v_C + v_alpha final_T / (1 - alpha)
-            const float cv = (col.x * vC0 + col.y * vC1) + col.z * vC2;
+            float cv;
+            if (kRGB) {
+                const float4 col = s_col[e];
+                cv = (col.x * vC[0] + col.y * vC[1]) + col.z * vC[2];
+            } else {
+                cv = 0.0f;
+#pragma unroll
+                for (int d = 0; d < DM; d++) cv = fmaf(s_feat[d * kBatch + e], vC[d], cv);
+            }
             float v_al = fmaf(Tk, cv, inv * (vATf - SV));
             SV = fmaf(wgt, cv, SV);
             T = use ? Tk : T;
@@ -202,8 +260,8 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
             // transposing butterfly: 8 values -> lane holds value (lane & 7)
             const float w0 = bfly<kDppXor1>(g_mx, g_my, b0);
             const float w1 = bfly<kDppXor1>(h * dx * dx, v_sig * dx * dy, b0);
-            const float w2 = bfly<kDppXor1>(h * dy * dy, wgt * vC0, b0);
-            const float w3 = bfly<kDppXor1>(wgt * vC1, wgt * vC2, b0);
+            const float w2 = bfly<kDppXor1>(h * dy * dy, wgt * vC[0], b0);
+            const float w3 = bfly<kDppXor1>(wgt * vC[1], DM > 2 ? wgt * vC[DM > 2 ? 2 : 0] : 0.0f, b0);
             const float x0 = bfly<kDppXor2>(w0, w1, b1);
             const float x1 = bfly<kDppXor2>(w2, w3, b1);
             float y = bfly<kDppRor4>(x0, x1, b2);
@@ -211,13 +269,22 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
             y = add_xor32(add_xor16(y));
             const float zo = wave_total(ex * v_al);
             float val = lane < 8 ? y : zo;
+#pragma unroll
+            for (int d = 3; d < DM; d++) {
+                if (d < Dt) {                            // uniform: Dt is the same for every lane
+                    const float zc = wave_total(wgt * vC[d]);
+                    val = lane == 6 + d ? zc : val;
+                }
+            }
             if (want_abs) {
                 const float zx = wave_total(fabsf(g_mx)), zy = wave_total(fabsf(g_my));
-                val = lane == 9 ? zx : lane == 10 ? zy : val;
+                val = lane == 9 + extra ? zx : lane == 10 + extra ? zy : val;
             }
-            if (lane < nslots) {
+            if (lane < nslots && dst_base) {
                 const int g = s_id[e];
-                unsafeAtomicAdd(dst_base + (int64_t)g * dst_mul, val);
+                int n = g - cam_base;
+                if ((unsigned)n >= (unsigned)a.N) n = 0;   // only a bad id can leave the tile's camera
+                unsafeAtomicAdd(dst_base + (int64_t)(dst_by_n ? n : g) * dst_mul, val);
             }
         }
     }
@@ -225,19 +292,21 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
 
 }  // namespace
 
-int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
-                         const float *conics, const float *colors, const float *opacities,
+int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D, const float *means2d,
+                         const float *conics, const float *colors, const float *depths, const float *opacities,
                          const float *comps, const float *background, const int32_t *ranges,
-                         const int32_t *ids, const float *final_T, const int32_t *last_ids,
+                         const int32_t *ids, const float *image, const float *final_T, const int32_t *last_ids,
                          const float *v_image, const float *v_alpha, float *v_means2d, float *v_conics,
-                         float *v_colors, float *v_opac, float *v_means2d_abs, void *ws, int flags,
+                         float *v_colors, float *v_depths, float *v_opac, float *v_means2d_abs, void *ws, int flags,
                          hipStream_t s) {
     const size_t CN = (size_t)cams.C * (size_t)N;
+    const size_t FN = p.colors_shared ? (size_t)N : CN;
     int rc = GSR_OK;
     if (!(flags & GSR_BWD_ACCUMULATE)) {
         rc = launch_fill_zero(v_means2d, CN * 2 * sizeof(float), s);
         if (rc == GSR_OK) rc = launch_fill_zero(v_conics, CN * 3 * sizeof(float), s);
-        if (rc == GSR_OK) rc = launch_fill_zero(v_colors, CN * 3 * sizeof(float), s);
+        if (rc == GSR_OK && D > 0) rc = launch_fill_zero(v_colors, FN * (size_t)D * sizeof(float), s);
+        if (rc == GSR_OK && p.render_depth != GSR_DEPTH_NONE) rc = launch_fill_zero(v_depths, CN * sizeof(float), s);
         if (rc == GSR_OK) rc = launch_fill_zero(v_opac, CN * sizeof(float), s);
         if (rc == GSR_OK && v_means2d_abs) rc = launch_fill_zero(v_means2d_abs, CN * 2 * sizeof(float), s);
     }
@@ -245,12 +314,21 @@ int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, const
     const int cn = cams.C * N;
     PackedGauss *gauss = (PackedGauss *)ws;
     if (!(flags & GSR_BWD_PACKED)) {
-        rc = launch_pack(p, cn, N, means2d, conics, colors, opacities, p.antialiased ? comps : nullptr, gauss, s);
+        rc = launch_pack(p, cn, N, D, means2d, conics, colors, opacities, p.antialiased ? comps : nullptr, gauss,
+                         s);
         if (rc != GSR_OK) return rc;
     }
-    RasterBwdArgs a{p, N, cn, gauss, background, ranges, ids, final_T, last_ids, v_image, v_alpha, v_means2d,
-                    v_conics, v_colors, v_opac, v_means2d_abs};
-    raster_bwd_kernel<<<dim3((unsigned)cams.total_tiles), dim3(kThreads), 0, s>>>(a, cams);
+    RasterBwdArgs a{p, N, cn, D, composited_channels(p, D), colors, depths, gauss, background, ranges, ids, image,
+                    final_T, last_ids, v_image, v_alpha, v_means2d, v_conics, v_colors, v_depths, v_opac,
+                    v_means2d_abs};
+    const dim3 grid((unsigned)cams.total_tiles), block(kThreads);
+    switch (channel_capacity(p, D)) {
+        case 3: raster_bwd_kernel<3><<<grid, block, 0, s>>>(a, cams); break;
+        case 4: raster_bwd_kernel<4><<<grid, block, 0, s>>>(a, cams); break;
+        case 8: raster_bwd_kernel<8><<<grid, block, 0, s>>>(a, cams); break;
+        case 16: raster_bwd_kernel<16><<<grid, block, 0, s>>>(a, cams); break;
+        default: raster_bwd_kernel<32><<<grid, block, 0, s>>>(a, cams); break;
+    }
     return launch_check("rasterize_bwd");
 }
 

@@ -18,20 +18,26 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kBatch = 256;
 
-__global__ void __launch_bounds__(256) pack_kernel(int CN, int N, float alpha_min,
+// Colours go into the record only for plain RGB (D = 3, no depth channel);
+// other channel sets are staged from the feature array by the compositing
+// kernels.  shared: colours are [N,D], one row per Gaussian for all cameras.
+__global__ void __launch_bounds__(256) pack_kernel(int CN, int N, bool rgb, bool shared, float alpha_min,
         const float *__restrict__ means2d, const float *__restrict__ conics, const float *__restrict__ colors,
         const float *__restrict__ opacities, const float *__restrict__ comps, PackedGauss *__restrict__ out) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= CN) return;
-    float o = opacities[g % N];
+    const int n = g % N;
+    float o = opacities[n];
     if (comps) o *= comps[g];
     const float ca = conics[3 * g], cb = conics[3 * g + 1], cc = conics[3 * g + 2];
     const float2 h = support_extent(ca, cb, cc, o, alpha_min);
     PackedGauss r;
     r.xyoh = make_float4(means2d[2 * g], means2d[2 * g + 1], o, h.x);
     r.conh = make_float4(0.5f * kLog2e * ca, kLog2e * cb, 0.5f * kLog2e * cc, h.y);
-    r.col = make_float4(colors[3 * g], colors[3 * g + 1], colors[3 * g + 2],
-                        o >= alpha_min ? log2f(o / alpha_min) : -1.0f);
+    const float Lq = o >= alpha_min ? log2f(o / alpha_min) : -1.0f;
+    const int f = shared ? n : g;
+    r.col = rgb ? make_float4(colors[3 * f], colors[3 * f + 1], colors[3 * f + 2], Lq)
+                : make_float4(0.0f, 0.0f, 0.0f, Lq);
     out[g] = r;
 }
 
@@ -39,6 +45,10 @@ struct RasterArgs {
     gsr_params p;
     int N;
     int CN;
+    int D;                                // feature channels of colors
+    int Dt;                               // channels composited: D, plus one for depth; at most the kernel's DM
+    const float *__restrict__ feat;       // colors [C,N,D] or [N,D] (read here unless plain RGB)
+    const float *__restrict__ depths;     // [C,N], composited as channel D when a depth mode is set
     const PackedGauss *__restrict__ gauss;
     const float *__restrict__ background;
     const int32_t *__restrict__ ranges;
@@ -51,11 +61,15 @@ struct RasterArgs {
 };
 
 // kCount: also count the entries each pixel evaluates and composites.
-template <bool kCount>
+// DM: channel capacity; DM = 3 takes RGB from the packed records, any other
+// DM stages a.Dt <= DM channels per entry into LDS.
+template <bool kCount, int DM>
 __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamTable cams) {
+    constexpr bool kRGB = DM == 3;
     __shared__ float4 s_xyo[kBatch];   // mean x, mean y, opacity, -
     __shared__ float4 s_con[kBatch];   // conic a, b, c, -
-    __shared__ float4 s_col[kBatch];   // colour r, g, b, -
+    __shared__ float4 s_col[kBatch];   // colour r, g, b, log2(opacity / alpha_min)
+    __shared__ float s_feat[kRGB ? 1 : DM * kBatch];
     __shared__ uint8_t s_qlist[4][kBatch];
     __shared__ int32_t s_wcnt[4][4];
     __shared__ int32_t s_qcnt[4];
@@ -74,7 +88,9 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     const int start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const float amin = a.p.alpha_min, amax = __builtin_canonicalizef(a.p.alpha_max), tmin = a.p.T_min;
 
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    float T = 1.0f, Wacc = 0.0f, Cacc[DM];   // Wacc: sum of alpha T, the expected-depth normaliser
+#pragma unroll
+    for (int d = 0; d < DM; d++) Cacc[d] = 0.0f;
     int last = -1, ncomp = 0, stop_at = -1;
     bool done = !inside;
     for (int b0 = start; b0 < end; b0 += kBatch) {
@@ -90,6 +106,7 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
             s_xyo[threadIdx.x] = r.xyoh;
             s_con[threadIdx.x] = r.conh;
             s_col[threadIdx.x] = r.col;
+            if (!kRGB) stage_features<DM, kBatch>(a, c, g, threadIdx.x, s_feat);
         }
         compact_quads(qm, s_qlist, s_wcnt, s_qcnt);
         const int cnt = s_qcnt[w];                  // entries that can reach this wave's quad
@@ -108,8 +125,14 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
             if (kCount) stop_at = stop ? b0 + e : stop_at;
             done = done || stop;
             const float wgt = comp ? al * T : 0.0f;
-            const float4 col = s_col[e];
-            C0 += col.x * wgt; C1 += col.y * wgt; C2 += col.z * wgt;
+            if (kRGB) {
+                const float4 col = s_col[e];
+                Cacc[0] += col.x * wgt; Cacc[1] += col.y * wgt; Cacc[2] += col.z * wgt;
+            } else {
+#pragma unroll
+                for (int d = 0; d < DM; d++) Cacc[d] += s_feat[d * kBatch + e] * wgt;
+                Wacc += wgt;
+            }
             T = comp ? Tn : T;
             last = comp ? b0 + e : last;
             if (kCount) ncomp += comp ? 1 : 0;
@@ -118,11 +141,16 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     }
     if (!inside) return;
     const int64_t pix = ci.pix_off + (int64_t)yi * ci.W + xi;
-    float bg0 = 0.0f, bg1 = 0.0f, bg2 = 0.0f;
-    if (a.background) { bg0 = a.background[3 * c]; bg1 = a.background[3 * c + 1]; bg2 = a.background[3 * c + 2]; }
-    a.image[3 * pix] = C0 + T * bg0;
-    a.image[3 * pix + 1] = C1 + T * bg1;
-    a.image[3 * pix + 2] = C2 + T * bg2;
+    const int D = kRGB ? 3 : a.D, Dt = kRGB ? 3 : a.Dt;
+#pragma unroll
+    for (int d = 0; d < DM; d++) {
+        if (d < D) {
+            a.image[(int64_t)Dt * pix + d] = Cacc[d] + T * (a.background ? a.background[D * c + d] : 0.0f);
+        } else if (d < Dt) {                         // depth: no background; expected depth divides by sum alpha T
+            a.image[(int64_t)Dt * pix + d] =
+                a.p.render_depth == GSR_DEPTH_EXPECTED ? (Wacc > 0.0f ? Cacc[d] / Wacc : 0.0f) : Cacc[d];
+        }
+    }
     a.alpha[pix] = 1.0f - T;
     a.final_T[pix] = T;
     a.last_ids[pix] = last;
@@ -137,15 +165,24 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
 
 size_t pack_workspace_bytes(int64_t cn) { return ((size_t)(cn > 0 ? cn : 1) * sizeof(PackedGauss) + 255) & ~(size_t)255; }
 
-int launch_pack(const gsr_params &p, int CN, int N, const float *means2d, const float *conics, const float *colors,
-                const float *opacities, const float *comps, PackedGauss *out, hipStream_t s) {
-    pack_kernel<<<dim3((unsigned)((CN + 255) / 256)), dim3(256), 0, s>>>(CN, N, p.alpha_min, means2d, conics, colors,
-                                                                        opacities, comps, out);
+int launch_pack(const gsr_params &p, int CN, int N, int D, const float *means2d, const float *conics,
+                const float *colors, const float *opacities, const float *comps, PackedGauss *out, hipStream_t s) {
+    pack_kernel<<<dim3((unsigned)((CN + 255) / 256)), dim3(256), 0, s>>>(
+        CN, N, channel_capacity(p, D) == 3, p.colors_shared != 0, p.alpha_min, means2d, conics, colors, opacities,
+        comps, out);
     return launch_check("pack");
 }
 
-int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
-                         const float *conics, const float *colors, const float *opacities,
+int composited_channels(const gsr_params &p, int D) { return D + (p.render_depth != GSR_DEPTH_NONE ? 1 : 0); }
+
+int channel_capacity(const gsr_params &p, int D) {
+    if (D == 3 && p.render_depth == GSR_DEPTH_NONE) return 3;
+    const int Dt = composited_channels(p, D);
+    return Dt <= 4 ? 4 : Dt <= 8 ? 8 : Dt <= 16 ? 16 : 32;
+}
+
+int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, int D, const float *means2d,
+                         const float *conics, const float *colors, const float *depths, const float *opacities,
                          const float *comps, const float *background, const int32_t *ranges,
                          const int32_t *ids, float *image, float *alpha, float *final_T, int32_t *last_ids,
                          int32_t *n_eval, void *ws, hipStream_t s) {
@@ -153,14 +190,23 @@ int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, const
     const int CN = cams.C * N;
     PackedGauss *gauss = (PackedGauss *)ws;
     if (CN > 0) {
-        int rc = launch_pack(p, CN, N, means2d, conics, colors, opacities, p.antialiased ? comps : nullptr, gauss, s);
+        int rc = launch_pack(p, CN, N, D, means2d, conics, colors, opacities, p.antialiased ? comps : nullptr,
+                             gauss, s);
         if (rc != GSR_OK) return rc;
     }
-    RasterArgs a{p, N, CN, gauss, background, ranges, ids, image, alpha, final_T, last_ids, n_eval};
-    if (n_eval)
-        raster_fwd_kernel<true><<<dim3((unsigned)cams.total_tiles), dim3(kThreads), 0, s>>>(a, cams);
-    else
-        raster_fwd_kernel<false><<<dim3((unsigned)cams.total_tiles), dim3(kThreads), 0, s>>>(a, cams);
+    RasterArgs a{p, N, CN, D, composited_channels(p, D), colors, depths, gauss, background, ranges, ids, image,
+                 alpha, final_T, last_ids, n_eval};
+    const dim3 grid((unsigned)cams.total_tiles), block(kThreads);
+#define GSR_RF(DM) do { if (n_eval) raster_fwd_kernel<true, DM><<<grid, block, 0, s>>>(a, cams); \
+                        else raster_fwd_kernel<false, DM><<<grid, block, 0, s>>>(a, cams); } while (0)
+    switch (channel_capacity(p, D)) {
+        case 3: GSR_RF(3); break;
+        case 4: GSR_RF(4); break;
+        case 8: GSR_RF(8); break;
+        case 16: GSR_RF(16); break;
+        default: GSR_RF(32); break;
+    }
+#undef GSR_RF
     return launch_check("rasterize_fwd");
 }
 

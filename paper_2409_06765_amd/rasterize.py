@@ -15,8 +15,24 @@ import torch
 from . import _lib as L
 
 
-def make_params(sh_degree=-1, antialiased=False, **kw):
-    return L.default_params(sh_degree=int(sh_degree), antialiased=int(bool(antialiased)), **kw)
+DEPTH_MODES = {"none": L.GSR_DEPTH_NONE, "accumulated": L.GSR_DEPTH_ACCUMULATED, "expected": L.GSR_DEPTH_EXPECTED}
+RENDER_MODES = {"RGB": (True, "none"), "D": (False, "accumulated"), "ED": (False, "expected"),
+                "RGB+D": (True, "accumulated"), "RGB+ED": (True, "expected")}
+
+
+def make_params(sh_degree=-1, antialiased=False, render_depth="none", **kw):
+    """Library parameters; ``render_depth`` is "none", "accumulated" or
+    "expected" (a depth channel after the features)."""
+    return L.default_params(sh_degree=int(sh_degree), antialiased=int(bool(antialiased)),
+                            render_depth=DEPTH_MODES[render_depth] if isinstance(render_depth, str)
+                            else int(render_depth), **kw)
+
+
+def _with(p, **fields):
+    q = L.gsr_params.from_buffer_copy(p)
+    for k, v in fields.items():
+        setattr(q, k, v)
+    return q
 
 
 def _dev(t):
@@ -41,12 +57,14 @@ def layout(W, H, tile=16):
 
 
 def project(p, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H, stream=None):
+    """Projection; ``sh_or_colors`` None (direct colours only) skips the colour
+    output: the rasterizer then takes features of its own."""
     C, N = viewmats.shape[0], means.shape[0]
     d = _dev(means)
     f = dict(device=d, dtype=torch.float32)
     out = dict(means2d=torch.empty((C, N, 2), **f), conics=torch.empty((C, N, 3), **f),
                radii=torch.empty((C, N), device=d, dtype=torch.int32), depths=torch.empty((C, N), **f),
-               colors=torch.empty((C, N, 3), **f),
+               colors=torch.empty((C, N, 3), **f) if sh_or_colors is not None else None,
                comps=torch.empty((C, N), **f) if p.antialiased else None)
     L.gsr_project_fwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors, viewmats, Ks,
                       out["means2d"], out["conics"], out["radii"], out["depths"], out["colors"], out["comps"],
@@ -195,41 +213,81 @@ def raster_workspace(C, N, device):
     return torch.empty(max(L.workspace_bytes(L.GSR_OP_RASTERIZE, C, N, 0), 1), device=device, dtype=torch.uint8)
 
 
-def rasterize_forward(p, proj, opacities, isect, W, H, background=None, n_eval=False, stream=None):
+def _features(p, proj, features):
+    """(params, D, feature tensor) for the rasterizer: the projected colours
+    [C,N,3] by default, else ``features`` [C,N,D] or [N,D] (shared by all
+    cameras); D = 0 (a [..,0] tensor) renders the depth channel alone."""
+    if features is None:
+        if proj.get("colors") is None:
+            raise ValueError("no projected colours: pass features")
+        return _with(p, colors_shared=0), 3, proj["colors"]
+    C, N = proj["radii"].shape
+    if features.dim() == 2 and features.shape[0] == N:
+        shared = 1
+    elif features.dim() == 3 and tuple(features.shape[:2]) == (C, N):
+        shared = 0
+    else:
+        raise ValueError(f"features must be [N,D] or [C,N,D] with N={N}, C={C}; got {tuple(features.shape)}")
+    D = int(features.shape[-1])
+    if not features.is_contiguous():
+        raise ValueError("features must be contiguous")
+    return _with(p, colors_shared=shared), D, (features if D > 0 else None)
+
+
+def channels(p, D):
+    """Channels of the rendered image: D features plus the depth channel."""
+    return D + (1 if p.render_depth != L.GSR_DEPTH_NONE else 0)
+
+
+def rasterize_forward(p, proj, opacities, isect, W, H, background=None, n_eval=False, features=None, stream=None):
+    """Composite the sorted lists.  Returns image [P, Dt] (D feature channels,
+    then depth when ``p.render_depth`` is set), alpha, final_T, last_ids, the
+    optional per-pixel counts and the workspace holding the packed records."""
     C, N = proj["radii"].shape
     d = proj["radii"].device
+    pf, D, feat = _features(p, proj, features)
     pix_off, _ = layout(W, H)
     P = pix_off[-1]
     f = dict(device=d, dtype=torch.float32)
-    out = dict(image=torch.empty((P, 3), **f), alpha=torch.empty(P, **f), final_T=torch.empty(P, **f),
+    out = dict(image=torch.empty((P, channels(p, D)), **f), alpha=torch.empty(P, **f), final_T=torch.empty(P, **f),
                last_ids=torch.empty(P, device=d, dtype=torch.int32),
                n_eval=torch.empty((P, 2), device=d, dtype=torch.int32) if n_eval else None)
     # the workspace keeps the packed per-Gaussian records for the backward
     out["ws"] = raster_workspace(C, N, d)
-    L.gsr_rasterize_fwd(p, C, N, W, H, proj["means2d"], proj["conics"], proj["colors"], opacities,
+    L.gsr_rasterize_fwd(pf, C, N, D, W, H, proj["means2d"], proj["conics"], feat, proj["depths"], opacities,
                         proj["comps"], background, isect["ranges"], isect["ids_buf"], out["image"], out["alpha"],
                         out["final_T"], out["last_ids"], out["n_eval"], ws=out["ws"], stream=stream)
     return out
 
 
-def grad_buffers(C, N, device, absgrad=False):
+def grad_buffers(C, N, device, absgrad=False, D=3, shared=False, depth=False):
     """Zeroed per-camera gradient buffers of the compositing backward, carved
-    from one allocation (one fill)."""
+    from one allocation (one fill): v_colors is [N,D] for shared features,
+    else [C,N,D]; v_depths [C,N] when depth is rendered."""
     n = C * N
-    flat = torch.zeros(n * (11 if absgrad else 9), device=device, dtype=torch.float32)
-    return dict(v_means2d=flat[:2 * n].view(C, N, 2), v_conics=flat[2 * n:5 * n].view(C, N, 3),
-                v_colors=flat[5 * n:8 * n].view(C, N, 3), v_opacities=flat[8 * n:9 * n].view(C, N),
-                v_means2d_abs=flat[9 * n:11 * n].view(C, N, 2) if absgrad else None)
+    nf = (N if shared else n) * D
+    sizes = dict(v_means2d=2 * n, v_conics=3 * n, v_colors=nf, v_opacities=n, v_depths=n if depth else 0,
+                 v_means2d_abs=2 * n if absgrad else 0)
+    flat = torch.zeros(sum(sizes.values()), device=device, dtype=torch.float32)
+    shapes = dict(v_means2d=(C, N, 2), v_conics=(C, N, 3), v_colors=(N, D) if shared else (C, N, D),
+                  v_opacities=(C, N), v_depths=(C, N), v_means2d_abs=(C, N, 2))
+    out, o = {}, 0
+    for k, m in sizes.items():
+        out[k] = flat[o:o + m].view(shapes[k]) if (m or k == "v_colors") else None
+        o += m
+    return out
 
 
 def rasterize_backward(p, proj, opacities, isect, W, H, fwd, v_image, v_alpha=None, background=None,
-                       absgrad=False, grads=None, stream=None):
+                       absgrad=False, grads=None, features=None, stream=None):
     """Gradients of the compositing.  ``grads`` (from ``grad_buffers``) are
     added to; by default fresh zeroed buffers are used.  The records the
     forward packed into its workspace are reused."""
     C, N = proj["radii"].shape
     d = proj["radii"].device
-    g = grad_buffers(C, N, d, absgrad) if grads is None else grads
+    pf, D, feat = _features(p, proj, features)
+    depth = p.render_depth != L.GSR_DEPTH_NONE
+    g = grad_buffers(C, N, d, absgrad, D, bool(pf.colors_shared), depth) if grads is None else grads
     if absgrad and g["v_means2d_abs"] is None:
         raise ValueError("absgrad needs grad buffers made with absgrad=True")
     ws = fwd.get("ws")
@@ -238,97 +296,123 @@ def rasterize_backward(p, proj, opacities, isect, W, H, fwd, v_image, v_alpha=No
         ws = raster_workspace(C, N, d)
     else:
         flags |= L.GSR_BWD_PACKED
-    L.gsr_rasterize_bwd(p, C, N, W, H, proj["means2d"], proj["conics"], proj["colors"], opacities, proj["comps"],
-                        background, isect["ranges"], isect["ids_buf"], fwd["final_T"], fwd["last_ids"], v_image,
-                        v_alpha, g["v_means2d"], g["v_conics"], g["v_colors"], g["v_opacities"],
+    L.gsr_rasterize_bwd(pf, C, N, D, W, H, proj["means2d"], proj["conics"], feat, proj["depths"], opacities,
+                        proj["comps"], background, isect["ranges"], isect["ids_buf"], fwd["image"], fwd["final_T"],
+                        fwd["last_ids"], v_image, v_alpha, g["v_means2d"], g["v_conics"],
+                        g["v_colors"] if D > 0 else None, g["v_depths"] if depth else None, g["v_opacities"],
                         g["v_means2d_abs"] if absgrad else None, ws=ws, flags=flags, stream=stream)
     return g
 
 
 def project_backward(p, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H, proj, g2,
                      v_depths=None, viewmat_grad=False, stream=None):
-    """Gradients of the projection; ``viewmat_grad`` adds "v_viewmats" [C,4,4]."""
+    """Gradients of the projection; ``viewmat_grad`` adds "v_viewmats" [C,4,4].
+    ``sh_or_colors`` None: the colours did not come from the projection (the
+    rasterizer took features of its own), so none are differentiated here.
+    The depth gradient is ``v_depths`` or, by default, the depth channel's."""
     C, N = viewmats.shape[0], means.shape[0]
     d = means.device
+    colour = sh_or_colors is not None
+    if v_depths is None:
+        v_depths = g2.get("v_depths")
     out = dict(v_means=torch.empty_like(means), v_quats=torch.empty_like(quats), v_scales=torch.empty_like(scales),
-               v_opacities=torch.empty_like(opacities), v_sh=torch.empty_like(sh_or_colors),
+               v_opacities=torch.empty_like(opacities), v_sh=torch.empty_like(sh_or_colors) if colour else None,
                v_viewmats=torch.empty((C, 4, 4), device=d, dtype=torch.float32) if viewmat_grad else None)
     ws = None
     if viewmat_grad:
         ws = torch.empty(max(L.workspace_bytes(L.GSR_OP_PROJECT_BWD, C, N, 0), 1), device=d, dtype=torch.uint8)
     L.gsr_project_bwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, proj["radii"],
-                      proj["comps"], g2["v_means2d"], g2["v_conics"], g2["v_colors"], g2["v_opacities"], v_depths,
-                      out["v_means"], out["v_quats"], out["v_scales"], out["v_opacities"], out["v_sh"],
-                      v_viewmats=out["v_viewmats"], ws=ws, stream=stream)
+                      proj["comps"], g2["v_means2d"], g2["v_conics"], g2["v_colors"] if colour else None,
+                      g2["v_opacities"], v_depths, out["v_means"], out["v_quats"], out["v_scales"],
+                      out["v_opacities"], out["v_sh"], v_viewmats=out["v_viewmats"], ws=ws, stream=stream)
     return out
 
 
 class RasterizeGaussians(torch.autograd.Function):
-    """(means, quats, scales, opacities, sh_or_colors) -> (image [P,3], alpha [P]);
-    viewmats, Ks and background are constants."""
+    """(means, quats, scales, opacities, colors, viewmats) -> (image [P,Dt], alpha [P]).
+    ``sh``: colors are SH coefficients [N,K,3] that the projection evaluates
+    per view; otherwise features [N,D] or [C,N,D] composited as they are.
+    Ks and background are constants."""
 
     @staticmethod
-    def forward(ctx, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, background, p, W, H, absgrad,
+    def forward(ctx, means, quats, scales, opacities, colors, viewmats, Ks, background, p, W, H, absgrad, sh,
                 meta):
-        means, quats, scales, opacities, sh_or_colors, viewmats = (t.contiguous() for t in
-                                                                   (means, quats, scales, opacities, sh_or_colors,
-                                                                    viewmats))
-        proj = project(p, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H)
+        means, quats, scales, opacities, colors, viewmats = (t.contiguous() for t in
+                                                             (means, quats, scales, opacities, colors, viewmats))
+        feats = None if sh else colors
+        proj = project(p, means, quats, scales, opacities, colors if sh else None, viewmats, Ks, W, H)
         isect = intersect(p, proj, W, H)
-        fwd = rasterize_forward(p, proj, opacities, isect, W, H, background)
+        fwd = rasterize_forward(p, proj, opacities, isect, W, H, background, features=feats)
         if isect.check():            # the list capacity was too small: composite the rebuilt lists
-            fwd = rasterize_forward(p, proj, opacities, isect, W, H, background)
-        ctx.p, ctx.W, ctx.H, ctx.absgrad = p, W, H, absgrad
+            fwd = rasterize_forward(p, proj, opacities, isect, W, H, background, features=feats)
+        ctx.p, ctx.W, ctx.H, ctx.absgrad, ctx.sh = p, W, H, absgrad, sh
         ctx.proj, ctx.isect, ctx.fwd = proj, isect, fwd
-        ctx.save_for_backward(means, quats, scales, opacities, sh_or_colors, viewmats, Ks, background)
+        ctx.save_for_backward(means, quats, scales, opacities, colors, viewmats, Ks, background)
         ctx.meta = meta
         meta.update(radii=proj["radii"], means2d=proj["means2d"], depths=proj["depths"], conics=proj["conics"],
-                    colors=proj["colors"], n_intersections=isect["M"],
+                    colors=proj["colors"] if sh else colors, n_intersections=isect["M"],
                     last_ids=fwd["last_ids"], final_T=fwd["final_T"])
         return fwd["image"], fwd["alpha"]
 
     @staticmethod
     def backward(ctx, v_image, v_alpha):
-        means, quats, scales, opacities, sh, viewmats, Ks, background = ctx.saved_tensors
-        p, W, H = ctx.p, ctx.W, ctx.H
+        means, quats, scales, opacities, colors, viewmats, Ks, background = ctx.saved_tensors
+        p, W, H, sh = ctx.p, ctx.W, ctx.H, ctx.sh
         v_image = torch.zeros_like(ctx.fwd["image"]) if v_image is None else v_image.contiguous()
         v_alpha = None if v_alpha is None else v_alpha.contiguous()
         g2 = rasterize_backward(p, ctx.proj, opacities, ctx.isect, W, H, ctx.fwd, v_image, v_alpha, background,
-                                absgrad=ctx.absgrad)
+                                absgrad=ctx.absgrad, features=None if sh else colors)
         if ctx.absgrad:
             ctx.meta["means2d_absgrad"] = g2["v_means2d_abs"]
         want_vm = ctx.needs_input_grad[5]
-        g3 = project_backward(p, means, quats, scales, opacities, sh, viewmats, Ks, W, H, ctx.proj, g2,
-                              viewmat_grad=want_vm)
-        return (g3["v_means"], g3["v_quats"], g3["v_scales"], g3["v_opacities"], g3["v_sh"],
-                g3["v_viewmats"] if want_vm else None, None, None, None, None, None, None, None)
+        g3 = project_backward(p, means, quats, scales, opacities, colors if sh else None, viewmats, Ks, W, H,
+                              ctx.proj, g2, viewmat_grad=want_vm)
+        v_colors = g3["v_sh"] if sh else g2["v_colors"]
+        return (g3["v_means"], g3["v_quats"], g3["v_scales"], g3["v_opacities"], v_colors,
+                g3["v_viewmats"] if want_vm else None, None, None, None, None, None, None, None, None)
 
 
 def rasterization(means, quats, scales, opacities, colors, viewmats, Ks, width, height, sh_degree=None,
-                  background=None, absgrad=False, antialiased=False, **params):
+                  background=None, absgrad=False, antialiased=False, render_mode="RGB", **params):
     """Render C views of N Gaussians (scales and opacities already activated).
 
-    colors: [N,3] direct colours, or [N,K,3] SH coefficients with K = (d+1)^2
-    (``sh_degree`` defaults to the largest degree K holds).  Returns
-    (image [C,H,W,3], alpha [C,H,W,1], meta); views of different sizes are
-    returned packed, as [P,3] and [P,1], when width/height are sequences.
+    colors: SH coefficients [N,K,3] with K = (d+1)^2, evaluated per view
+    (``sh_degree`` defaults to the largest degree K holds); or, with
+    ``sh_degree`` None, features [N,D] (shared by all views) or [C,N,D]
+    composited as they are (D <= 32; D = 3 is plain RGB).
+    render_mode: "RGB" (the colours or features), "D" / "ED" (accumulated /
+    expected depth alone), "RGB+D" / "RGB+ED" (features, then depth).
+    background: [D] or [C,D] for the feature channels (depth has none).
+    Returns (render [C,H,W,Dt], alpha [C,H,W,1], meta); views of different
+    sizes are returned packed, as [P,Dt] and [P,1], when width/height are
+    sequences.
     """
-    C = viewmats.shape[0]
-    if colors.dim() == 3:
-        deg = int(math.isqrt(colors.shape[1])) - 1 if sh_degree is None else int(sh_degree)
+    C, N = viewmats.shape[0], means.shape[0]
+    if render_mode not in RENDER_MODES:
+        raise ValueError(f"render_mode must be one of {sorted(RENDER_MODES)}")
+    want_feat, depth = RENDER_MODES[render_mode]
+    colors = colors.float()
+    if not want_feat:                                  # depth alone: no feature channels
+        sh, deg, colors = False, -1, torch.zeros((N, 0), device=means.device, dtype=torch.float32)
+    elif sh_degree is not None:
+        sh, deg = True, int(sh_degree)
+    elif colors.dim() == 3 and tuple(colors.shape[:2]) != (C, N):
+        sh, deg = True, int(math.isqrt(colors.shape[1])) - 1
     else:
-        deg = -1
-    p = make_params(sh_degree=deg, antialiased=antialiased, **params)
+        sh, deg = False, -1
+    p = make_params(sh_degree=deg, antialiased=antialiased, render_depth=depth, **params)
     W, H = _sizes_per_cam(C, width, height)
+    D = 3 if sh else int(colors.shape[-1])
     bg = None
-    if background is not None:
-        bg = background.to(torch.float32).reshape(-1, 3).expand(C, 3).contiguous()
-    meta = dict(width=W, height=H, sh_degree=deg)
-    image, alpha = RasterizeGaussians.apply(means.float(), quats.float(), scales.float(), opacities.float(),
-                                            colors.float(), viewmats.float().contiguous(), Ks.float().contiguous(),
-                                            bg, p, W, H, absgrad, meta)
+    if background is not None and D > 0:
+        bg = background.to(torch.float32).reshape(-1, D).expand(C, D).contiguous()
+    meta = dict(width=W, height=H, sh_degree=deg, render_mode=render_mode)
+    image, alpha = RasterizeGaussians.apply(means.float(), quats.float(), scales.float(), opacities.float(), colors,
+                                            viewmats.float().contiguous(), Ks.float().contiguous(), bg, p, W, H,
+                                            absgrad, sh, meta)
+    Dt = image.shape[-1]
     if len(set(W)) == 1 and len(set(H)) == 1:
-        image = image.view(C, H[0], W[0], 3)
+        image = image.view(C, H[0], W[0], Dt)
         alpha = alpha.view(C, H[0], W[0], 1)
     else:
         alpha = alpha.view(-1, 1)

@@ -138,10 +138,10 @@ def test_backward_flags_overwrite_repack_and_accumulate():
     ws = R.raster_workspace(C, N, vi.device)      # fresh workspace: must be packed again
 
     def call(g, ws, flags):
-        L.gsr_rasterize_bwd(p, C, N, st["W"], st["H"], pr["means2d"], pr["conics"], pr["colors"], d["opacities"],
-                            pr["comps"], None, st["isect"]["ranges"], st["isect"]["ids_buf"], fw["final_T"],
-                            fw["last_ids"], vi, va, g["v_means2d"], g["v_conics"], g["v_colors"], g["v_opacities"],
-                            g["v_means2d_abs"], ws=ws, flags=flags)
+        L.gsr_rasterize_bwd(p, C, N, 3, st["W"], st["H"], pr["means2d"], pr["conics"], pr["colors"], None,
+                            d["opacities"], pr["comps"], None, st["isect"]["ranges"], st["isect"]["ids_buf"], None,
+                            fw["final_T"], fw["last_ids"], vi, va, g["v_means2d"], g["v_conics"], g["v_colors"], None,
+                            g["v_opacities"], g["v_means2d_abs"], ws=ws, flags=flags)
 
     call(junk, ws, 0)
     torch.cuda.synchronize()
