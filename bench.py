@@ -190,7 +190,7 @@ def main():
     achieved = bwd_flops / (bwd_ms * 1e-3) / 1e12
     fwd_flops = (FLOPS_EVAL * E_fwd + FLOPS_FWD_COMP * C_tot) / args.steps
     fwd_tflops = fwd_flops / (stage_ms["rasterize_fwd"] * 1e-3) / 1e12
-    roofline = {"kernel": "raster_bwd_kernel", "bound": "alu", "achieved": round(achieved, 3),
+    roofline = {"kernel": "raster_bwd_rgb_kernel", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                 "traffic": measured_traffic() if args.workload == "clusters1m_sh3_1080p" else None}
 

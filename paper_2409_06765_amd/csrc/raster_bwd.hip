@@ -14,6 +14,11 @@
 // in bit 0, 1 and 2), three more finish the sums, so lane i ends up with the
 // total of value i & 7.  Lanes 0..8 (0..10 with the absolute mean gradient)
 // then issue one hardware float atomic instruction.
+//
+// Plain RGB runs raster_bwd_rgb_kernel, one wave per tile with four pixels
+// per lane (one per quad), which sums each entry's gradients over the quads
+// it reaches before that reduction; other channel sets run
+// raster_bwd_kernel, four waves per tile, a quad each.
 #include "common.hpp"
 
 namespace gsr {
@@ -290,6 +295,173 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
     }
 }
 
+// Plain RGB: one wave per 16x16 tile.  Lane l owns pixel (l & 7, l >> 3) of
+// each of the four 8x8 quads, so an entry's per-pixel gradients are first
+// summed in registers over the quads it reaches (its quad mask is uniform
+// across the wave) and then reduced and added to memory once per (tile,
+// entry) instead of once per (quad, entry): fewer butterfly reductions and
+// fewer atomics for the same per-pixel work.  Batches of 64 entries are
+// staged in LDS; entries that reach no quad (or only quads past their last
+// composited entry) are dropped from the batch's list at staging time.
+constexpr int kTileBatch = 64;
+
+__global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, CamTable cams) {
+    __shared__ float4 s_xyo[kTileBatch];
+    __shared__ float4 s_con[kTileBatch];
+    __shared__ float4 s_col[kTileBatch];
+    __shared__ int32_t s_id[kTileBatch];
+    __shared__ uint8_t s_qm[kTileBatch];
+    __shared__ uint8_t s_list[kTileBatch];
+
+    const int tile = blockIdx.x;
+    const int c = camera_of_tile(cams, tile);
+    const CamInfo ci = cams.cam[c];
+    const int lt = tile - ci.tile_base;
+    const int ty = lt / ci.TX, tx = lt - ty * ci.TX;
+    const int lane = threadIdx.x;
+    const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
+    // pixel centre of this lane in quad 0; quad q adds (8 (q & 1), 8 (q >> 1))
+    const float px0 = tile_x0 + (float)(lane & 7) + 0.5f, py0 = tile_y0 + (float)(lane >> 3) + 0.5f;
+    const int start = a.ranges[2 * tile];
+    const float amin = a.p.alpha_min, amax = __builtin_canonicalizef(a.p.alpha_max);
+
+    // per pixel (one per quad): T restored back to front, SV = S . v_C, v_alpha final_T, v_C, last index
+    float T[4], SV[4], vATf[4], vC[4][3];
+    int last[4], qlast[4];
+    int stop = -1;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int xi = tx * kTile + (q & 1) * 8 + (lane & 7), yi = ty * kTile + (q >> 1) * 8 + (lane >> 3);
+        T[q] = 1.0f; SV[q] = 0.0f; vATf[q] = 0.0f; vC[q][0] = vC[q][1] = vC[q][2] = 0.0f;
+        last[q] = -1;
+        if (xi < ci.W && yi < ci.H) {
+            const int64_t pix = ci.pix_off + (int64_t)yi * ci.W + xi;
+            last[q] = a.last_ids[pix];
+            const float Tf = a.final_T[pix];
+            T[q] = Tf;
+            vC[q][0] = a.v_image[3 * pix]; vC[q][1] = a.v_image[3 * pix + 1]; vC[q][2] = a.v_image[3 * pix + 2];
+            if (a.v_alpha) vATf[q] = a.v_alpha[pix] * Tf;
+            if (a.background) {
+                const float *bg = a.background + 3 * c;
+                SV[q] = Tf * ((bg[0] * vC[q][0] + bg[1] * vC[q][1]) + bg[2] * vC[q][2]);
+            }
+        }
+        int m = last[q];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) m = max(m, __shfl_xor(m, d, kWave));
+        qlast[q] = __builtin_amdgcn_readfirstlane(m);       // largest last index of quad q
+        stop = max(stop, qlast[q]);
+    }
+    const bool want_abs = a.v_means2d_abs != nullptr;
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+    const int nslots = want_abs ? 11 : 9;
+    float *dst_base = nullptr;
+    int dst_mul = 0;
+    bool dst_by_n = false;
+    if (lane < 2) { dst_base = a.v_means2d + lane; dst_mul = 2; }
+    else if (lane < 5) { dst_base = a.v_conics + (lane - 2); dst_mul = 3; }
+    else if (lane < 8) { dst_base = a.v_colors + (lane - 5); dst_mul = 3; dst_by_n = a.p.colors_shared != 0; }
+    else if (lane == 8) { dst_base = a.v_opac; dst_mul = 1; }
+    else if (lane < 11 && want_abs) { dst_base = a.v_means2d_abs + (lane - 9); dst_mul = 2; }
+    const int cam_base = c * a.N;
+
+    for (int hi = stop + 1; hi > start; hi -= kTileBatch) {
+        const int base = max(start, hi - kTileBatch);
+        const int k = base + lane;
+        uint32_t qm = 0u;
+        if (k < hi) {
+            int g = a.ids[k];
+            if ((unsigned)g >= (unsigned)a.CN) g = 0;   // ids come from the sort; this only bounds a bad input
+            const PackedGauss r = a.gauss[g];
+            qm = refine_quad_mask(quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0), r.xyoh,
+                                  r.conh, r.col.w, tile_x0, tile_y0);
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (k > qlast[q]) qm &= ~(1u << q);      // past every pixel of the quad's last entry
+            s_xyo[lane] = r.xyoh;
+            s_con[lane] = r.conh;
+            s_col[lane] = r.col;
+            s_id[lane] = g;
+        }
+        s_qm[lane] = (uint8_t)qm;
+        const uint64_t bal = __ballot(qm != 0u);
+        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        if (qm != 0u) s_list[__popcll(bal & below)] = (uint8_t)lane;
+        __syncthreads();
+        for (int j = __popcll(bal) - 1; j >= 0; j--) {
+            const int e = __builtin_amdgcn_readfirstlane(s_list[j]);
+            const int kk = base + e;
+            const uint32_t qme = __builtin_amdgcn_readfirstlane(s_qm[e]);
+            const float4 xyo = s_xyo[e];
+            const float4 con = s_con[e];
+            const float4 col = s_col[e];
+            // per-lane sums over this lane's pixels: mean x, y; conic a, b, c; colour r, g, b; opacity; |mean|
+            float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            float acc_o = 0.0f, acc_ax = 0.0f, acc_ay = 0.0f;
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                if (!((qme >> q) & 1u)) continue;                  // uniform
+                const float dx = xyo.x - (px0 + (float)((q & 1) * 8)), dy = xyo.y - (py0 + (float)((q >> 1) * 8));
+                const float sig = scaled_sigma(con, dx, dy);      // log2(e) sigma, as in the forward
+                const float ex = __builtin_amdgcn_exp2f(-sig);
+                const float araw = xyo.z * ex;
+                const float al = fminf(amax, araw);
+                const bool use = kk <= last[q] && sig >= 0.0f && al >= amin;
+                if (__ballot(use) == 0ull) continue;               // uniform
+                any = true;
+                const float inv = __builtin_amdgcn_rcpf(1.0f - al);
+                const float Tk = T[q] * inv;
+                const float wgt = use ? al * Tk : 0.0f;
+                const float cv = (col.x * vC[q][0] + col.y * vC[q][1]) + col.z * vC[q][2];
+                float v_al = fmaf(Tk, cv, inv * (vATf[q] - SV[q]));
+                SV[q] = fmaf(wgt, cv, SV[q]);
+                T[q] = use ? Tk : T[q];
+                v_al = (use && araw <= amax) ? v_al : 0.0f;       // clamped alpha: no gradient to o or sigma
+                const float v_sig = -araw * v_al;
+                const float h = 0.5f * v_sig;
+                const float u = v_sig * (1.0f / kLog2e);
+                const float g_mx = u * fmaf(2.0f * con.x, dx, con.y * dy);
+                const float g_my = u * fmaf(2.0f * con.z, dy, con.y * dx);
+                acc[0] += g_mx;
+                acc[1] += g_my;
+                acc[2] = fmaf(h * dx, dx, acc[2]);
+                acc[3] = fmaf(v_sig * dx, dy, acc[3]);
+                acc[4] = fmaf(h * dy, dy, acc[4]);
+                acc[5] = fmaf(wgt, vC[q][0], acc[5]);
+                acc[6] = fmaf(wgt, vC[q][1], acc[6]);
+                acc[7] = fmaf(wgt, vC[q][2], acc[7]);
+                acc_o = fmaf(ex, v_al, acc_o);
+                if (want_abs) { acc_ax += fabsf(g_mx); acc_ay += fabsf(g_my); }
+            }
+            if (!any) continue;
+            // transposing butterfly: 8 values -> lane holds the total of value (lane & 7)
+            const float w0 = bfly<kDppXor1>(acc[0], acc[1], b0);
+            const float w1 = bfly<kDppXor1>(acc[2], acc[3], b0);
+            const float w2 = bfly<kDppXor1>(acc[4], acc[5], b0);
+            const float w3 = bfly<kDppXor1>(acc[6], acc[7], b0);
+            const float x0 = bfly<kDppXor2>(w0, w1, b1);
+            const float x1 = bfly<kDppXor2>(w2, w3, b1);
+            float y = bfly<kDppRor4>(x0, x1, b2);
+            y += dpp<kDppRor8>(y);
+            y = add_xor32(add_xor16(y));
+            const float zo = wave_total(acc_o);
+            float val = lane < 8 ? y : zo;
+            if (want_abs) {
+                const float zx = wave_total(acc_ax), zy = wave_total(acc_ay);
+                val = lane == 9 ? zx : lane == 10 ? zy : val;
+            }
+            if (lane < nslots && dst_base) {
+                const int g = s_id[e];
+                int n = g - cam_base;
+                if ((unsigned)n >= (unsigned)a.N) n = 0;   // only a bad id can leave the tile's camera
+                unsafeAtomicAdd(dst_base + (int64_t)(dst_by_n ? n : g) * dst_mul, val);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D, const float *means2d,
@@ -323,7 +495,7 @@ int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D
                     v_means2d_abs};
     const dim3 grid((unsigned)cams.total_tiles), block(kThreads);
     switch (channel_capacity(p, D)) {
-        case 3: raster_bwd_kernel<3><<<grid, block, 0, s>>>(a, cams); break;
+        case 3: raster_bwd_rgb_kernel<<<grid, dim3(kWave), 0, s>>>(a, cams); break;
         case 4: raster_bwd_kernel<4><<<grid, block, 0, s>>>(a, cams); break;
         case 8: raster_bwd_kernel<8><<<grid, block, 0, s>>>(a, cams); break;
         case 16: raster_bwd_kernel<16><<<grid, block, 0, s>>>(a, cams); break;
