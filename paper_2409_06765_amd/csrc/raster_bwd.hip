@@ -364,6 +364,7 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
     else if (lane == 8) { dst_base = a.v_opac; dst_mul = 1; }
     else if (lane < 11 && want_abs) { dst_base = a.v_means2d_abs + (lane - 9); dst_mul = 2; }
     const int cam_base = c * a.N;
+    const float lscale = (lane == 2 || lane == 4) ? 0.5f : 1.0f;
 
     for (int hi = stop + 1; hi > start; hi -= kTileBatch) {
         const int base = max(start, hi - kTileBatch);
@@ -395,7 +396,10 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
             const float4 xyo = s_xyo[e];
             const float4 con = s_con[e];
             const float4 col = s_col[e];
-            // per-lane sums over this lane's pixels: mean x, y; conic a, b, c; colour r, g, b; opacity; |mean|
+            // Per-lane sums over this lane's pixels of v_sigma times (dx, dy, dx^2, dx dy, dy^2), of the
+            // colour gradients, of v_sigma, and of |dL/dmu'|: the conic and the opacity are the same for
+            // every pixel, so the mean gradient (d sigma / d mu' is linear in dx, dy) and the opacity
+            // gradient (v_sigma = -o e^-sigma dL/dalpha) follow from these sums after the reduction.
             float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             float acc_o = 0.0f, acc_ax = 0.0f, acc_ay = 0.0f;
             bool any = false;
@@ -419,20 +423,20 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
                 T[q] = use ? Tk : T[q];
                 v_al = (use && araw <= amax) ? v_al : 0.0f;       // clamped alpha: no gradient to o or sigma
                 const float v_sig = -araw * v_al;
-                const float h = 0.5f * v_sig;
-                const float u = v_sig * (1.0f / kLog2e);
-                const float g_mx = u * fmaf(2.0f * con.x, dx, con.y * dy);
-                const float g_my = u * fmaf(2.0f * con.z, dy, con.y * dx);
-                acc[0] += g_mx;
-                acc[1] += g_my;
-                acc[2] = fmaf(h * dx, dx, acc[2]);
-                acc[3] = fmaf(v_sig * dx, dy, acc[3]);
-                acc[4] = fmaf(h * dy, dy, acc[4]);
+                const float t = v_sig * dx, sy = v_sig * dy;
+                acc[0] += t;
+                acc[1] += sy;
+                acc[2] = fmaf(t, dx, acc[2]);
+                acc[3] = fmaf(t, dy, acc[3]);
+                acc[4] = fmaf(sy, dy, acc[4]);
                 acc[5] = fmaf(wgt, vC[q][0], acc[5]);
                 acc[6] = fmaf(wgt, vC[q][1], acc[6]);
                 acc[7] = fmaf(wgt, vC[q][2], acc[7]);
-                acc_o = fmaf(ex, v_al, acc_o);
-                if (want_abs) { acc_ax += fabsf(g_mx); acc_ay += fabsf(g_my); }
+                acc_o += v_sig;
+                if (want_abs) {                                   // per-pixel |dL/dmu'|, log2(e) folded in
+                    acc_ax += fabsf(fmaf(2.0f * con.x, t, con.y * sy));
+                    acc_ay += fabsf(fmaf(2.0f * con.z, sy, con.y * t));
+                }
             }
             if (!any) continue;
             // transposing butterfly: 8 values -> lane holds the total of value (lane & 7)
@@ -445,11 +449,15 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
             float y = bfly<kDppRor4>(x0, x1, b2);
             y += dpp<kDppRor8>(y);
             y = add_xor32(add_xor16(y));
-            const float zo = wave_total(acc_o);
-            float val = lane < 8 ? y : zo;
+            // lanes 0, 1: dL/dmu' = (2 A' S_dx + B' S_dy, B' S_dx + 2 C' S_dy) / log2(e) with the scaled
+            // conic (A', B', C'); lanes 2, 4: dL/da, dL/dc are half the dx^2, dy^2 moments
+            const float yo = dpp<kDppXor1>(y);            // lane 0 <-> lane 1
+            const float mean = fmaf(2.0f * (lane == 0 ? con.x : con.z), y, con.y * yo) * (1.0f / kLog2e);
+            const float zo = wave_total(acc_o) * -__builtin_amdgcn_rcpf(xyo.z);
+            float val = lane < 2 ? mean : lane < 8 ? y * lscale : zo;
             if (want_abs) {
                 const float zx = wave_total(acc_ax), zy = wave_total(acc_ay);
-                val = lane == 9 ? zx : lane == 10 ? zy : val;
+                val = lane == 9 ? zx * (1.0f / kLog2e) : lane == 10 ? zy * (1.0f / kLog2e) : val;
             }
             if (lane < nslots && dst_base) {
                 const int g = s_id[e];
