@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 4
+#define GSR_ABI_VERSION 5
 #define GSR_MAX_CAMERAS 64
 
 enum gsr_status {
@@ -90,7 +90,8 @@ enum gsr_op {
     GSR_OP_RASTERIZE = 3,         /* workspace of gsr_rasterize_fwd / _bwd, C*N       */
     GSR_OP_BIN_PREPARE = 4,       /* workspace kept from gsr_bin_prepare to _finish   */
     GSR_OP_BIN_FINISH = 5,        /* workspace of gsr_bin_finish for M intersections  */
-    GSR_OP_PROJECT_BWD = 6        /* workspace of gsr_project_bwd with v_viewmats     */
+    GSR_OP_PROJECT_BWD = 6,       /* workspace of gsr_project_bwd with v_viewmats     */
+    GSR_OP_TILE_ORDER = 7         /* workspace of gsr_tile_order                      */
 };
 
 /* Flags of gsr_rasterize_bwd. */
@@ -198,6 +199,16 @@ int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const in
                    int32_t *ids, int32_t *ranges, uint64_t *keys, void *ws_prep, size_t ws_prep_bytes,
                    void *ws_fin, size_t ws_fin_bytes, gsr_stream_t stream);
 
+/* Dispatch order for the compositing entry points: the tiles' indices
+ * sorted by the length of their lists (ranges [T,2] from gsr_tile_ranges or
+ * gsr_bin_finish), longest first, lengths grouped in buckets of an eighth of
+ * an octave (the order within a bucket is not fixed).  Launching the longest
+ * lists first keeps the GPU full until the end of a compositing pass; the
+ * images and gradients do not depend on the order.  order [T] int32 (output),
+ * ws of gsr_workspace_bytes(GSR_OP_TILE_ORDER, 0, 0, 0) bytes. */
+int gsr_tile_order(int32_t total_tiles, const int32_t *ranges, int32_t *order, void *ws, size_t ws_bytes,
+                   gsr_stream_t stream);
+
 /* Front-to-back compositing (Rasterization of Gaussians).  For every pixel
  * with centre p = (x + 0.5, y + 0.5), over its tile's sorted list:
  *   Delta = mu' - p;  sigma = 0.5 (a Dx^2 + c Dy^2) + b Dx Dy (skipped if < 0);
@@ -215,6 +226,9 @@ int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const in
  * channel takes the same alpha and T, so channels are independent.  Plain RGB
  * (D = 3, no depth) is the fastest case: the colours travel in the
  * per-Gaussian record; other channel sets are staged in LDS per batch.
+ * tile_order [T] (nullable): the order in which the tiles' blocks are
+ * launched, a permutation of 0 .. T-1 such as gsr_tile_order writes (NULL:
+ * tile index order; an index out of range skips that block).
  * Outputs: image [P,Dt], alpha [P] = 1 - T, final_T [P] = T, last_ids [P] int32
  * (position in the sorted list of the last composited entry, -1 if none),
  * n_eval [P,2] int32 (nullable): per pixel, the entries evaluated (including
@@ -223,9 +237,9 @@ int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const in
 int gsr_rasterize_fwd(const gsr_params *p, int C, int N, int D, const int32_t *W, const int32_t *H,
                       const float *means2d, const float *conics, const float *colors, const float *depths,
                       const float *opacities, const float *compensations, const float *background,
-                      const int32_t *ranges, const int32_t *ids, float *image, float *alpha,
-                      float *final_T, int32_t *last_ids, int32_t *n_eval, void *ws, size_t ws_bytes,
-                      gsr_stream_t stream);
+                      const int32_t *ranges, const int32_t *ids, const int32_t *tile_order, float *image,
+                      float *alpha, float *final_T, int32_t *last_ids, int32_t *n_eval, void *ws,
+                      size_t ws_bytes, gsr_stream_t stream);
 
 /* Depth Compositing Gradients.  Per pixel, from last_ids back to its tile's
  * start, recomputes alpha, restores T_k = T_{k+1} / (1 - alpha_k) from final_T,
@@ -240,7 +254,7 @@ int gsr_rasterize_fwd(const gsr_params *p, int C, int N, int D, const int32_t *W
  * Expected depth E = A / W (A the composited depth, W = sum alpha T = 1 -
  * final_T) passes v_E / W on to A and -v_E E / W to the alpha output; image
  * (the forward's output, [P,Dt]) supplies E and is read only in that mode.
- * Channels, p, D, colors and depths as in gsr_rasterize_fwd.  v_image
+ * Channels, p, D, colors, depths and tile_order as in gsr_rasterize_fwd.  v_image
  * [P,Dt], v_alpha [P] (nullable).  Outputs, overwritten: v_means2d [C,N,2],
  * v_conics [C,N,3], v_colors (shape of colors; NULL when D = 0), v_depths
  * [C,N] (depth channel; NULL unless depth is rendered), v_opacities [C,N]
@@ -260,8 +274,9 @@ int gsr_rasterize_fwd(const gsr_params *p, int C, int N, int D, const int32_t *W
 int gsr_rasterize_bwd(const gsr_params *p, int C, int N, int D, const int32_t *W, const int32_t *H,
                       const float *means2d, const float *conics, const float *colors, const float *depths,
                       const float *opacities, const float *compensations, const float *background,
-                      const int32_t *ranges, const int32_t *ids, const float *image, const float *final_T,
-                      const int32_t *last_ids, const float *v_image, const float *v_alpha,
+                      const int32_t *ranges, const int32_t *ids, const int32_t *tile_order,
+                      const float *image, const float *final_T, const int32_t *last_ids,
+                      const float *v_image, const float *v_alpha,
                       float *v_means2d, float *v_conics, float *v_colors, float *v_depths, float *v_opacities,
                       float *v_means2d_abs, void *ws, size_t ws_bytes, int flags, gsr_stream_t stream);
 

@@ -17,10 +17,11 @@ LIB_PATH = os.path.join(_PKG, "libgsraster.so")
 GSR_OK, GSR_EINVAL, GSR_EOVERFLOW, GSR_EWORKSPACE, GSR_EHIP = 0, 1, 2, 3, 4
 GSR_OP_INTERSECT_COUNT, GSR_OP_SORT, GSR_OP_RASTERIZE, GSR_OP_BIN_PREPARE, GSR_OP_BIN_FINISH = 1, 2, 3, 4, 5
 GSR_OP_PROJECT_BWD = 6
+GSR_OP_TILE_ORDER = 7
 GSR_MAX_CAMERAS = 64
 GSR_BWD_ACCUMULATE, GSR_BWD_PACKED = 1, 2
 GSR_DEPTH_NONE, GSR_DEPTH_ACCUMULATED, GSR_DEPTH_EXPECTED = 0, 1, 2
-ABI_VERSION = 4                 # the signatures below
+ABI_VERSION = 5                 # the signatures below
 _NAMES = {0: "GSR_OK", 1: "GSR_EINVAL", 2: "GSR_EOVERFLOW", 3: "GSR_EWORKSPACE", 4: "GSR_EHIP"}
 
 
@@ -52,8 +53,9 @@ _SIGS = {
     "gsr_tile_ranges": ([_i64, _vp, ctypes.c_int32, _vp, _vp], _i),
     "gsr_bin_prepare": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
     "gsr_bin_finish": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp, _sz, _vp], _i),
-    "gsr_rasterize_fwd": ([_P, _i, _i, _i, _vp, _vp] + [_vp] * 9 + [_vp] * 5 + [_vp, _sz, _vp], _i),
-    "gsr_rasterize_bwd": ([_P, _i, _i, _i, _vp, _vp] + [_vp] * 14 + [_vp] * 6 + [_vp, _sz, _i, _vp], _i),
+    "gsr_tile_order": ([ctypes.c_int32, _vp, _vp, _vp, _sz, _vp], _i),
+    "gsr_rasterize_fwd": ([_P, _i, _i, _i, _vp, _vp] + [_vp] * 10 + [_vp] * 5 + [_vp, _sz, _vp], _i),
+    "gsr_rasterize_bwd": ([_P, _i, _i, _i, _vp, _vp] + [_vp] * 15 + [_vp] * 6 + [_vp, _sz, _i, _vp], _i),
     "gsr_project_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 9 + [_vp] * 5 + [_vp] * 5 + [_vp, _vp, _sz, _vp], _i),
 }
 
@@ -190,25 +192,32 @@ def _ws(ws):
     return (_ptr(ws, None, "workspace"), ws.numel() * ws.element_size()) if ws is not None else (None, 0)
 
 
+def gsr_tile_order(total_tiles, ranges, order, ws, stream=None):
+    _check(lib().gsr_tile_order(int(total_tiles), _ptr(ranges, I32, "ranges"), _ptr(order, I32, "order"), *_ws(ws),
+                                _stream(stream)))
+
+
 def gsr_rasterize_fwd(p, C, N, D, W, H, means2d, conics, colors, depths, opacities, compensations, background,
-                      ranges, ids, image, alpha, final_T, last_ids, n_eval=None, ws=None, stream=None):
+                      ranges, ids, tile_order, image, alpha, final_T, last_ids, n_eval=None, ws=None, stream=None):
     _check(lib().gsr_rasterize_fwd(
         ctypes.byref(p), C, N, D, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(conics, F32, "conics"),
         _ptr(colors, F32, "colors"), _ptr(depths, F32, "depths"), _ptr(opacities, F32, "opacities"),
         _ptr(compensations, F32, "compensations"), _ptr(background, F32, "background"),
-        _ptr(ranges, I32, "ranges"), _ptr(ids, I32, "ids"), _ptr(image, F32, "image"), _ptr(alpha, F32, "alpha"),
+        _ptr(ranges, I32, "ranges"), _ptr(ids, I32, "ids"), _ptr(tile_order, I32, "tile_order"),
+        _ptr(image, F32, "image"), _ptr(alpha, F32, "alpha"),
         _ptr(final_T, F32, "final_T"), _ptr(last_ids, I32, "last_ids"), _ptr(n_eval, I32, "n_eval"), *_ws(ws),
         _stream(stream)))
 
 
 def gsr_rasterize_bwd(p, C, N, D, W, H, means2d, conics, colors, depths, opacities, compensations, background,
-                      ranges, ids, image, final_T, last_ids, v_image, v_alpha, v_means2d, v_conics, v_colors,
-                      v_depths, v_opacities, v_means2d_abs=None, ws=None, flags=0, stream=None):
+                      ranges, ids, tile_order, image, final_T, last_ids, v_image, v_alpha, v_means2d, v_conics,
+                      v_colors, v_depths, v_opacities, v_means2d_abs=None, ws=None, flags=0, stream=None):
     _check(lib().gsr_rasterize_bwd(
         ctypes.byref(p), C, N, D, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(conics, F32, "conics"),
         _ptr(colors, F32, "colors"), _ptr(depths, F32, "depths"), _ptr(opacities, F32, "opacities"),
         _ptr(compensations, F32, "compensations"), _ptr(background, F32, "background"),
-        _ptr(ranges, I32, "ranges"), _ptr(ids, I32, "ids"), _ptr(image, F32, "image"),
+        _ptr(ranges, I32, "ranges"), _ptr(ids, I32, "ids"), _ptr(tile_order, I32, "tile_order"),
+        _ptr(image, F32, "image"),
         _ptr(final_T, F32, "final_T"), _ptr(last_ids, I32, "last_ids"), _ptr(v_image, F32, "v_image"),
         _ptr(v_alpha, F32, "v_alpha"), _ptr(v_means2d, F32, "v_means2d"), _ptr(v_conics, F32, "v_conics"),
         _ptr(v_colors, F32, "v_colors"), _ptr(v_depths, F32, "v_depths"), _ptr(v_opacities, F32, "v_opacities"),

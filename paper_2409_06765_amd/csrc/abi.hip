@@ -115,6 +115,7 @@ size_t gsr_workspace_bytes(int op, int C, int N, int64_t M) {
         case GSR_OP_BIN_PREPARE: return bin_prepare_bytes((int64_t)(C > 0 ? C : 0) * (N > 0 ? N : 0));
         case GSR_OP_BIN_FINISH: return bin_finish_bytes(M > 0 ? M : 0);
         case GSR_OP_PROJECT_BWD: return pose_workspace_bytes(C > 0 ? C : 0, N > 0 ? N : 0);
+        case GSR_OP_TILE_ORDER: return tile_order_bytes();
         default: return 0;
     }
 }
@@ -204,6 +205,17 @@ int gsr_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_
     return launch_tile_ranges(M, keys, total_tiles, ranges, (hipStream_t)stream);
 }
 
+int gsr_tile_order(int32_t total_tiles, const int32_t *ranges, int32_t *order, void *ws, size_t ws_bytes,
+                   gsr_stream_t stream) {
+    static const char *fn = "gsr_tile_order";
+    if (total_tiles < 0) return fail(GSR_EINVAL, "%s: total_tiles < 0", fn);
+    if (total_tiles == 0) return GSR_OK;
+    GSR_NEED(ranges); GSR_NEED(order);
+    if (!ws || ws_bytes < tile_order_bytes())
+        return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed", fn, tile_order_bytes());
+    return launch_tile_order(total_tiles, ranges, order, ws, (hipStream_t)stream);
+}
+
 int gsr_bin_prepare(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
                     const float *means2d, const int32_t *radii, const float *depths,
                     int64_t *total_dev, int64_t *total_host, void *ws_prep, size_t ws_prep_bytes,
@@ -265,9 +277,9 @@ static int check_channels(const char *fn, const gsr_params *p, int D) {
 int gsr_rasterize_fwd(const gsr_params *p, int C, int N, int D, const int32_t *W, const int32_t *H,
                       const float *means2d, const float *conics, const float *colors, const float *depths,
                       const float *opacities, const float *compensations, const float *background,
-                      const int32_t *ranges, const int32_t *ids, float *image, float *alpha,
-                      float *final_T, int32_t *last_ids, int32_t *n_eval, void *ws, size_t ws_bytes,
-                      gsr_stream_t stream) {
+                      const int32_t *ranges, const int32_t *ids, const int32_t *tile_order, float *image,
+                      float *alpha, float *final_T, int32_t *last_ids, int32_t *n_eval, void *ws,
+                      size_t ws_bytes, gsr_stream_t stream) {
     static const char *fn = "gsr_rasterize_fwd";
     int rc = check_params(p);
     if (rc == GSR_OK) rc = check_channels(fn, p, D);
@@ -285,15 +297,17 @@ int gsr_rasterize_fwd(const gsr_params *p, int C, int N, int D, const int32_t *W
         if (!ws || ws_bytes < need)
             return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws ? ws_bytes : 0);
     }
-    return launch_rasterize_fwd(*p, cams, N, D, means2d, conics, colors, depths, opacities, compensations, background, ranges,
-                                ids, image, alpha, final_T, last_ids, n_eval, ws, (hipStream_t)stream);
+    return launch_rasterize_fwd(*p, cams, N, D, means2d, conics, colors, depths, opacities, compensations, background,
+                                ranges, ids, tile_order, image, alpha, final_T, last_ids, n_eval, ws,
+                                (hipStream_t)stream);
 }
 
 int gsr_rasterize_bwd(const gsr_params *p, int C, int N, int D, const int32_t *W, const int32_t *H,
                       const float *means2d, const float *conics, const float *colors, const float *depths,
                       const float *opacities, const float *compensations, const float *background,
-                      const int32_t *ranges, const int32_t *ids, const float *image, const float *final_T,
-                      const int32_t *last_ids, const float *v_image, const float *v_alpha,
+                      const int32_t *ranges, const int32_t *ids, const int32_t *tile_order,
+                      const float *image, const float *final_T, const int32_t *last_ids,
+                      const float *v_image, const float *v_alpha,
                       float *v_means2d, float *v_conics, float *v_colors, float *v_depths, float *v_opacities,
                       float *v_means2d_abs, void *ws, size_t ws_bytes, int flags, gsr_stream_t stream) {
     static const char *fn = "gsr_rasterize_bwd";
@@ -315,8 +329,8 @@ int gsr_rasterize_bwd(const gsr_params *p, int C, int N, int D, const int32_t *W
     if (!ws || ws_bytes < need)
         return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws ? ws_bytes : 0);
     return launch_rasterize_bwd(*p, cams, N, D, means2d, conics, colors, depths, opacities, compensations,
-                                background, ranges, ids, image, final_T, last_ids, v_image, v_alpha, v_means2d,
-                                v_conics, v_colors, v_depths, v_opacities, v_means2d_abs, ws, flags,
+                                background, ranges, ids, tile_order, image, final_T, last_ids, v_image, v_alpha,
+                                v_means2d, v_conics, v_colors, v_depths, v_opacities, v_means2d_abs, ws, flags,
                                 (hipStream_t)stream);
 }
 

@@ -59,6 +59,9 @@ int launch_sort_pairs(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uin
                       int32_t *ids_alt, void *ws, hipStream_t s);
 int launch_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_t *ranges, hipStream_t s);
 
+size_t tile_order_bytes();
+int launch_tile_order(int32_t T, const int32_t *ranges, int32_t *order, void *ws, hipStream_t s);
+
 size_t bin_prepare_bytes(int64_t n);
 size_t bin_finish_bytes(int64_t M);
 const int64_t *bin_total_ptr(void *ws_prep, int64_t n);
@@ -71,13 +74,15 @@ int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const fl
 int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, int D, const float *means2d,
                          const float *conics, const float *colors, const float *depths, const float *opacities,
                          const float *comps, const float *background, const int32_t *ranges,
-                         const int32_t *ids, float *image, float *alpha, float *final_T, int32_t *last_ids,
+                         const int32_t *ids, const int32_t *tile_order, float *image, float *alpha, float *final_T,
+                         int32_t *last_ids,
                          int32_t *n_eval, void *ws, hipStream_t s);
 
 int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D, const float *means2d,
                          const float *conics, const float *colors, const float *depths, const float *opacities,
                          const float *comps, const float *background, const int32_t *ranges,
-                         const int32_t *ids, const float *image, const float *final_T, const int32_t *last_ids,
+                         const int32_t *ids, const int32_t *tile_order, const float *image, const float *final_T,
+                         const int32_t *last_ids,
                          const float *v_image, const float *v_alpha, float *v_means2d, float *v_conics,
                          float *v_colors, float *v_depths, float *v_opac, float *v_means2d_abs, void *ws, int flags,
                          hipStream_t s);
@@ -86,6 +91,14 @@ int launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
 
 // ---- device helpers ----------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// The tile a compositing block works on: blockIdx.x through the dispatch
+// order when one is given; -1 (the block does nothing) for an index outside
+// the tile range.
+__device__ __forceinline__ int block_tile(const int32_t *order, int total_tiles) {
+    const int t = order ? order[blockIdx.x] : (int)blockIdx.x;
+    return (unsigned)t < (unsigned)total_tiles ? t : -1;
+}
 
 // Camera of a global tile id (linear scan; C is small and the value uniform).
 __device__ __forceinline__ int camera_of_tile(const CamTable &cams, int tile) {

@@ -509,6 +509,72 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__
     }
 }
 
+// ---- dispatch order of the compositing blocks ---------------------------------
+// Tiles sorted by list length, longest first, so that the blocks that run
+// longest start first and the short ones fill in behind them (longest
+// processing time first).  Lengths are grouped in buckets of an eighth of an
+// octave (bucket = 1 + 8 floor(log2 len) + the next three bits of len, 0 for
+// an empty list); the order within a bucket is whatever the atomics give.
+constexpr int kOrderBuckets = 256;
+constexpr int kOrderThreads = 256;
+static_assert(kOrderThreads == kOrderBuckets, "one thread per bucket");
+
+__device__ __forceinline__ int order_bucket(int len) {
+    if (len <= 0) return 0;
+    const int o = 31 - __clz(len);
+    const int m = o >= 3 ? (len >> (o - 3)) & 7 : (len << (3 - o)) & 7;
+    return min(kOrderBuckets - 1, 1 + 8 * o + m);
+}
+
+// hist[b] += tiles of bucket b (one block-local histogram per block).
+__global__ void __launch_bounds__(kOrderThreads) order_hist_kernel(int32_t T, const int32_t *__restrict__ ranges,
+                                                                   int32_t *__restrict__ hist) {
+    __shared__ int32_t s_hist[kOrderBuckets];
+    s_hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int t = blockIdx.x * kOrderThreads + threadIdx.x;
+    if (t < T) atomicAdd(&s_hist[order_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1);
+    __syncthreads();
+    if (s_hist[threadIdx.x] > 0) atomicAdd(&hist[threadIdx.x], s_hist[threadIdx.x]);
+}
+
+// order[pos] = tile with pos = (tiles in longer buckets) + (slot of this
+// block within the bucket, from cursor) + (rank within the block).
+__global__ void __launch_bounds__(kOrderThreads) order_scatter_kernel(int32_t T, const int32_t *__restrict__ ranges,
+                                                                      const int32_t *__restrict__ hist,
+                                                                      int32_t *__restrict__ cursor,
+                                                                      int32_t *__restrict__ order) {
+    __shared__ int32_t s_base[kOrderBuckets];
+    __shared__ int32_t s_cnt[kOrderBuckets];
+    const int b = threadIdx.x;
+    s_base[b] = hist[b];
+    s_cnt[b] = 0;
+    __syncthreads();
+    // s_base[b] = tiles in buckets above b (inclusive suffix scan minus own count)
+    const int own = s_base[b];
+    for (int off = 1; off < kOrderBuckets; off <<= 1) {
+        const int v = b + off < kOrderBuckets ? s_base[b + off] : 0;
+        __syncthreads();
+        s_base[b] += v;
+        __syncthreads();
+    }
+    s_base[b] -= own;
+    const int t = blockIdx.x * kOrderThreads + threadIdx.x;
+    int bk = 0, rank = 0;
+    if (t < T) {
+        bk = order_bucket(ranges[2 * t + 1] - ranges[2 * t]);
+        rank = atomicAdd(&s_cnt[bk], 1);
+    }
+    __syncthreads();
+    __shared__ int32_t s_off[kOrderBuckets];
+    s_off[b] = s_cnt[b] > 0 ? atomicAdd(&cursor[b], s_cnt[b]) : 0;
+    __syncthreads();
+    if (t < T) {
+        const int pos = s_base[bk] + s_off[bk] + rank;
+        if (pos >= 0 && pos < T) order[pos] = t;
+    }
+}
+
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 int hist_stride(int64_t nb) { return (int)((nb + 3) & ~(int64_t)3); }
@@ -668,6 +734,18 @@ int launch_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int
     ranges_kernel<uint64_t><<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, nullptr, keys, total_tiles,
                                                                                   ranges);
     return launch_check("tile_ranges");
+}
+
+size_t tile_order_bytes() { return 2 * kOrderBuckets * sizeof(int32_t); }
+
+int launch_tile_order(int32_t T, const int32_t *ranges, int32_t *order, void *ws, hipStream_t s) {
+    int32_t *hist = (int32_t *)ws, *cursor = hist + kOrderBuckets;
+    int rc = launch_fill_zero(ws, tile_order_bytes(), s);
+    if (rc != GSR_OK || T == 0) return rc;
+    const dim3 grid((unsigned)((T + kOrderThreads - 1) / kOrderThreads)), block(kOrderThreads);
+    order_hist_kernel<<<grid, block, 0, s>>>(T, ranges, hist);
+    order_scatter_kernel<<<grid, block, 0, s>>>(T, ranges, hist, cursor, order);
+    return launch_check("tile_order");
 }
 
 size_t sort_workspace_bytes(int64_t M) { return radix_ws_bytes(M); }

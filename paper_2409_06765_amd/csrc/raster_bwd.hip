@@ -46,6 +46,7 @@ struct RasterBwdArgs {
     const float *__restrict__ background;
     const int32_t *__restrict__ ranges;
     const int32_t *__restrict__ ids;
+    const int32_t *__restrict__ order;     // dispatch order of the tiles (nullable)
     const float *__restrict__ image;      // the forward's image (expected depth reads its depth channel)
     const float *__restrict__ final_T;
     const int32_t *__restrict__ last_ids;
@@ -127,7 +128,8 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
     __shared__ int32_t s_qcnt[4];
     __shared__ int32_t s_wmax[kThreads / kWave];
 
-    const int tile = blockIdx.x;
+    const int tile = block_tile(a.order, cams.total_tiles);
+    if (tile < 0) return;
     const int c = camera_of_tile(cams, tile);
     const CamInfo ci = cams.cam[c];
     const int lt = tile - ci.tile_base;
@@ -313,7 +315,8 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
     __shared__ uint8_t s_qm[kTileBatch];
     __shared__ uint8_t s_list[kTileBatch];
 
-    const int tile = blockIdx.x;
+    const int tile = block_tile(a.order, cams.total_tiles);
+    if (tile < 0) return;
     const int c = camera_of_tile(cams, tile);
     const CamInfo ci = cams.cam[c];
     const int lt = tile - ci.tile_base;
@@ -475,7 +478,8 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
 int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D, const float *means2d,
                          const float *conics, const float *colors, const float *depths, const float *opacities,
                          const float *comps, const float *background, const int32_t *ranges,
-                         const int32_t *ids, const float *image, const float *final_T, const int32_t *last_ids,
+                         const int32_t *ids, const int32_t *tile_order, const float *image, const float *final_T,
+                         const int32_t *last_ids,
                          const float *v_image, const float *v_alpha, float *v_means2d, float *v_conics,
                          float *v_colors, float *v_depths, float *v_opac, float *v_means2d_abs, void *ws, int flags,
                          hipStream_t s) {
@@ -498,7 +502,8 @@ int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D
                          s);
         if (rc != GSR_OK) return rc;
     }
-    RasterBwdArgs a{p, N, cn, D, composited_channels(p, D), colors, depths, gauss, background, ranges, ids, image,
+    RasterBwdArgs a{p, N, cn, D, composited_channels(p, D), colors, depths, gauss, background, ranges, ids, tile_order,
+                    image,
                     final_T, last_ids, v_image, v_alpha, v_means2d, v_conics, v_colors, v_depths, v_opac,
                     v_means2d_abs};
     const dim3 grid((unsigned)cams.total_tiles), block(kThreads);

@@ -53,6 +53,7 @@ struct RasterArgs {
     const float *__restrict__ background;
     const int32_t *__restrict__ ranges;
     const int32_t *__restrict__ ids;
+    const int32_t *__restrict__ order;     // dispatch order of the tiles (nullable)
     float *__restrict__ image;
     float *__restrict__ alpha;
     float *__restrict__ final_T;
@@ -74,7 +75,8 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     __shared__ int32_t s_wcnt[4][4];
     __shared__ int32_t s_qcnt[4];
 
-    const int tile = blockIdx.x;
+    const int tile = block_tile(a.order, cams.total_tiles);
+    if (tile < 0) return;
     const int c = camera_of_tile(cams, tile);
     const CamInfo ci = cams.cam[c];
     const int lt = tile - ci.tile_base;
@@ -184,8 +186,8 @@ int channel_capacity(const gsr_params &p, int D) {
 int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, int D, const float *means2d,
                          const float *conics, const float *colors, const float *depths, const float *opacities,
                          const float *comps, const float *background, const int32_t *ranges,
-                         const int32_t *ids, float *image, float *alpha, float *final_T, int32_t *last_ids,
-                         int32_t *n_eval, void *ws, hipStream_t s) {
+                         const int32_t *ids, const int32_t *tile_order, float *image, float *alpha,
+                         float *final_T, int32_t *last_ids, int32_t *n_eval, void *ws, hipStream_t s) {
     if (cams.total_tiles == 0) return GSR_OK;
     const int CN = cams.C * N;
     PackedGauss *gauss = (PackedGauss *)ws;
@@ -194,8 +196,8 @@ int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, int D
                              gauss, s);
         if (rc != GSR_OK) return rc;
     }
-    RasterArgs a{p, N, CN, D, composited_channels(p, D), colors, depths, gauss, background, ranges, ids, image,
-                 alpha, final_T, last_ids, n_eval};
+    RasterArgs a{p, N, CN, D, composited_channels(p, D), colors, depths, gauss, background, ranges, ids, tile_order,
+                 image, alpha, final_T, last_ids, n_eval};
     const dim3 grid((unsigned)cams.total_tiles), block(kThreads);
 #define GSR_RF(DM) do { if (n_eval) raster_fwd_kernel<true, DM><<<grid, block, 0, s>>>(a, cams); \
                         else raster_fwd_kernel<false, DM><<<grid, block, 0, s>>>(a, cams); } while (0)

@@ -168,7 +168,7 @@ def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None, capacit
                               dtype=torch.uint8)
             L.gsr_bin_finish(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], cap, ids, ranges, keys,
                              wsp, wsf, stream=stream)
-            return dict(ids_buf=ids, keys_buf=keys)
+            return dict(ids_buf=ids, keys_buf=keys, order=tile_order(ranges, total_tiles, stream))
 
         out = Intersections(ranges=ranges, total_tiles=total_tiles, key_bits=key_bits, total_dev=total,
                             **build(cap))
@@ -206,7 +206,18 @@ def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None, capacit
     # keys/ids are views of length M; the *_buf tensors (length max(M, 1)) are
     # what the library is handed, so a pointer is never NULL when M == 0
     return dict(counts=counts, offsets=offsets, M=M, keys=keys[:M], ids=ids[:M], ids_buf=ids, keys_buf=keys,
-                ranges=ranges, total_tiles=total_tiles, key_bits=key_bits)
+                ranges=ranges, total_tiles=total_tiles, key_bits=key_bits,
+                order=tile_order(ranges, total_tiles, stream))
+
+
+def tile_order(ranges, total_tiles, stream=None):
+    """Launch order of the compositing blocks: tiles by list length, longest
+    first (gsr_tile_order)."""
+    d = ranges.device
+    order = torch.empty(max(total_tiles, 1), device=d, dtype=torch.int32)
+    ws = torch.empty(max(L.workspace_bytes(L.GSR_OP_TILE_ORDER, 0, 0, 0), 1), device=d, dtype=torch.uint8)
+    L.gsr_tile_order(total_tiles, ranges, order, ws, stream=stream)
+    return order
 
 
 def raster_workspace(C, N, device):
@@ -255,8 +266,9 @@ def rasterize_forward(p, proj, opacities, isect, W, H, background=None, n_eval=F
     # the workspace keeps the packed per-Gaussian records for the backward
     out["ws"] = raster_workspace(C, N, d)
     L.gsr_rasterize_fwd(pf, C, N, D, W, H, proj["means2d"], proj["conics"], feat, proj["depths"], opacities,
-                        proj["comps"], background, isect["ranges"], isect["ids_buf"], out["image"], out["alpha"],
-                        out["final_T"], out["last_ids"], out["n_eval"], ws=out["ws"], stream=stream)
+                        proj["comps"], background, isect["ranges"], isect["ids_buf"], isect.get("order"),
+                        out["image"], out["alpha"], out["final_T"], out["last_ids"], out["n_eval"], ws=out["ws"],
+                        stream=stream)
     return out
 
 
@@ -297,7 +309,8 @@ def rasterize_backward(p, proj, opacities, isect, W, H, fwd, v_image, v_alpha=No
     else:
         flags |= L.GSR_BWD_PACKED
     L.gsr_rasterize_bwd(pf, C, N, D, W, H, proj["means2d"], proj["conics"], feat, proj["depths"], opacities,
-                        proj["comps"], background, isect["ranges"], isect["ids_buf"], fwd["image"], fwd["final_T"],
+                        proj["comps"], background, isect["ranges"], isect["ids_buf"], isect.get("order"), fwd["image"],
+                        fwd["final_T"],
                         fwd["last_ids"], v_image, v_alpha, g["v_means2d"], g["v_conics"],
                         g["v_colors"] if D > 0 else None, g["v_depths"] if depth else None, g["v_opacities"],
                         g["v_means2d_abs"] if absgrad else None, ws=ws, flags=flags, stream=stream)

@@ -139,7 +139,7 @@ def test_backward_flags_overwrite_repack_and_accumulate():
 
     def call(g, ws, flags):
         L.gsr_rasterize_bwd(p, C, N, 3, st["W"], st["H"], pr["means2d"], pr["conics"], pr["colors"], None,
-                            d["opacities"], pr["comps"], None, st["isect"]["ranges"], st["isect"]["ids_buf"], None,
+                            d["opacities"], pr["comps"], None, st["isect"]["ranges"], st["isect"]["ids_buf"], None, None,
                             fw["final_T"], fw["last_ids"], vi, va, g["v_means2d"], g["v_conics"], g["v_colors"], None,
                             g["v_opacities"], g["v_means2d_abs"], ws=ws, flags=flags)
 
@@ -183,3 +183,44 @@ def test_binning_capacity_below_and_above_the_count(capacity):
     assert isect["M"] == ref["M"]
     np.testing.assert_array_equal(np_(isect["ids"]), ref["ids"])
     np.testing.assert_array_equal(np_(isect["ranges"])[:len(ref["ranges"])], ref["ranges"])
+
+
+def test_tile_order_is_longest_first_and_changes_nothing():
+    """gsr_tile_order: a permutation of the tiles whose list lengths, taken
+    in bucket units of an eighth of an octave, never increase; compositing
+    in that order gives the same forward outputs bit for bit and the same
+    gradients (up to the atomics' rounding order) as tile-index order."""
+    from _gpu import assert_grad_close, gpu_forward, np_, params, to_dev
+    from paper_2409_06765_amd import rasterize as R
+    _say("tile order")
+    sc = scenes.scene_tiny(700, sh_degree=1, seed=31, log_scale_mean=-2.3)
+    cams = scenes.cams_tiny(W=131, H=77, f=80.0, n_cams=3, seed=31)
+    p = params(sh_degree=1)
+    st = gpu_forward(p, sc, cams)
+    isect = st["isect"]
+    T = int(isect["total_tiles"])
+    order = np_(isect["order"])[:T]
+    np.testing.assert_array_equal(np.sort(order), np.arange(T))
+    rg = np_(isect["ranges"])[:T]
+    lens = (rg[:, 1] - rg[:, 0]).astype(np.int64)
+
+    def bucket(n):
+        if n <= 0:
+            return 0
+        o = int(n).bit_length() - 1
+        m = (n >> (o - 3)) & 7 if o >= 3 else (n << (3 - o)) & 7
+        return min(255, 1 + 8 * o + m)
+    b = np.array([bucket(n) for n in lens[order]])
+    assert np.all(np.diff(b) <= 0) and lens.max() > 4 * max(np.median(lens), 1)
+    d = st["d"]
+    plain = R.Intersections(**{k: v for k, v in isect.items() if k != "order"})
+    plain._set_count(isect["M"])
+    f0 = R.rasterize_forward(p, st["proj"], d["opacities"], plain, st["W"], st["H"], n_eval=True)
+    f1 = R.rasterize_forward(p, st["proj"], d["opacities"], isect, st["W"], st["H"], n_eval=True)
+    for k in ("image", "alpha", "final_T", "last_ids", "n_eval"):
+        np.testing.assert_array_equal(np_(f0[k]), np_(f1[k]), err_msg=k)
+    v = to_dev(scenes.upstream_grads("tiny", f0["image"].shape[0], seed=32)[0])
+    g0 = R.rasterize_backward(p, st["proj"], d["opacities"], plain, st["W"], st["H"], f0, v)
+    g1 = R.rasterize_backward(p, st["proj"], d["opacities"], isect, st["W"], st["H"], f1, v)
+    for k in ("v_means2d", "v_conics", "v_colors", "v_opacities"):
+        assert_grad_close(np_(g1[k]), np_(g0[k]), k)
