@@ -113,9 +113,10 @@ def main():
     N = int(sc["means"].shape[0])
     v_image_np, _ = scenes.upstream_grads(args.workload, npix, seed=0)
     v_image = torch.from_numpy(v_image_np).to(dev)
-    p = R.make_params(sh_degree=wl["sh_degree"])
+    p = R.make_params(sh_degree=wl["sh_degree"])               # the pipeline's defaults (culled binning)
+    p_square = R.make_params(sh_degree=wl["sh_degree"], tile_cull=0)   # the paper's whole 3-sigma squares
 
-    def step(v, timing=None, n_eval=False):
+    def step(v, timing=None, n_eval=False, p=p):
         vm, Ks = vms[v:v + 1], Kss[v:v + 1]
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)] if timing is not None else None
         if ev: ev[0].record()
@@ -141,14 +142,18 @@ def main():
     views = [i % n_views for i in range(args.steps)]
     counts = {}
     for v in sorted(set(views)):
-        proj, isect, fwd, _, _ = step(v, n_eval=True)
+        # the algorithmic work: evaluations over the paper's square lists (the timed steps composite
+        # the culled lists, which hold every entry a pixel can composite, in the same order)
+        proj, isect, fwd, _, _ = step(v, n_eval=True, p=p_square)
+        M_culled = step(v, p=p)[1]["M"]
         ne = fwd["n_eval"].to(torch.int64)
         last = fwd["last_ids"].to(torch.int64)
         pix = torch.arange(npix, device=dev)
         tile = (pix // W // 16) * ((W + 15) // 16) + (pix % W) // 16
         start = isect["ranges"][tile, 0].to(torch.int64)
         e_bwd = torch.where(last >= 0, last - start + 1, torch.zeros_like(last)).sum()
-        counts[v] = dict(E_fwd=int(ne[:, 0].sum()), C=int(ne[:, 1].sum()), E_bwd=int(e_bwd), M=isect["M"])
+        counts[v] = dict(E_fwd=int(ne[:, 0].sum()), C=int(ne[:, 1].sum()), E_bwd=int(e_bwd), M=isect["M"],
+                         M_culled=M_culled)
     torch.cuda.synchronize()
     log(f"counts view 0: {counts[views[0]]}")
 
@@ -209,7 +214,8 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "evals": {"E_fwd_per_view": E_fwd / args.steps, "E_bwd_per_view": E_bwd / args.steps,
                   "composited_per_view": C_tot / args.steps,
-                  "M_per_view": sum(counts[v]["M"] for v in views) / args.steps},
+                  "M_per_view": sum(counts[v]["M"] for v in views) / args.steps,
+                  "M_culled_per_view": sum(counts[v]["M_culled"] for v in views) / args.steps},
         "evals_per_s_raster": (E_fwd + E_bwd) / (1e-3 * args.steps * (stage_ms["rasterize_fwd"] + stage_ms["rasterize_bwd"])),
         "raster_fwd_tflops": round(fwd_tflops, 3),
         "roofline": roofline,

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 5
+#define GSR_ABI_VERSION 6
 #define GSR_MAX_CAMERAS 64
 
 enum gsr_status {
@@ -70,6 +70,9 @@ typedef struct gsr_params {
     int32_t antialiased;/* 1: opacity times sqrt(|Sigma'| / |Sigma' + eps2d I|)         */
     int32_t render_depth;  /* gsr_depth_mode: composite the depth t_z as a last channel */
     int32_t colors_shared; /* rasterizer colours [N,D] shared by all cameras, not [C,N,D] */
+    int32_t tile_cull;     /* gsr_bin_*: 1 drops the tiles of a Gaussian's 3-sigma square
+                              that no pixel centre can see at alpha >= alpha_min; 0 keeps
+                              the whole square, as the paper bins                       */
 } gsr_params;
 
 /* Depth rendering (Depth rendering appendix): the camera-space depth t_z of
@@ -177,6 +180,15 @@ int gsr_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_
  * depth, their tiles are emitted in that order with 32-bit tile keys, and a
  * stable sort on the tile bits alone leaves every tile's run in (depth, id)
  * order (per-tile depth sort of Rasterization of Gaussians).
+ * With p->tile_cull the lists leave out the tiles that no pixel centre of
+ * theirs sees at alpha >= alpha_min: per tile row, the run of columns whose
+ * pixel centres the ellipse sigma <= ln(o / alpha_min) reaches, with margins
+ * that keep every tile in which the compositing kernels' own per-quad test
+ * keeps a quad.  Every entry a pixel composites, and the order of those
+ * entries, is then the same as with whole squares, so images and gradients
+ * are too (bit for bit in the forward); only the lists are shorter and the
+ * positions in them (last_ids) differ.  conics [C,N,3], opacities [N] and
+ * compensations [C,N] (nullable unless antialiased) are read only then.
  * gsr_bin_prepare: counts and depth order; writes M to total_dev (device,
  * nullable) and, when total_host is not NULL, to *total_host after waiting
  * for the stream.  ws_prep: gsr_workspace_bytes(GSR_OP_BIN_PREPARE, C, N, 0),
@@ -191,11 +203,12 @@ int gsr_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_
  * launches over empty blocks.
  * ws_fin: gsr_workspace_bytes(GSR_OP_BIN_FINISH, C, N, M). */
 int gsr_bin_prepare(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
-                    const float *means2d, const int32_t *radii, const float *depths,
-                    int64_t *total_dev, int64_t *total_host, void *ws_prep, size_t ws_prep_bytes,
+                    const float *means2d, const int32_t *radii, const float *depths, const float *conics,
+                    const float *opacities, const float *compensations, int64_t *total_dev, int64_t *total_host, void *ws_prep, size_t ws_prep_bytes,
                     gsr_stream_t stream);
 int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
-                   const float *means2d, const int32_t *radii, const float *depths, int64_t M,
+                   const float *means2d, const int32_t *radii, const float *depths, const float *conics,
+                   const float *opacities, const float *compensations, int64_t M,
                    int32_t *ids, int32_t *ranges, uint64_t *keys, void *ws_prep, size_t ws_prep_bytes,
                    void *ws_fin, size_t ws_fin_bytes, gsr_stream_t stream);
 

@@ -21,7 +21,7 @@ GSR_OP_TILE_ORDER = 7
 GSR_MAX_CAMERAS = 64
 GSR_BWD_ACCUMULATE, GSR_BWD_PACKED = 1, 2
 GSR_DEPTH_NONE, GSR_DEPTH_ACCUMULATED, GSR_DEPTH_EXPECTED = 0, 1, 2
-ABI_VERSION = 5                 # the signatures below
+ABI_VERSION = 6                 # the signatures below
 _NAMES = {0: "GSR_OK", 1: "GSR_EINVAL", 2: "GSR_EOVERFLOW", 3: "GSR_EWORKSPACE", 4: "GSR_EHIP"}
 
 
@@ -36,7 +36,7 @@ class gsr_params(ctypes.Structure):
                 ("jac_clamp", ctypes.c_float), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("T_min", ctypes.c_float), ("tile", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
                 ("antialiased", ctypes.c_int32), ("render_depth", ctypes.c_int32),
-                ("colors_shared", ctypes.c_int32)]
+                ("colors_shared", ctypes.c_int32), ("tile_cull", ctypes.c_int32)]
 
 
 _vp, _i, _i64, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
@@ -51,8 +51,9 @@ _SIGS = {
     "gsr_intersect_emit": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp], _i),
     "gsr_sort_pairs": ([_i64, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
     "gsr_tile_ranges": ([_i64, _vp, ctypes.c_int32, _vp, _vp], _i),
-    "gsr_bin_prepare": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
-    "gsr_bin_finish": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp, _sz, _vp], _i),
+    "gsr_bin_prepare": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
+    "gsr_bin_finish": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp, _sz,
+                        _vp], _i),
     "gsr_tile_order": ([ctypes.c_int32, _vp, _vp, _vp, _sz, _vp], _i),
     "gsr_rasterize_fwd": ([_P, _i, _i, _i, _vp, _vp] + [_vp] * 10 + [_vp] * 5 + [_vp, _sz, _vp], _i),
     "gsr_rasterize_bwd": ([_P, _i, _i, _i, _vp, _vp] + [_vp] * 15 + [_vp] * 6 + [_vp, _sz, _i, _vp], _i),
@@ -171,20 +172,24 @@ def gsr_tile_ranges(M, keys, total_tiles, ranges, stream=None):
                                  _stream(stream)))
 
 
-def gsr_bin_prepare(p, C, N, W, H, means2d, radii, depths, total_dev, ws_prep, sync=True, stream=None):
+def gsr_bin_prepare(p, C, N, W, H, means2d, radii, depths, conics, opacities, compensations, total_dev, ws_prep,
+                    sync=True, stream=None):
     """Returns M when ``sync`` (the call then waits for the stream), else None."""
     host = ctypes.c_int64(0)
     _check(lib().gsr_bin_prepare(
         ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(radii, I32, "radii"),
-        _ptr(depths, F32, "depths"), _ptr(total_dev, I64, "total"), ctypes.byref(host) if sync else None,
-        *_ws(ws_prep), _stream(stream)))
+        _ptr(depths, F32, "depths"), _ptr(conics, F32, "conics"), _ptr(opacities, F32, "opacities"),
+        _ptr(compensations, F32, "compensations"), _ptr(total_dev, I64, "total"),
+        ctypes.byref(host) if sync else None, *_ws(ws_prep), _stream(stream)))
     return int(host.value) if sync else None
 
 
-def gsr_bin_finish(p, C, N, W, H, means2d, radii, depths, M, ids, ranges, keys, ws_prep, ws_fin, stream=None):
+def gsr_bin_finish(p, C, N, W, H, means2d, radii, depths, conics, opacities, compensations, M, ids, ranges, keys,
+                   ws_prep, ws_fin, stream=None):
     _check(lib().gsr_bin_finish(
         ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(radii, I32, "radii"),
-        _ptr(depths, F32, "depths"), int(M), _ptr(ids, I32, "ids"), _ptr(ranges, I32, "ranges"),
+        _ptr(depths, F32, "depths"), _ptr(conics, F32, "conics"), _ptr(opacities, F32, "opacities"),
+        _ptr(compensations, F32, "compensations"), int(M), _ptr(ids, I32, "ids"), _ptr(ranges, I32, "ranges"),
         _ptr(keys, U64, "keys"), *_ws(ws_prep), *_ws(ws_fin), _stream(stream)))
 
 

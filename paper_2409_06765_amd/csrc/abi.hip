@@ -47,6 +47,7 @@ int check_params(const gsr_params *p) {
     if (p->render_depth < GSR_DEPTH_NONE || p->render_depth > GSR_DEPTH_EXPECTED)
         return fail(GSR_EINVAL, "render_depth must be 0, 1 or 2 (got %d)", p->render_depth);
     if (p->colors_shared != 0 && p->colors_shared != 1) return fail(GSR_EINVAL, "colors_shared must be 0 or 1");
+    if (p->tile_cull != 0 && p->tile_cull != 1) return fail(GSR_EINVAL, "tile_cull must be 0 or 1");
     return GSR_OK;
 }
 
@@ -105,6 +106,7 @@ void gsr_default_params(gsr_params *p) {
     p->antialiased = 0;
     p->render_depth = GSR_DEPTH_NONE;
     p->colors_shared = 0;
+    p->tile_cull = 1;
 }
 
 size_t gsr_workspace_bytes(int op, int C, int N, int64_t M) {
@@ -217,8 +219,8 @@ int gsr_tile_order(int32_t total_tiles, const int32_t *ranges, int32_t *order, v
 }
 
 int gsr_bin_prepare(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
-                    const float *means2d, const int32_t *radii, const float *depths,
-                    int64_t *total_dev, int64_t *total_host, void *ws_prep, size_t ws_prep_bytes,
+                    const float *means2d, const int32_t *radii, const float *depths, const float *conics,
+                    const float *opacities, const float *compensations, int64_t *total_dev, int64_t *total_host, void *ws_prep, size_t ws_prep_bytes,
                     gsr_stream_t stream) {
     static const char *fn = "gsr_bin_prepare";
     int rc = check_params(p);
@@ -227,11 +229,13 @@ int gsr_bin_prepare(const gsr_params *p, int C, int N, const int32_t *W, const i
     if (rc != GSR_OK) return rc;
     const int64_t n = (int64_t)C * N;
     if (n > 0) { GSR_NEED(means2d); GSR_NEED(radii); GSR_NEED(depths); }
+    if (n > 0 && p->tile_cull) { GSR_NEED(conics); GSR_NEED(opacities); if (p->antialiased) GSR_NEED(compensations); }
     const size_t need = bin_prepare_bytes(n);
     if (!ws_prep || ws_prep_bytes < need)
         return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_prep ? ws_prep_bytes : 0);
     hipStream_t s = (hipStream_t)stream;
-    rc = launch_bin_prepare(*p, cams, N, means2d, radii, depths, ws_prep, total_dev, s);
+    rc = launch_bin_prepare(*p, cams, N, means2d, radii, depths, conics, opacities, compensations, ws_prep, total_dev,
+                            s);
     if (rc != GSR_OK || !total_host) return rc;
     rc = hip_check(hipMemcpyAsync(total_host, bin_total_ptr(ws_prep, n), sizeof(int64_t), hipMemcpyDeviceToHost, s),
                    fn);
@@ -242,7 +246,8 @@ int gsr_bin_prepare(const gsr_params *p, int C, int N, const int32_t *W, const i
 }
 
 int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const int32_t *H,
-                   const float *means2d, const int32_t *radii, const float *depths, int64_t M,
+                   const float *means2d, const int32_t *radii, const float *depths, const float *conics,
+                   const float *opacities, const float *compensations, int64_t M,
                    int32_t *ids, int32_t *ranges, uint64_t *keys, void *ws_prep, size_t ws_prep_bytes,
                    void *ws_fin, size_t ws_fin_bytes, gsr_stream_t stream) {
     static const char *fn = "gsr_bin_finish";
@@ -254,6 +259,7 @@ int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const in
     const int64_t n = (int64_t)C * N;
     if (cams.total_tiles > 0) GSR_NEED(ranges);
     if (M > 0) { GSR_NEED(means2d); GSR_NEED(radii); GSR_NEED(depths); GSR_NEED(ids); }
+    if (M > 0 && p->tile_cull) { GSR_NEED(conics); GSR_NEED(opacities); if (p->antialiased) GSR_NEED(compensations); }
     const size_t need_p = bin_prepare_bytes(n), need_f = bin_finish_bytes(M);
     if (!ws_prep || ws_prep_bytes < need_p)
         return fail(GSR_EWORKSPACE, "%s: prepare workspace of %zu bytes needed", fn, need_p);
@@ -261,8 +267,8 @@ int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const in
         return fail(GSR_EWORKSPACE, "%s: finish workspace of %zu bytes needed, %zu given", fn, need_f,
                     ws_fin ? ws_fin_bytes : 0);
     if (cams.total_tiles == 0) return GSR_OK;
-    return launch_bin_finish(*p, cams, N, means2d, radii, depths, M, ws_prep, ws_fin, ids, ranges, keys,
-                             (hipStream_t)stream);
+    return launch_bin_finish(*p, cams, N, means2d, radii, depths, conics, opacities, compensations, M, ws_prep,
+                             ws_fin, ids, ranges, keys, (hipStream_t)stream);
 }
 
 // The channel count: D features (0 .. 32) plus the depth channel, 1 .. 32 in all.

@@ -66,10 +66,12 @@ size_t bin_prepare_bytes(int64_t n);
 size_t bin_finish_bytes(int64_t M);
 const int64_t *bin_total_ptr(void *ws_prep, int64_t n);
 int launch_bin_prepare(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
-                       const int32_t *radii, const float *depths, void *ws_prep, int64_t *total_dev, hipStream_t s);
+                       const int32_t *radii, const float *depths, const float *conics, const float *opacities,
+                       const float *comps, void *ws_prep, int64_t *total_dev, hipStream_t s);
 int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
-                      const int32_t *radii, const float *depths, int64_t M, void *ws_prep, void *ws_fin,
-                      int32_t *ids, int32_t *ranges, uint64_t *keys64, hipStream_t s);
+                      const int32_t *radii, const float *depths, const float *conics, const float *opacities,
+                      const float *comps, int64_t M, void *ws_prep, void *ws_fin, int32_t *ids, int32_t *ranges,
+                      uint64_t *keys64, hipStream_t s);
 
 int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, int D, const float *means2d,
                          const float *conics, const float *colors, const float *depths, const float *opacities,
@@ -206,6 +208,78 @@ __device__ __forceinline__ uint32_t refine_quad_mask(uint32_t m, float4 xyoh, fl
         if (smin > Lq + 1e-5f * smag + 1e-4f * fabsf(Lq) + 1e-4f) m &= ~(1u << q);
     }
     return m;
+}
+
+// Tile culling of the binning (params tile_cull): per row of tiles, the
+// columns whose rectangle of pixel centres the scaled quadratic reaches at
+// or below a threshold L.  For a fixed v = mean_y - y the quadratic
+// A u^2 + B u v + C v^2 <= L holds for u between the roots
+// (-B v -+ sqrt(4 A L - (4 A C - B^2) v^2)) / (2 A); over a strip of v the
+// largest u is at the v of the ellipse's rightmost point clamped to the
+// strip (the upper root is concave in v), the smallest at the mirror image.
+// Pixel centres x = mean_x - u in that range give a contiguous run of tile
+// columns.  L is built so that the run holds every tile in which
+// refine_quad_mask can keep a quad: the quad test's threshold Lq + 1e-5
+// smag + 1e-4 |Lq| + 1e-4, with 2e-5 times a bound on smag (every quad of
+// the 3-sigma square lies within radius + 16 px of the mean in x and y) for
+// the float error of that test, then 1e-4 relative and absolute on top.
+// The arithmetic is float with the hardware's approximate reciprocal, square
+// root and log2 (a few ulp): 4AC - B^2 keeps its digits (B^2 is split into a
+// rounded product and its exact error), and the strip and the run are
+// widened by 2e-3 of the ellipse's extent plus 1e-2 px, far above the
+// rounding error of the rest.  Without a positive-definite conic (the quad
+// test keeps every box quad then) the whole rectangle is kept; below
+// alpha_min opacity nothing is.
+struct TileCull {
+    int mode;          // 0: cull, 1: whole rectangle, 2: no tile
+    float mx, my, B, det, L4A, vmax, vr, inv2A, su;
+};
+
+__device__ __forceinline__ TileCull tile_cull_setup(float mx, float my, float ca, float cb, float cc, float o,
+                                                    float alpha_min, int radius) {
+    TileCull t;
+    t.mode = 0;
+    t.mx = mx;
+    t.my = my;
+    if (!(o >= alpha_min)) { t.mode = 2; return t; }
+    const float A = 0.5f * kLog2e * ca, B = kLog2e * cb, C = 0.5f * kLog2e * cc;
+    if (!(A > 0.0f) || !(C > 0.0f) || !(4.0f * A * C > B * B)) { t.mode = 1; return t; }
+    const float bb = B * B, bbe = fmaf(B, B, -bb);
+    const float det = fmaf(4.0f * A, C, -bb) - bbe;
+    const float Lq = __builtin_amdgcn_logf(o * __builtin_amdgcn_rcpf(alpha_min));   // log2, within 1e-6
+    const float ub = (float)radius + 16.0f;
+    const float smag = (A + fabsf(B) + C) * ub * ub;
+    const float L = (Lq + 1e-4f * fabsf(Lq) + 1e-4f + 2e-5f * smag) * (1.0f + 1e-4f) + 1e-4f;
+    const float idet = __builtin_amdgcn_rcpf(det);
+    const float umax = __builtin_amdgcn_sqrtf(4.0f * C * L * idet), vmax = __builtin_amdgcn_sqrtf(4.0f * A * L * idet);
+    if (!(det > 0.0f) || !(L > 0.0f) || !(umax < 1e7f) || !(vmax < 1e7f)) { t.mode = 1; return t; }
+    t.B = B;
+    t.det = det;
+    t.L4A = 4.0f * A * L;
+    t.inv2A = 0.5f * __builtin_amdgcn_rcpf(A);
+    t.vr = -B * umax * (0.5f * __builtin_amdgcn_rcpf(C));     // v of the rightmost point
+    t.vmax = vmax;
+    t.su = 2e-3f * (umax + vmax) + 1e-2f;
+    return t;
+}
+
+// Columns [xa, xb) of tile row ty, within the rectangle [x0, x1).
+__device__ __forceinline__ void tile_cull_row(const TileCull &t, int ty, int x0, int x1, int &xa, int &xb) {
+    xa = x0;
+    xb = t.mode == 1 ? x1 : x0;
+    if (t.mode != 0) return;
+    const float y0 = (float)(kTile * ty) + 0.5f, y1 = y0 + (float)(kTile - 1);
+    const float v0 = t.my - y1 - t.su, v1 = t.my - y0 + t.su;
+    if (v1 < -t.vmax || v0 > t.vmax) return;
+    const float va = fmaxf(v0, -t.vmax), vb = fminf(v1, t.vmax);
+    const float vr = fminf(fmaxf(t.vr, va), vb), vl = fminf(fmaxf(-t.vr, va), vb);
+    const float ur = (-t.B * vr + __builtin_amdgcn_sqrtf(fmaxf(t.L4A - t.det * vr * vr, 0.0f))) * t.inv2A;
+    const float ul = (-t.B * vl - __builtin_amdgcn_sqrtf(fmaxf(t.L4A - t.det * vl * vl, 0.0f))) * t.inv2A;
+    const float xl = t.mx - ur - t.su, xr = t.mx - ul + t.su;     // pixel centres x = mean_x - u
+    const float a = ceilf((xl - (float)(kTile - 1) - 0.5f) * (1.0f / kTile));
+    const float b = floorf((xr - 0.5f) * (1.0f / kTile)) + 1.0f;
+    xa = (int)fminf(fmaxf(a, (float)x0), (float)x1);
+    xb = (int)fminf(fmaxf(b, (float)xa), (float)x1);
 }
 
 struct PackedGauss {

@@ -68,6 +68,66 @@ __device__ __forceinline__ int tile_count(const CamTable &cams, int N, int64_t g
     return (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0;
 }
 
+// What the binning needs to cull tiles (params tile_cull): the conics and the
+// opacities the compositing kernels use (opacity times compensation when
+// antialiased); on = 0 keeps whole rectangles.
+struct CullIn {
+    const float *conics;
+    const float *opacities;
+    const float *comps;
+    float alpha_min;
+    int on;
+};
+
+// The tile rectangle of projected Gaussian g (camera c) and its culling rule.
+struct GaussTiles {
+    int x0, x1, y0, y1;
+    TileCull cull;
+};
+
+__device__ __forceinline__ GaussTiles gauss_tiles(const CamTable &cams, int N, int64_t g, const float *means2d,
+                                                  const int32_t *radii, const CullIn &ci) {
+    GaussTiles t;
+    t.x0 = t.x1 = t.y0 = t.y1 = 0;
+    t.cull.mode = 1;
+    const int r = radii[g];
+    if (r <= 0) return t;
+    const int c = (int)(g / N);
+    const float mx = means2d[2 * g], my = means2d[2 * g + 1];
+    tile_rect(mx, my, r, cams.cam[c].TX, cams.cam[c].TY, t.x0, t.x1, t.y0, t.y1);
+    if (!(t.x1 > t.x0 && t.y1 > t.y0)) { t.x1 = t.x0; t.y1 = t.y0; return t; }
+    if (ci.on) {
+        float o = ci.opacities[g % N];
+        if (ci.comps) o *= ci.comps[g];
+        t.cull = tile_cull_setup(mx, my, ci.conics[3 * g], ci.conics[3 * g + 1], ci.conics[3 * g + 2], o, ci.alpha_min, r);
+    }
+    return t;
+}
+
+// Tiles of a Gaussian: the rectangle's area, or the sum of its rows' runs.
+__device__ __forceinline__ int gauss_tile_count(const GaussTiles &t) {
+    if (t.cull.mode == 1) return (t.x1 - t.x0) * (t.y1 - t.y0);
+    int n = 0;
+#pragma clang loop unroll(disable) vectorize(disable) interleave(disable)
+    for (int ty = t.y0; ty < t.y1; ty++) {
+        int xa, xb;
+        tile_cull_row(t.cull, ty, t.x0, t.x1, xa, xb);
+        n += xb - xa;
+    }
+    return n;
+}
+
+// First row at or after ty with a non-empty run (t.y1 if none) and its run.
+__device__ __forceinline__ int next_row(const GaussTiles &t, int ty, int &xa, int &xb) {
+#pragma clang loop unroll(disable) vectorize(disable) interleave(disable)
+    for (; ty < t.y1; ty++) {
+        tile_cull_row(t.cull, ty, t.x0, t.x1, xa, xb);
+        if (xb > xa) return ty;
+    }
+    xa = xb = t.x0;
+    return t.y1;
+}
+
 // ---- prefix sums ----------------------------------------------------------
 // Tiles per Gaussian and per-block sums.
 __global__ void __launch_bounds__(kScanThreads) count_kernel(CamTable cams, int N, int64_t n_total,
@@ -143,14 +203,19 @@ __global__ void __launch_bounds__(kScanThreads) offsets_kernel(int64_t n_total, 
 // Gaussians covering thousands of tiles, clustered in depth order, would
 // otherwise keep single waves busy long after the rest finished).  A wave
 // finds the entry owning its first slot with a 64-way search over the
-// exclusive offsets, then walks windows of 64 consecutive entries of the
+// exclusive offsets, then walks windows of consecutive entries of the
 // emission sequence (projected Gaussians in id order, or in depth order when
-// `order` is given): each lane stages one entry's rectangle in LDS and, for
-// each slot it writes, finds the owning entry by binary search over the
-// window's offsets.  Writes are coalesced.  Keys are tile << 32 | depth bits
+// `order` is given).  Each lane takes one entry and writes the runs of its
+// tile rows (whole rectangle rows, or the culled runs) into an LDS table of
+// up to kEmitRows rows: slot of the run's first tile, that tile, run length,
+// entry.  An entry with more rows than fit is continued in the next window.
+// Then each lane writes a run of at most 8 consecutive slots of the wave's
+// slice, finding its row by binary search over the table.  The slice is
+// staged in LDS and written out coalesced.  Keys are tile << 32 | depth bits
 // (uint64) or the tile id alone (uint32).
 constexpr int kEmitThreads = 256;
 constexpr int kEmitChunk = 512;
+constexpr int kEmitRows = 256;
 
 template <typename K>
 __device__ __forceinline__ K make_key(uint32_t tile, uint32_t dbits);
@@ -178,17 +243,23 @@ __device__ __forceinline__ int64_t owner_search(const int64_t *__restrict__ offs
     return lo;
 }
 
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N, int64_t n_total,
         const float *__restrict__ means2d, const int32_t *__restrict__ radii, const float *__restrict__ depths,
-        const int32_t *__restrict__ order, const int64_t *__restrict__ offsets, int64_t cap,
+        CullIn cull, const int32_t *__restrict__ order, const int64_t *__restrict__ offsets, int64_t cap,
         const int64_t *__restrict__ count_dev, K *__restrict__ keys, int32_t *__restrict__ ids) {
     constexpr int kWaves = kEmitThreads / kWave;
-    if (count_dev) cap = min(cap, *count_dev);   // capacity mode: the true count lives on the device
-    __shared__ int64_t s_start[kWaves][kWave];   // first slot of each entry of the window
-    __shared__ int32_t s_w[kWaves][kWave];       // rectangle width in tiles
-    __shared__ int32_t s_row[kWaves][kWave];     // tile_base + y0 * TX + x0 of the entry's camera
-    __shared__ int32_t s_TX[kWaves][kWave];
+    const int64_t total = count_dev ? *count_dev : cap;   // end of the last entry
+    cap = min(cap, total);                       // capacity mode: the true count lives on the device
+    __shared__ int32_t s_rslot[kWaves][kEmitRows];   // slot of the row run's first tile, from the window start
+    __shared__ int32_t s_rtile[kWaves][kEmitRows];   // that tile
+    __shared__ uint8_t s_rent[kWaves][kEmitRows];    // entry (lane) of the row
     __shared__ uint32_t s_dbits[kWaves][kWave];
     __shared__ int32_t s_g[kWaves][kWave];
     __shared__ K s_okey[kWaves][kEmitChunk];     // the wave's slice, written out coalesced at the end
@@ -197,81 +268,143 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
     const int64_t c0 = ((int64_t)blockIdx.x * kWaves + w) * kEmitChunk;
     if (c0 >= cap) return;                       // wave-uniform
     const int64_t c1 = min(c0 + (int64_t)kEmitChunk, cap);
-    for (int64_t s = owner_search(offsets, n_total, c0); s < n_total; s += kWave) {
+    int64_t s = owner_search(offsets, n_total, c0);
+    int r0 = 0;                                  // rows of entry s emitted by earlier windows
+    int64_t so = 0;                              // and their slots
+    while (s < n_total) {
+        // ---- the window: lane i takes entry s + i, from row r0 for lane 0
         const int64_t q = s + lane;
-        int cnt = 0, x0 = 0, x1 = 0, y0 = 0, y1 = 0, TX = 0, row = 0;
-        int64_t start = INT64_MAX, g = 0;
-        uint32_t dbits = 0;
+        int64_t g = 0, start = 0;
+        GaussTiles t;
+        t.x0 = t.x1 = t.y0 = t.y1 = 0;
+        t.cull.mode = 1;
+        int nr = 0, base = 0, TX = 0;
         if (q < n_total) {
             g = order ? order[q] : q;
             if (g < 0 || g >= n_total) g = 0;    // order comes from the depth sort; this only bounds a bad input
-            start = offsets[q];
-            const int r = radii[g];
-            if (r > 0) {
-                const int c = (int)(g / N);
-                TX = cams.cam[c].TX;
-                tile_rect(means2d[2 * g], means2d[2 * g + 1], r, TX, cams.cam[c].TY, x0, x1, y0, y1);
-                if (x1 > x0 && y1 > y0) cnt = (x1 - x0) * (y1 - y0);
-                row = cams.cam[c].tile_base + y0 * TX + x0;
-                dbits = __float_as_uint(depths[g]);
+            start = offsets[q] + (lane == 0 ? so : 0);
+            const int64_t end = q + 1 < n_total ? offsets[q + 1] : total;
+            if (end > start) {
+                t = gauss_tiles(cams, N, g, means2d, radii, cull);
+                nr = t.y1 - t.y0 - (lane == 0 ? r0 : 0);
+                base = cams.cam[g / N].tile_base;
+                TX = cams.cam[g / N].TX;
             }
+            s_dbits[w][lane] = __float_as_uint(depths[g]);
+            s_g[w][lane] = (int32_t)g;
         }
-        // the window covers slots [start of lane 0, largest end)
-        int64_t wend = q < n_total ? start + cnt : INT64_MIN;
+        const int ry0 = t.y0 + (lane == 0 ? r0 : 0);   // first row of this lane's entry in the table
+        // rows of the lanes before this one; lanes that fit whole, and a partial last one
+        int rb = nr;
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-            const int64_t o2 = __shfl_xor(wend, d, kWave);
-            wend = o2 > wend ? o2 : wend;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int u = __shfl_up(rb, d, kWave);
+            if (lane >= d) rb += u;
         }
-        const int64_t wbeg = __shfl(start, 0, kWave);
-        s_start[w][lane] = start;
-        s_w[w][lane] = x1 - x0;
-        s_row[w][lane] = row;
-        s_TX[w][lane] = TX;
-        s_dbits[w][lane] = dbits;
-        s_g[w][lane] = (int32_t)g;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // Each lane writes a run of at most 8 consecutive slots of [p0, p1): it finds the owner of its
-        // first slot by binary search (the largest L with s_start[L] <= pos; zero-count entries share
-        // their successor's start and lose to it), then walks the owner's rectangle row by row and
-        // moves to the next owner where a rectangle ends.
-        const int64_t p0 = max(c0, wbeg), p1 = min(c1, wend);
-        const int run = (int)((p1 - p0 + kWave - 1) / kWave);
-        int64_t pos = p0 + (int64_t)lane * run;
-        const int64_t pend = min(pos + run, p1);
-        if (pos < pend) {
-            int lo = 0, hi = kWave - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_start[w][mid] <= pos) lo = mid; else hi = mid - 1;
+        rb -= nr;
+        const int nfit = __popcll(__ballot(q < n_total && rb + nr <= kEmitRows));   // a prefix of the lanes
+        const int take = lane < nfit ? nr : (lane == nfit ? max(0, min(nr, kEmitRows - rb)) : 0);
+        const int nrows = __shfl(rb + take, min(nfit, kWave - 1), kWave);
+        // ---- the table's rows, four consecutive ones per lane: owner entry, tile run, length
+        constexpr int kPer = kEmitRows / kWave;
+        int len[kPer], tile[kPer], own[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; k++) {
+            const int i = lane * kPer + k;
+            // owner: the last lane whose first row is <= i (rb is non-decreasing; a lane without rows
+            // shares its first row with the next lane, and every lane after the owner starts past i)
+            int lo = 0;
+#pragma unroll
+            for (int step = kWave / 2; step >= 1; step >>= 1) {
+                const int cand = lo + step;
+                if (__shfl(rb, cand, kWave) <= i) lo = cand;
             }
-            int local = (int)(pos - s_start[w][lo]);
-            int wdt = max(s_w[w][lo], 1);
-            int dy = local / wdt;
-            int dx = local - dy * wdt;
-            for (; pos < pend; pos++) {
-                while (lo + 1 < kWave && s_start[w][lo + 1] <= pos) {   // next owner (its rectangle starts here)
-                    lo++;
-                    wdt = max(s_w[w][lo], 1);
-                    dx = 0;
-                    dy = 0;
+            own[k] = lo;
+            GaussTiles ot;
+            ot.x0 = __shfl(t.x0, lo, kWave);
+            ot.x1 = __shfl(t.x1, lo, kWave);
+            ot.cull.mode = __shfl(t.cull.mode, lo, kWave);
+            ot.cull.mx = __shfl(t.cull.mx, lo, kWave);
+            ot.cull.my = __shfl(t.cull.my, lo, kWave);
+            ot.cull.B = __shfl(t.cull.B, lo, kWave);
+            ot.cull.det = __shfl(t.cull.det, lo, kWave);
+            ot.cull.L4A = __shfl(t.cull.L4A, lo, kWave);
+            ot.cull.vmax = __shfl(t.cull.vmax, lo, kWave);
+            ot.cull.vr = __shfl(t.cull.vr, lo, kWave);
+            ot.cull.inv2A = __shfl(t.cull.inv2A, lo, kWave);
+            ot.cull.su = __shfl(t.cull.su, lo, kWave);
+            const int ty = __shfl(ry0, lo, kWave) + (i - __shfl(rb, lo, kWave));
+            int xa = ot.x0, xb = ot.x0;
+            if (i < nrows) tile_cull_row(ot.cull, ty, ot.x0, ot.x1, xa, xb);
+            len[k] = xb - xa;
+            tile[k] = __shfl(base, lo, kWave) + ty * __shfl(TX, lo, kWave) + xa;
+        }
+        // slots of the rows: the window's first slot plus the lengths of the rows before
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; k++) sum += len[k];
+        int ex = sum;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int u = __shfl_up(ex, d, kWave);
+            if (lane >= d) ex += u;
+        }
+        const int wlen = __shfl(ex, kWave - 1, kWave);   // slots of the window
+        ex -= sum;
+        const int64_t wbeg = __shfl(start, 0, kWave);
+        const int64_t wend = wbeg + wlen;
+#pragma unroll
+        for (int k = 0; k < kPer; k++) {
+            const int i = lane * kPer + k;
+            if (i < nrows) {
+                s_rslot[w][i] = (int32_t)(wbeg - c0) + ex;     // may be negative: rows before the slice
+                s_rtile[w][i] = tile[k];
+                s_rent[w][i] = (uint8_t)own[k];
+            }
+            ex += len[k];
+        }
+        const bool partial = nfit < kWave && s + nfit < n_total;   // lane nfit stopped inside its entry (or at 0 rows)
+        const int taken = partial ? __shfl(take, nfit, kWave) : 0;
+        wave_sync_lds();
+        // ---- write the slice's slots of this window
+        const int64_t p0 = max(c0, wbeg), p1 = min(c1, wend);
+        if (p0 < p1) {
+            const int run = (int)((p1 - p0 + kWave - 1) / kWave);
+            int64_t pos = p0 + (int64_t)lane * run;
+            const int64_t pend = min(pos + run, p1);
+            if (pos < pend) {
+                int rel = (int)(pos - c0);
+                int lo = 0, hi = nrows - 1;      // the last row whose first slot is <= rel
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_rslot[w][mid] <= rel) lo = mid; else hi = mid - 1;
                 }
-                const int slot = (int)(pos - c0);
-                s_okey[w][slot] = make_key<K>((uint32_t)(s_row[w][lo] + dy * s_TX[w][lo] + dx), s_dbits[w][lo]);
-                s_oid[w][slot] = s_g[w][lo];
-                if (++dx == wdt) { dx = 0; dy++; }
+#pragma clang loop unroll(disable) vectorize(disable) interleave(disable)
+                for (; pos < pend; pos++, rel++) {
+                    while (lo + 1 < nrows && s_rslot[w][lo + 1] <= rel) lo++;
+                    const int e = s_rent[w][lo];
+                    s_okey[w][rel] = make_key<K>((uint32_t)(s_rtile[w][lo] + (rel - s_rslot[w][lo])), s_dbits[w][e]);
+                    s_oid[w][rel] = s_g[w][e];
+                }
             }
         }
         if (wend >= c1) break;
-        __builtin_amdgcn_wave_barrier();         // the window's LDS is rewritten next
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // the next window
+        if (partial && nfit == 0) {              // lane 0's entry continues
+            r0 += taken;
+            so = wend - offsets[s];
+        } else if (partial) {
+            s += nfit;
+            r0 = taken;
+            so = wend - offsets[s];
+        } else {
+            s += kWave;
+            r0 = 0;
+            so = 0;
+        }
+        wave_sync_lds();                         // the window's LDS is rewritten next
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync_lds();
     const int n_out = (int)(c1 - c0);             // every slot of [c0, c1) was written above
     for (int i = lane; i < n_out; i += kWave) {
         keys[c0 + i] = s_okey[w][i];
@@ -308,10 +441,10 @@ __global__ void ranges_kernel(int64_t M, const int64_t *__restrict__ count_dev, 
 // Depth-sort keys of the projected Gaussians (culled ones last) and their counts.
 __global__ void __launch_bounds__(256) bin_keys_kernel(CamTable cams, int N, int64_t n_total,
         const float *__restrict__ means2d, const int32_t *__restrict__ radii, const float *__restrict__ depths,
-        int32_t *__restrict__ counts, uint32_t *__restrict__ dkeys, int32_t *__restrict__ dvals) {
+        CullIn cull, int32_t *__restrict__ counts, uint32_t *__restrict__ dkeys, int32_t *__restrict__ dvals) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_total) return;
-    const int k = tile_count(cams, N, g, means2d, radii);
+    const int k = gauss_tile_count(gauss_tiles(cams, N, g, means2d, radii, cull));
     counts[g] = k;
     dkeys[g] = k > 0 ? __float_as_uint(depths[g]) : 0xFFFFFFFFu;
     dvals[g] = (int32_t)g;
@@ -714,8 +847,10 @@ int launch_intersect_emit(const gsr_params &p, const CamTable &cams, int N, cons
     const int64_t n = (int64_t)cams.C * N;
     if (n == 0 || cap == 0) return GSR_OK;
     const int64_t nb = emit_blocks(cap);
+    const CullIn none{nullptr, nullptr, nullptr, 0.0f, 0};   // this route keeps whole rectangles
     emit_kernel<uint64_t><<<dim3((unsigned)nb), dim3(kEmitThreads), 0, s>>>(cams, N, n, means2d, radii, depths,
-                                                                           nullptr, offsets, cap, nullptr, keys, ids);
+                                                                           none, nullptr, offsets, cap, nullptr, keys,
+                                                                           ids);
     return launch_check("intersect_emit");
 }
 
@@ -759,14 +894,21 @@ size_t bin_prepare_bytes(int64_t n) { return prep_bytes(n); }
 size_t bin_finish_bytes(int64_t M) { return fin_bytes(M); }
 const int64_t *bin_total_ptr(void *ws_prep, int64_t n) { return carve_prep(ws_prep, n).total; }
 
+namespace {
+CullIn cull_inputs(const gsr_params &p, const float *conics, const float *opacities, const float *comps) {
+    return CullIn{conics, opacities, p.antialiased ? comps : nullptr, p.alpha_min, p.tile_cull ? 1 : 0};
+}
+}  // namespace
+
 int launch_bin_prepare(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
-                       const int32_t *radii, const float *depths, void *ws_prep, int64_t *total_dev, hipStream_t s) {
-    (void)p;
+                       const int32_t *radii, const float *depths, const float *conics, const float *opacities,
+                       const float *comps, void *ws_prep, int64_t *total_dev, hipStream_t s) {
     const int64_t n = (int64_t)cams.C * N;
     BinPrep b = carve_prep(ws_prep, n);
     if (n == 0) return launch_fill_zero(b.total, sizeof(int64_t), s);
     const unsigned nb = (unsigned)((n + 255) / 256);
-    bin_keys_kernel<<<nb, 256, 0, s>>>(cams, N, n, means2d, radii, depths, b.counts, b.dkeys, b.order);
+    bin_keys_kernel<<<nb, 256, 0, s>>>(cams, N, n, means2d, radii, depths, cull_inputs(p, conics, opacities, comps),
+                                       b.counts, b.dkeys, b.order);
     int rc = radix_sort<uint32_t>(n, 32, b.dkeys, b.order, b.dkeys_alt, b.order_alt, b.sort_ws, s);
     if (rc != GSR_OK) return rc;
     gather_counts_kernel<<<nb, 256, 0, s>>>(n, b.order, b.counts, b.counts_sorted);
@@ -777,9 +919,9 @@ int launch_bin_prepare(const gsr_params &p, const CamTable &cams, int N, const f
 }
 
 int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
-                      const int32_t *radii, const float *depths, int64_t M, void *ws_prep, void *ws_fin,
-                      int32_t *ids, int32_t *ranges, uint64_t *keys64, hipStream_t s) {
-    (void)p;
+                      const int32_t *radii, const float *depths, const float *conics, const float *opacities,
+                      const float *comps, int64_t M, void *ws_prep, void *ws_fin, int32_t *ids, int32_t *ranges,
+                      uint64_t *keys64, hipStream_t s) {
     const int64_t n = (int64_t)cams.C * N;
     BinPrep b = carve_prep(ws_prep, n);
     BinFin f = carve_fin(ws_fin, M);
@@ -787,9 +929,9 @@ int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const fl
     if (rc != GSR_OK || n == 0 || M == 0) return rc;
     const int64_t ne = emit_blocks(M);
     // M is the capacity; the true count (b.total, from the prepare step) is read on the device
-    emit_kernel<uint32_t><<<dim3((unsigned)ne), dim3(kEmitThreads), 0, s>>>(cams, N, n, means2d, radii, depths,
-                                                                           b.order, b.offsets_sorted, M, b.total,
-                                                                           f.tkeys, ids);
+    emit_kernel<uint32_t><<<dim3((unsigned)ne), dim3(kEmitThreads), 0, s>>>(
+        cams, N, n, means2d, radii, depths, cull_inputs(p, conics, opacities, comps), b.order, b.offsets_sorted, M,
+        b.total, f.tkeys, ids);
     const int tile_bits = cams.total_tiles > 1 ? 32 - __builtin_clz((unsigned)(cams.total_tiles - 1)) : 1;
     rc = radix_sort<uint32_t>(M, tile_bits, f.tkeys, ids, f.tkeys_alt, f.ids_alt, f.sort_ws, s, b.total);
     if (rc != GSR_OK) return rc;

@@ -65,7 +65,8 @@ def project(p, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, W, H
     out = dict(means2d=torch.empty((C, N, 2), **f), conics=torch.empty((C, N, 3), **f),
                radii=torch.empty((C, N), device=d, dtype=torch.int32), depths=torch.empty((C, N), **f),
                colors=torch.empty((C, N, 3), **f) if sh_or_colors is not None else None,
-               comps=torch.empty((C, N), **f) if p.antialiased else None)
+               comps=torch.empty((C, N), **f) if p.antialiased else None,
+               opacities=opacities)          # the binning's tile culling reads them
     L.gsr_project_fwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors, viewmats, Ks,
                       out["means2d"], out["conics"], out["radii"], out["depths"], out["colors"], out["comps"],
                       stream=stream)
@@ -137,13 +138,14 @@ def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None, capacit
     """Per-tile depth-sorted lists.
 
     method="bin" (default): depth order of the projected Gaussians, then a
-    stable sort of 32-bit tile keys (gsr_bin_prepare / gsr_bin_finish).  The
+    stable sort of 32-bit tile keys (gsr_bin_prepare / gsr_bin_finish), with
+    the tiles no pixel can see dropped when ``p.tile_cull`` is set.  The
     host does not wait for the intersection count: the lists are built in a
     buffer of ``capacity`` entries (default: from earlier calls of the same
     shape; the first call of a shape waits for the count) and the count is
     checked when M is read.  method="keys64": count (waits for it), emit
-    64-bit keys, stable radix sort, ranges.  Both give the same ids and
-    ranges."""
+    64-bit keys, stable radix sort, ranges of whole squares.  Without tile
+    culling both give the same ids and ranges."""
     C, N = proj["radii"].shape
     d = proj["radii"].device
     _, tile_off = layout(W, H)
@@ -152,10 +154,11 @@ def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None, capacit
     ranges = torch.empty((max(total_tiles, 1), 2), device=d, dtype=torch.int32)
     key_bits = 32 + max(total_tiles - 1, 0).bit_length()
     if method == "bin":
-        shape = (str(d), C, N, tuple(int(w) for w in W), tuple(int(h) for h in H))
+        shape = (str(d), C, N, tuple(int(w) for w in W), tuple(int(h) for h in H), int(p.tile_cull))
         wsp = torch.empty(max(L.workspace_bytes(L.GSR_OP_BIN_PREPARE, C, N, 0), 1), device=d, dtype=torch.uint8)
         cap = int(capacity) if capacity is not None else _CAPACITY.get(shape)
-        M_known = L.gsr_bin_prepare(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], total, wsp,
+        cull = (proj["conics"], proj.get("opacities"), proj.get("comps"))
+        M_known = L.gsr_bin_prepare(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], *cull, total, wsp,
                                     sync=cap == 0, stream=stream)
         if M_known is not None:
             _CAPACITY.note(shape, M_known)
@@ -166,8 +169,8 @@ def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None, capacit
             keys = torch.empty(max(cap, 1), device=d, dtype=torch.uint64) if want_keys else None
             wsf = torch.empty(max(L.workspace_bytes(L.GSR_OP_BIN_FINISH, C, N, cap), 1), device=d,
                               dtype=torch.uint8)
-            L.gsr_bin_finish(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], cap, ids, ranges, keys,
-                             wsp, wsf, stream=stream)
+            L.gsr_bin_finish(p, C, N, W, H, proj["means2d"], proj["radii"], proj["depths"], *cull, cap, ids, ranges,
+                             keys, wsp, wsf, stream=stream)
             return dict(ids_buf=ids, keys_buf=keys, order=tile_order(ranges, total_tiles, stream))
 
         out = Intersections(ranges=ranges, total_tiles=total_tiles, key_bits=key_bits, total_dev=total,

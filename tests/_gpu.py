@@ -15,8 +15,11 @@ def to_dev(a, dtype=None):
     return t.to(DEV)
 
 
-def params(sh_degree=-1, antialiased=False, **kw):
-    return R.make_params(sh_degree=sh_degree, antialiased=antialiased, **kw)
+def params(sh_degree=-1, antialiased=False, tile_cull=0, **kw):
+    """Library parameters for the tests: by default the paper's whole-square
+    binning, whose lists (and list positions) the oracle reproduces bit for
+    bit; tile_cull=1 is the culled binning the pipeline uses by default."""
+    return R.make_params(sh_degree=sh_degree, antialiased=antialiased, tile_cull=tile_cull, **kw)
 
 
 def scene_to_dev(sc):
