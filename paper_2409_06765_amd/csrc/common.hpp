@@ -171,6 +171,12 @@ __device__ __forceinline__ uint32_t quad_mask(float mx, float my, float hx, floa
 // log2(e) sigma <= log2(opacity / alpha_min).
 constexpr float kLog2e = 1.4426950408889634f;
 
+// min(alpha, alpha_max) for a non-NaN alpha in one instruction: the median of
+// (alpha, -inf, alpha_max).
+__device__ __forceinline__ float min_alpha(float alpha, float alpha_max) {
+    return __builtin_amdgcn_fmed3f(alpha, -__builtin_inff(), alpha_max);
+}
+
 __device__ __forceinline__ float scaled_sigma(float4 con, float dx, float dy) {
     return fmaf(dx, fmaf(con.x, dx, con.y * dy), con.z * dy * dy);
 }

@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
     const float px = (float)xi + 0.5f, py = (float)yi + 0.5f;
     const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
     const int start = a.ranges[2 * tile];
-    const float amin = a.p.alpha_min, amax = __builtin_canonicalizef(a.p.alpha_max);
+    const float amin = a.p.alpha_min, amax = a.p.alpha_max;
 
     // Per pixel: T restored back to front, and SV = (S . v_C) with S the colour accumulated behind the
     // current entry (plus final_T times the background): dL/dalpha only needs S through that dot
@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
             const float sig = scaled_sigma(con, dx, dy);          // log2(e) sigma, as in the forward
             const float ex = __builtin_amdgcn_exp2f(-sig);
             const float araw = xyo.z * ex;
-            const float al = fminf(amax, araw);
+            const float al = min_alpha(araw, amax);
             const bool use = kk <= last && sig >= 0.0f && al >= amin;
             if (__ballot(use) == 0ull) continue;
             const float inv = __builtin_amdgcn_rcpf(1.0f - al);
@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
                 val = lane == 9 + extra ? zx : lane == 10 + extra ? zy : val;
             }
             if (lane < nslots && dst_base) {
-                const int g = s_id[e];
+                const int g = __builtin_amdgcn_readfirstlane(s_id[e]);   // uniform: scalar index arithmetic
                 int n = g - cam_base;
                 if ((unsigned)n >= (unsigned)a.N) n = 0;   // only a bad id can leave the tile's camera
                 unsafeAtomicAdd(dst_base + (int64_t)(dst_by_n ? n : g) * dst_mul, val);
@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
     // pixel centre of this lane in quad 0; quad q adds (8 (q & 1), 8 (q >> 1))
     const float px0 = tile_x0 + (float)(lane & 7) + 0.5f, py0 = tile_y0 + (float)(lane >> 3) + 0.5f;
     const int start = a.ranges[2 * tile];
-    const float amin = a.p.alpha_min, amax = __builtin_canonicalizef(a.p.alpha_max);
+    const float amin = a.p.alpha_min, amax = a.p.alpha_max;
 
     // per pixel (one per quad): T restored back to front, SV = S . v_C, v_alpha final_T, v_C, last index
     float T[4], SV[4], vATf[4], vC[4][3];
@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
                 const float sig = scaled_sigma(con, dx, dy);      // log2(e) sigma, as in the forward
                 const float ex = __builtin_amdgcn_exp2f(-sig);
                 const float araw = xyo.z * ex;
-                const float al = fminf(amax, araw);
+                const float al = min_alpha(araw, amax);
                 const bool use = kk <= last[q] && sig >= 0.0f && al >= amin;
                 if (__ballot(use) == 0ull) continue;               // uniform
                 any = true;
@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
                 val = lane == 9 ? zx * (1.0f / kLog2e) : lane == 10 ? zy * (1.0f / kLog2e) : val;
             }
             if (lane < nslots && dst_base) {
-                const int g = s_id[e];
+                const int g = __builtin_amdgcn_readfirstlane(s_id[e]);   // uniform: scalar index arithmetic
                 int n = g - cam_base;
                 if ((unsigned)n >= (unsigned)a.N) n = 0;   // only a bad id can leave the tile's camera
                 unsafeAtomicAdd(dst_base + (int64_t)(dst_by_n ? n : g) * dst_mul, val);

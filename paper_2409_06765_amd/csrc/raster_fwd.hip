@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     const float px = (float)xi + 0.5f, py = (float)yi + 0.5f;
     const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
     const int start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
-    const float amin = a.p.alpha_min, amax = __builtin_canonicalizef(a.p.alpha_max), tmin = a.p.T_min;
+    const float amin = a.p.alpha_min, amax = a.p.alpha_max, tmin = a.p.T_min;
 
     float T = 1.0f, Wacc = 0.0f, Cacc[DM];   // Wacc: sum of alpha T, the expected-depth normaliser
 #pragma unroll
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
             const float4 con = s_con[e];
             const float dx = xyo.x - px, dy = xyo.y - py;
             const float sig = scaled_sigma(con, dx, dy);          // log2(e) sigma
-            const float al = fminf(amax, xyo.z * __builtin_amdgcn_exp2f(-sig));
+            const float al = min_alpha(xyo.z * __builtin_amdgcn_exp2f(-sig), amax);
             const float Tn = T * (1.0f - al);
             const bool use = !done && sig >= 0.0f && al >= amin;
             const bool stop = use && Tn < tmin;
