@@ -38,6 +38,9 @@ PEAK_HBM_GBS = 8000.0
 FLOPS_EVAL, FLOPS_FWD_COMP, FLOPS_BWD_COMP = 14, 9, 49
 
 WORKLOADS = {
+    "uniform10k_256": dict(
+        desc="10k Gaussians, direct RGB colours, 256x256, fx=fy=256, one view from (0, 0, 4)",
+        scene="scene_uniform10k_256", cams="cams_uniform10k_256", sh_degree=-1),
     "clusters1m_sh3_1080p": dict(
         desc="1M Gaussians, 32 clusters, SH degree 3, 1920x1080, fx=fy=1500, 16 views on a radius-6 sphere",
         scene="scene_clusters1m_sh3_1080p", cams="cams_clusters1m_sh3_1080p", sh_degree=3),
@@ -241,9 +244,9 @@ def serving(d, p, args):
     probe = scenes.serving_trace(1.0, n_requests=60, seed=1)
     for r in probe:
         r.arrival = 0.0
-    serve_one_at_a_time(be, probe[:10])                      # warm up
+    serve_one_at_a_time(be, probe)                           # warm up: every size (capacity, allocations)
     torch.cuda.synchronize()
-    _, cap = serve_one_at_a_time(be, probe[10:])
+    _, cap = serve_one_at_a_time(be, probe)
     rate = args.serve_load * cap.views_per_s
     trace = scenes.serving_trace(rate, n_requests=args.serve_requests, seed=0)
     log(f"serving: one-view capacity {cap.views_per_s:.1f} views/s, trace at {rate:.1f} req/s")
