@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 6
+#define GSR_ABI_VERSION 7
 #define GSR_MAX_CAMERAS 64
 
 enum gsr_status {
@@ -94,7 +94,9 @@ enum gsr_op {
     GSR_OP_BIN_PREPARE = 4,       /* workspace kept from gsr_bin_prepare to _finish   */
     GSR_OP_BIN_FINISH = 5,        /* workspace of gsr_bin_finish for M intersections  */
     GSR_OP_PROJECT_BWD = 6,       /* workspace of gsr_project_bwd with v_viewmats     */
-    GSR_OP_TILE_ORDER = 7         /* workspace of gsr_tile_order                      */
+    GSR_OP_TILE_ORDER = 7,        /* workspace of gsr_tile_order                      */
+    GSR_OP_L1_LOSS = 8,           /* workspace of gsr_l1_loss (any size)              */
+    GSR_OP_DENSIFY_PLAN = 9       /* workspace of gsr_densify_plan for N Gaussians    */
 };
 
 /* Flags of gsr_rasterize_bwd. */
@@ -326,6 +328,151 @@ int gsr_project_bwd(const gsr_params *p, int C, int N, const int32_t *W, const i
                     float *v_means, float *v_quats, float *v_scales, float *v_opacities,
                     float *v_sh_or_colors, float *v_viewmats, void *ws, size_t ws_bytes,
                     gsr_stream_t stream);
+
+/* ==== Training-loop steps (Densification Strategies appendix) ================
+ * One optimisation step of a fit around the rasterizer: photometric loss,
+ * Adam on the raw parameters (scales = exp(raw), opacities = sigmoid(raw)),
+ * the ADC densification statistics, plan and apply, the opacity reset, and
+ * the MCMC strategy's noise on the centres.  Same conventions as above
+ * (device pointers, caller-owned buffers, status codes, asynchronous on the
+ * stream unless a host output is asked for). */
+
+#define GSR_ADAM_MAX_GROUPS 8
+#define GSR_DENSIFY_MAX_COLUMNS 16
+
+enum gsr_activation {
+    GSR_ACT_NONE = 0,     /* the rasterizer takes the raw value               */
+    GSR_ACT_EXP = 1,      /* it takes exp(raw) (scales)                       */
+    GSR_ACT_SIGMOID = 2   /* it takes 1 / (1 + exp(-raw)) (opacities)         */
+};
+
+/* One parameter tensor of gsr_adam_step. */
+typedef struct gsr_adam_group {
+    float *param;          /* [n] raw values, updated in place                                 */
+    const float *grad;     /* [n] gradient with respect to the ACTIVATED value                  */
+    float *exp_avg;        /* [n] first moment, updated in place (zero before the first step)   */
+    float *exp_avg_sq;     /* [n] second moment, updated in place                                */
+    float *activated;      /* [n] nullable: receives act(param) after the update                 */
+    int64_t n;             /* elements (0 allowed)                                               */
+    float lr;              /* learning rate                                                      */
+    float lr_rest;         /* learning rate of elements i with row > 0 and i % row >= row_first  */
+    int32_t row;           /* 0: lr for every element; else the row length of the split          */
+    int32_t row_first;     /* elements of a row that take lr (SH: the 3 degree-0 coefficients)  */
+    int32_t activation;    /* gsr_activation                                                     */
+    float reg;             /* L1 penalty weight per element on the activated value (> 0 values):
+                              added to the activated gradient; must be 0 with GSR_ACT_NONE      */
+} gsr_adam_group;
+
+/* out_i = act(raw_i) for n values (the activated scales or opacities the
+ * rasterizer takes; the same arithmetic as gsr_adam_step's activated output).
+ * out may be raw (in place). */
+int gsr_activate(int64_t n, const float *raw, int32_t activation, float *out, gsr_stream_t stream);
+
+/* L1 photometric loss over n values (the paper leaves the loss open; this is
+ * the mean absolute error when scale = 1/n):
+ *   loss[0] = scale * sum_i |image_i - target_i|  (device float; block
+ *             partial sums in float, combined in double in a fixed order, so
+ *             the value depends on n and the data only),
+ *   v_image_i = scale * sign(image_i - target_i), sign(0) = 0.
+ * v_image may alias neither input.  ws: gsr_workspace_bytes(GSR_OP_L1_LOSS,
+ * 0, 0, n) bytes.  n = 0 writes loss = 0. */
+int gsr_l1_loss(int64_t n, const float *image, const float *target, float scale, float *v_image, float *loss,
+                void *ws, size_t ws_bytes, gsr_stream_t stream);
+
+/* Adam (Kingma and Ba, with bias correction) on up to GSR_ADAM_MAX_GROUPS
+ * tensors in one launch, at step t >= 1:
+ *   g = grad                                  (GSR_ACT_NONE)
+ *   g = (grad + reg) * exp(param)             (GSR_ACT_EXP)
+ *   g = (grad + reg) * o (1 - o), o = sigmoid(param)   (GSR_ACT_SIGMOID)
+ *   m = beta1 m + (1 - beta1) g;  v = beta2 v + (1 - beta2) g^2
+ *   param -= lr_i * (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps)
+ *   activated = act(param).
+ * Groups must not overlap.  Errors: n_groups outside 0..GSR_ADAM_MAX_GROUPS,
+ * t < 1, betas outside [0, 1), eps < 0, a NULL required pointer, reg != 0
+ * without an activation. */
+int gsr_adam_step(int n_groups, const gsr_adam_group *groups, int32_t step, float beta1, float beta2, float eps,
+                  gsr_stream_t stream);
+
+/* ADC statistics (ADC and Absgrad): for every Gaussian n, over the cameras c
+ * with radii[c,n] > 0,
+ *   grad_accum[n] += sum_c scale * |(v_x W[c] / 2, v_y H[c] / 2)|,
+ *   count[n]      += number of such cameras,
+ * with (v_x, v_y) = v_means2d[c,n] (pass the absolute sums of
+ * gsr_rasterize_bwd's v_means2d_abs for Absgrad).  The factors W/2, H/2 turn
+ * pixel gradients into gradients with respect to normalised device
+ * coordinates, the units of the paper's threshold 0.0002; scale is the number
+ * of views a loss averaged over, so the statistic is that of a per-view loss.
+ * Cameras are summed in order per Gaussian (deterministic). */
+int gsr_densify_stats(int C, int N, const int32_t *W, const int32_t *H, const int32_t *radii,
+                      const float *v_means2d, float scale, float *grad_accum, int32_t *count, gsr_stream_t stream);
+
+enum gsr_densify_action {
+    GSR_PRUNE = 0,   /* removed                                           */
+    GSR_KEEP = 1,    /* one output slot, copied                           */
+    GSR_CLONE = 2,   /* two slots: the original and a copy                */
+    GSR_SPLIT = 3    /* two slots: children sampled from N(mu, Sigma)      */
+};
+
+/* ADC plan: per Gaussian (float32 comparisons),
+ *   PRUNE if opacities[n] < prune_opacity; else
+ *   SPLIT if count[n] > 0 and grad_accum[n] > grad_threshold * count[n] and
+ *         max(scales[n]) > scale_threshold;
+ *   CLONE under the same gradient test otherwise; else KEEP.
+ * scales [N,3] and opacities [N] are the activated values.  Writes action
+ * [N] and offsets [N+1] (int64, exclusive prefix sums of the slots 0/1/2/2;
+ * offsets[N] is the new count).  total_host (nullable): the new count is also
+ * copied to the host, and the call then waits for the stream.  Pass
+ * grad_threshold = +inf for pruning alone, prune_opacity = 0 for none.
+ * ws: gsr_workspace_bytes(GSR_OP_DENSIFY_PLAN, 0, N, 0) bytes. */
+int gsr_densify_plan(int N, const float *grad_accum, const int32_t *count, const float *scales,
+                     const float *opacities, float grad_threshold, float scale_threshold, float prune_opacity,
+                     int32_t *action, int64_t *offsets, int64_t *total_host, void *ws, size_t ws_bytes,
+                     gsr_stream_t stream);
+
+enum gsr_column_kind {
+    GSR_COLUMN_COPY = 0,        /* every output slot copies the row                        */
+    GSR_COLUMN_MEANS = 1,       /* width 3; split children: mu + R(q) diag(exp(ls)) eta_k  */
+    GSR_COLUMN_LOG_SCALES = 2,  /* width 3; split children: ls - log(split_shrink)         */
+    GSR_COLUMN_STATE = 3        /* optimiser state: copied for KEEP and a clone's original,
+                                   zero for a clone's copy and both split children         */
+};
+
+/* One per-Gaussian array of gsr_densify_apply: src [N,width] -> dst
+ * [offsets[N],width] (dst must not overlap src). */
+typedef struct gsr_densify_column {
+    const float *src;
+    float *dst;
+    int32_t width;   /* floats per Gaussian, 1..4096 */
+    int32_t kind;    /* gsr_column_kind */
+} gsr_densify_column;
+
+/* ADC apply (the paper's split and clone): Gaussian n with action and
+ * offsets from gsr_densify_plan writes its slots offsets[n] .. offsets[n+1]-1
+ * of every column, in input order.  quats [N,4] (w,x,y,z, normalised here)
+ * and log_scales [N,3] are the raw parameters the split children are drawn
+ * with; split_normals [N,2,3] are standard normal draws eta_k (an input: the
+ * library draws no random numbers).  Required when a MEANS column is given;
+ * log(split_shrink) is subtracted from a split child's log-scales (3D
+ * Gaussian Splatting divides the scale by 1.6). */
+int gsr_densify_apply(int N, const int32_t *action, const int64_t *offsets, const float *quats,
+                      const float *log_scales, const float *split_normals, float split_shrink, int n_columns,
+                      const gsr_densify_column *columns, gsr_stream_t stream);
+
+/* ADC opacity reset: logits[n] = min(logits[n], logit(max_opacity)), so the
+ * opacity becomes min(o, max_opacity); the Adam moments of the logits are
+ * cleared; opacities (nullable) receives sigmoid(logits). 0 < max_opacity < 1. */
+int gsr_opacity_reset(int N, float *logits, float *exp_avg, float *exp_avg_sq, float *opacities,
+                      float max_opacity, gsr_stream_t stream);
+
+/* MCMC noise on the centres (the MCMC strategy's SGLD update):
+ *   means[n] += coeff * sigmoid(-k (o_n - t)) * Sigma_n eta_n,
+ *   Sigma_n = R(q_n) diag(s_n)^2 R(q_n)^T,
+ * with quats [N,4] (normalised here), scales [N,3] and opacities [N]
+ * activated, normals [N,3] standard normal draws (an input), and coeff =
+ * lambda_noise * lr of the means.  The cited MCMC work uses k = 100 and
+ * t = 0.005. */
+int gsr_mcmc_noise(int N, float *means, const float *quats, const float *scales, const float *opacities,
+                   const float *normals, float coeff, float k, float t, gsr_stream_t stream);
 
 #ifdef __cplusplus
 }

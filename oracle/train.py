@@ -225,7 +225,8 @@ def train_step(o, P, raw, state, cams, targets, step, lrs, views, absgrad=False,
     raw parameter with Adam.  ``raw``: means, quats, log_scales, logits, sh;
     ``state``: per parameter (m, v), plus "accum" and "count"; ``lrs``: lr of
     each parameter and "sh_rest".  Returns (loss, new raw, new state,
-    raw-parameter gradients)."""
+    gradients): the raw-parameter gradients by name, and under "activated"
+    the gradients with respect to what the rasterizer took."""
     scales = np.exp(_f64(raw["log_scales"]))
     opac = 1.0 / (1.0 + np.exp(-_f64(raw["logits"])))
     scene = dict(means=raw["means"], quats=raw["quats"], scales=scales, opacities=opac, sh=raw["sh"])
@@ -240,13 +241,14 @@ def train_step(o, P, raw, state, cams, targets, step, lrs, views, absgrad=False,
                        cv["W"], cv["H"], g2["v_means2d"], g2["v_conics"], g2["v_colors"], g2["v_opacities"])
     v2 = g2["v_means2d_abs"] if absgrad else g2["v_means2d"]
     acc, cnt = densify_stats(proj["radii"], v2, cv["W"], cv["H"], float(len(views)), state["accum"], state["count"])
-    new_raw, new_state, grads = {}, {"accum": acc, "count": cnt}, {}
+    new_raw, new_state, grads = {}, {"accum": acc, "count": cnt}, {"activated": {}}
     groups = (("means", "v_means", ACT_NONE, 0.0), ("quats", "v_quats", ACT_NONE, 0.0),
               ("log_scales", "v_scales", ACT_EXP, scale_reg / max(np.size(raw["log_scales"]), 1)),
               ("logits", "v_opacities", ACT_SIGMOID, opacity_reg / max(np.size(raw["logits"]), 1)),
               ("sh", "v_sh", ACT_NONE, 0.0))
     for name, gname, kind, reg in groups:
         g_act = g3[gname]
+        grads["activated"][name] = _f64(g_act)
         grads[name] = raw_gradient(_f64(raw[name]).reshape(-1), _f64(g_act).reshape(-1), kind, reg)
         kw = {}
         if name == "sh" and np.ndim(raw["sh"]) == 3:

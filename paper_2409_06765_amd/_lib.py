@@ -18,10 +18,15 @@ GSR_OK, GSR_EINVAL, GSR_EOVERFLOW, GSR_EWORKSPACE, GSR_EHIP = 0, 1, 2, 3, 4
 GSR_OP_INTERSECT_COUNT, GSR_OP_SORT, GSR_OP_RASTERIZE, GSR_OP_BIN_PREPARE, GSR_OP_BIN_FINISH = 1, 2, 3, 4, 5
 GSR_OP_PROJECT_BWD = 6
 GSR_OP_TILE_ORDER = 7
+GSR_OP_L1_LOSS, GSR_OP_DENSIFY_PLAN = 8, 9
+GSR_ADAM_MAX_GROUPS, GSR_DENSIFY_MAX_COLUMNS = 8, 16
+GSR_ACT_NONE, GSR_ACT_EXP, GSR_ACT_SIGMOID = 0, 1, 2
+GSR_PRUNE, GSR_KEEP, GSR_CLONE, GSR_SPLIT = 0, 1, 2, 3
+GSR_COLUMN_COPY, GSR_COLUMN_MEANS, GSR_COLUMN_LOG_SCALES, GSR_COLUMN_STATE = 0, 1, 2, 3
 GSR_MAX_CAMERAS = 64
 GSR_BWD_ACCUMULATE, GSR_BWD_PACKED = 1, 2
 GSR_DEPTH_NONE, GSR_DEPTH_ACCUMULATED, GSR_DEPTH_EXPECTED = 0, 1, 2
-ABI_VERSION = 6                 # the signatures below
+ABI_VERSION = 7                 # the signatures below
 _NAMES = {0: "GSR_OK", 1: "GSR_EINVAL", 2: "GSR_EOVERFLOW", 3: "GSR_EWORKSPACE", 4: "GSR_EHIP"}
 
 
@@ -39,7 +44,20 @@ class gsr_params(ctypes.Structure):
                 ("colors_shared", ctypes.c_int32), ("tile_cull", ctypes.c_int32)]
 
 
+class gsr_adam_group(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("exp_avg", ctypes.c_void_p),
+                ("exp_avg_sq", ctypes.c_void_p), ("activated", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("lr", ctypes.c_float), ("lr_rest", ctypes.c_float), ("row", ctypes.c_int32),
+                ("row_first", ctypes.c_int32), ("activation", ctypes.c_int32), ("reg", ctypes.c_float)]
+
+
+class gsr_densify_column(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("width", ctypes.c_int32),
+                ("kind", ctypes.c_int32)]
+
+
 _vp, _i, _i64, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+_f = ctypes.c_float
 _P = ctypes.POINTER(gsr_params)
 _SIGS = {
     "gsr_abi_version": ([], _i),
@@ -58,6 +76,14 @@ _SIGS = {
     "gsr_rasterize_fwd": ([_P, _i, _i, _i, _vp, _vp] + [_vp] * 10 + [_vp] * 5 + [_vp, _sz, _vp], _i),
     "gsr_rasterize_bwd": ([_P, _i, _i, _i, _vp, _vp] + [_vp] * 15 + [_vp] * 6 + [_vp, _sz, _i, _vp], _i),
     "gsr_project_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 9 + [_vp] * 5 + [_vp] * 5 + [_vp, _vp, _sz, _vp], _i),
+    "gsr_l1_loss": ([_i64, _vp, _vp, _f, _vp, _vp, _vp, _sz, _vp], _i),
+    "gsr_activate": ([_i64, _vp, ctypes.c_int32, _vp, _vp], _i),
+    "gsr_adam_step": ([_i, ctypes.POINTER(gsr_adam_group), ctypes.c_int32, _f, _f, _f, _vp], _i),
+    "gsr_densify_stats": ([_i, _i, _vp, _vp, _vp, _vp, _f, _vp, _vp, _vp], _i),
+    "gsr_densify_plan": ([_i, _vp, _vp, _vp, _vp, _f, _f, _f, _vp, _vp, _vp, _vp, _sz, _vp], _i),
+    "gsr_densify_apply": ([_i, _vp, _vp, _vp, _vp, _vp, _f, _i, ctypes.POINTER(gsr_densify_column), _vp], _i),
+    "gsr_opacity_reset": ([_i, _vp, _vp, _vp, _vp, _f, _vp], _i),
+    "gsr_mcmc_noise": ([_i, _vp, _vp, _vp, _vp, _vp, _f, _f, _f, _vp], _i),
 }
 
 _lib = None
@@ -242,3 +268,85 @@ def gsr_project_bwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors
         _ptr(v_means, F32, "v_means"), _ptr(v_quats, F32, "v_quats"), _ptr(v_scales, F32, "v_scales"),
         _ptr(v_opacities, F32, "v_opacities"), _ptr(v_sh_or_colors, F32, "v_sh_or_colors"),
         _ptr(v_viewmats, F32, "v_viewmats"), *_ws(ws), _stream(stream)))
+
+
+# ---- training-loop steps ----------------------------------------------------------
+def gsr_l1_loss(image, target, scale, v_image, loss, ws, stream=None):
+    n = image.numel()
+    if target.numel() != n or v_image.numel() != n:
+        raise ValueError("image, target and v_image must have the same number of elements")
+    _check(lib().gsr_l1_loss(n, _ptr(image, F32, "image"), _ptr(target, F32, "target"), float(scale),
+                             _ptr(v_image, F32, "v_image"), _ptr(loss, F32, "loss"), *_ws(ws), _stream(stream)))
+
+
+def gsr_activate(raw, activation, out, stream=None):
+    if raw.numel() != out.numel():
+        raise ValueError("raw and out must have the same number of elements")
+    _check(lib().gsr_activate(raw.numel(), _ptr(raw, F32, "raw"), int(activation), _ptr(out, F32, "out"),
+                              _stream(stream)))
+
+
+def gsr_adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    """groups: dicts with param, grad, exp_avg, exp_avg_sq (tensors of one
+    size), optional activated, lr, lr_rest, row, row_first, activation, reg."""
+    arr = (gsr_adam_group * max(len(groups), 1))()
+    keep = []
+    for i, g in enumerate(groups):
+        n = g["param"].numel()
+        for k in ("grad", "exp_avg", "exp_avg_sq", "activated"):
+            if g.get(k) is not None and g[k].numel() != n:
+                raise ValueError(f"group {i}: {k} has {g[k].numel()} elements, param {n}")
+        e = arr[i]
+        e.param, e.grad = _ptr(g["param"], F32, "param"), _ptr(g["grad"], F32, "grad")
+        e.exp_avg, e.exp_avg_sq = _ptr(g["exp_avg"], F32, "exp_avg"), _ptr(g["exp_avg_sq"], F32, "exp_avg_sq")
+        e.activated = _ptr(g.get("activated"), F32, "activated")
+        e.n = n
+        e.lr = float(g["lr"])
+        e.lr_rest = float(g.get("lr_rest", g["lr"]))
+        e.row, e.row_first = int(g.get("row", 0)), int(g.get("row_first", 0))
+        e.activation, e.reg = int(g.get("activation", GSR_ACT_NONE)), float(g.get("reg", 0.0))
+        keep.append(g)
+    _check(lib().gsr_adam_step(len(groups), arr, int(step), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def gsr_densify_stats(C, N, W, H, radii, v_means2d, scale, grad_accum, count, stream=None):
+    _check(lib().gsr_densify_stats(C, N, _sizes(W), _sizes(H), _ptr(radii, I32, "radii"),
+                                   _ptr(v_means2d, F32, "v_means2d"), float(scale), _ptr(grad_accum, F32, "grad_accum"),
+                                   _ptr(count, I32, "count"), _stream(stream)))
+
+
+def gsr_densify_plan(N, grad_accum, count, scales, opacities, grad_threshold, scale_threshold, prune_opacity,
+                     action, offsets, ws, sync=True, stream=None):
+    """Returns the new count when ``sync`` (the call then waits)."""
+    host = ctypes.c_int64(-1)
+    _check(lib().gsr_densify_plan(N, _ptr(grad_accum, F32, "grad_accum"), _ptr(count, I32, "count"),
+                                  _ptr(scales, F32, "scales"), _ptr(opacities, F32, "opacities"),
+                                  float(grad_threshold), float(scale_threshold), float(prune_opacity),
+                                  _ptr(action, I32, "action"), _ptr(offsets, I64, "offsets"),
+                                  ctypes.byref(host) if sync else None, *_ws(ws), _stream(stream)))
+    return int(host.value) if sync else None
+
+
+def gsr_densify_apply(N, action, offsets, quats, log_scales, split_normals, split_shrink, columns, stream=None):
+    """columns: (src, dst, kind) triples; the width is src.numel() / N."""
+    arr = (gsr_densify_column * max(len(columns), 1))()
+    for i, (src, dst, kind) in enumerate(columns):
+        w = src.numel() // N if N > 0 else 1
+        arr[i].src, arr[i].dst = _ptr(src, F32, "src"), _ptr(dst, F32, "dst")
+        arr[i].width, arr[i].kind = int(w), int(kind)
+    _check(lib().gsr_densify_apply(N, _ptr(action, I32, "action"), _ptr(offsets, I64, "offsets"),
+                                   _ptr(quats, F32, "quats"), _ptr(log_scales, F32, "log_scales"),
+                                   _ptr(split_normals, F32, "split_normals"), float(split_shrink), len(columns), arr,
+                                   _stream(stream)))
+
+
+def gsr_opacity_reset(N, logits, exp_avg, exp_avg_sq, opacities, max_opacity, stream=None):
+    _check(lib().gsr_opacity_reset(N, _ptr(logits, F32, "logits"), _ptr(exp_avg, F32, "exp_avg"),
+                                   _ptr(exp_avg_sq, F32, "exp_avg_sq"), _ptr(opacities, F32, "opacities"),
+                                   float(max_opacity), _stream(stream)))
+
+
+def gsr_mcmc_noise(N, means, quats, scales, opacities, normals, coeff, k=100.0, t=0.005, stream=None):
+    _check(lib().gsr_mcmc_noise(N, _ptr(means, F32, "means"), _ptr(quats, F32, "quats"), _ptr(scales, F32, "scales"),
+                                _ptr(opacities, F32, "opacities"), _ptr(normals, F32, "normals"), float(coeff),
+                                float(k), float(t), _stream(stream)))

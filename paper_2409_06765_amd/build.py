@@ -29,6 +29,7 @@ UNITS = {
     "intersect.hip": ["-ffp-contract=off"],
     "raster_fwd.hip": [],
     "raster_bwd.hip": ["-munsafe-fp-atomics"],
+    "train.hip": [],
 }
 
 

@@ -118,6 +118,8 @@ size_t gsr_workspace_bytes(int op, int C, int N, int64_t M) {
         case GSR_OP_BIN_FINISH: return bin_finish_bytes(M > 0 ? M : 0);
         case GSR_OP_PROJECT_BWD: return pose_workspace_bytes(C > 0 ? C : 0, N > 0 ? N : 0);
         case GSR_OP_TILE_ORDER: return tile_order_bytes();
+        case GSR_OP_L1_LOSS: return (size_t)kL1Blocks * sizeof(double);
+        case GSR_OP_DENSIFY_PLAN: return densify_plan_bytes(N > 0 ? N : 0);
         default: return 0;
     }
 }
@@ -378,3 +380,146 @@ int gsr_project_bwd(const gsr_params *p, int C, int N, const int32_t *W, const i
 }
 
 }  // extern "C"
+
+// ---- training-loop steps ----------------------------------------------------------------
+int gsr_l1_loss(int64_t n, const float *image, const float *target, float scale, float *v_image, float *loss,
+                void *ws, size_t ws_bytes, gsr_stream_t stream) {
+    static const char *fn = "gsr_l1_loss";
+    if (n < 0) return fail(GSR_EINVAL, "%s: n < 0", fn);
+    GSR_NEED(loss);
+    if (n == 0) return launch_fill_zero(loss, sizeof(float), (hipStream_t)stream);
+    GSR_NEED(image); GSR_NEED(target); GSR_NEED(v_image);
+    if (v_image == image || v_image == target) return fail(GSR_EINVAL, "%s: v_image aliases an input", fn);
+    const size_t need = (size_t)kL1Blocks * sizeof(double);
+    if (!ws || ws_bytes < need) return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed", fn, need);
+    return launch_l1_loss(n, image, target, scale, v_image, loss, ws, (hipStream_t)stream);
+}
+
+int gsr_activate(int64_t n, const float *raw, int32_t activation, float *out, gsr_stream_t stream) {
+    static const char *fn = "gsr_activate";
+    if (n < 0 || n > ((int64_t)INT32_MAX << 8)) return fail(GSR_EINVAL, "%s: n out of range", fn);
+    if (activation < GSR_ACT_NONE || activation > GSR_ACT_SIGMOID)
+        return fail(GSR_EINVAL, "%s: unknown activation %d", fn, activation);
+    if (n == 0) return GSR_OK;
+    GSR_NEED(raw); GSR_NEED(out);
+    return launch_activate(n, raw, activation, out, (hipStream_t)stream);
+}
+
+int gsr_adam_step(int n_groups, const gsr_adam_group *groups, int32_t step, float beta1, float beta2, float eps,
+                  gsr_stream_t stream) {
+    static const char *fn = "gsr_adam_step";
+    if (n_groups < 0 || n_groups > GSR_ADAM_MAX_GROUPS)
+        return fail(GSR_EINVAL, "%s: n_groups must be in 0..%d", fn, GSR_ADAM_MAX_GROUPS);
+    if (n_groups > 0 && !groups) return fail(GSR_EINVAL, "%s: groups is NULL", fn);
+    if (step < 1) return fail(GSR_EINVAL, "%s: step must be >= 1", fn);
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
+        return fail(GSR_EINVAL, "%s: betas must be in [0, 1)", fn);
+    if (!(eps >= 0.0f)) return fail(GSR_EINVAL, "%s: eps must be >= 0", fn);
+    AdamLaunch a;
+    memset(&a, 0, sizeof(a));
+    for (int i = 0; i < n_groups; i++) {
+        const gsr_adam_group &g = groups[i];
+        if (g.n < 0) return fail(GSR_EINVAL, "%s: group %d: n < 0", fn, i);
+        if (g.activation < GSR_ACT_NONE || g.activation > GSR_ACT_SIGMOID)
+            return fail(GSR_EINVAL, "%s: group %d: unknown activation %d", fn, i, g.activation);
+        if (g.activation == GSR_ACT_NONE && g.reg != 0.0f)
+            return fail(GSR_EINVAL, "%s: group %d: reg needs an activation", fn, i);
+        if (g.row < 0 || g.row_first < 0) return fail(GSR_EINVAL, "%s: group %d: row < 0", fn, i);
+        if (g.n > 0 && (!g.param || !g.grad || !g.exp_avg || !g.exp_avg_sq))
+            return fail(GSR_EINVAL, "%s: group %d: NULL tensor", fn, i);
+        a.g[i] = g;
+    }
+    a.n_groups = n_groups;
+    a.beta1 = beta1;
+    a.beta2 = beta2;
+    a.eps = eps;
+    a.inv_bc1 = 1.0 / (1.0 - pow((double)beta1, (double)step));
+    a.inv_bc2 = 1.0 / (1.0 - pow((double)beta2, (double)step));
+    return launch_adam(a, (hipStream_t)stream);
+}
+
+int gsr_densify_stats(int C, int N, const int32_t *W, const int32_t *H, const int32_t *radii,
+                      const float *v_means2d, float scale, float *grad_accum, int32_t *count, gsr_stream_t stream) {
+    static const char *fn = "gsr_densify_stats";
+    CamTable cams;
+    int rc = make_cams(C, N, W, H, cams);
+    if (rc != GSR_OK) return rc;
+    if ((int64_t)C * N == 0) return GSR_OK;
+    GSR_NEED(radii); GSR_NEED(v_means2d); GSR_NEED(grad_accum); GSR_NEED(count);
+    return launch_densify_stats(cams, N, radii, v_means2d, scale, grad_accum, count, (hipStream_t)stream);
+}
+
+int gsr_densify_plan(int N, const float *grad_accum, const int32_t *count, const float *scales,
+                     const float *opacities, float grad_threshold, float scale_threshold, float prune_opacity,
+                     int32_t *action, int64_t *offsets, int64_t *total_host, void *ws, size_t ws_bytes,
+                     gsr_stream_t stream) {
+    static const char *fn = "gsr_densify_plan";
+    if (N < 0 || N > INT32_MAX / 2) return fail(GSR_EINVAL, "%s: N must be in 0..2^30", fn);
+    GSR_NEED(offsets);
+    if (N > 0) { GSR_NEED(grad_accum); GSR_NEED(count); GSR_NEED(scales); GSR_NEED(opacities); GSR_NEED(action); }
+    if (grad_threshold != grad_threshold || scale_threshold != scale_threshold || prune_opacity != prune_opacity)
+        return fail(GSR_EINVAL, "%s: NaN threshold", fn);
+    const size_t need = densify_plan_bytes(N);
+    if (!ws || ws_bytes < need) return fail(GSR_EWORKSPACE, "%s: workspace of %zu bytes needed", fn, need);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = launch_densify_plan(N, grad_accum, count, scales, opacities, grad_threshold, scale_threshold,
+                                 prune_opacity, action, offsets, ws, s);
+    if (rc != GSR_OK || !total_host) return rc;
+    rc = hip_check(hipMemcpyAsync(total_host, offsets + N, sizeof(int64_t), hipMemcpyDeviceToHost, s), fn);
+    if (rc == GSR_OK) rc = hip_check(hipStreamSynchronize(s), fn);
+    return rc;
+}
+
+int gsr_densify_apply(int N, const int32_t *action, const int64_t *offsets, const float *quats,
+                      const float *log_scales, const float *split_normals, float split_shrink, int n_columns,
+                      const gsr_densify_column *columns, gsr_stream_t stream) {
+    static const char *fn = "gsr_densify_apply";
+    if (N < 0 || N > INT32_MAX / 2) return fail(GSR_EINVAL, "%s: N must be in 0..2^30", fn);
+    if (n_columns < 0 || n_columns > GSR_DENSIFY_MAX_COLUMNS)
+        return fail(GSR_EINVAL, "%s: n_columns must be in 0..%d", fn, GSR_DENSIFY_MAX_COLUMNS);
+    if (n_columns > 0 && !columns) return fail(GSR_EINVAL, "%s: columns is NULL", fn);
+    bool means = false, logs = false;
+    for (int i = 0; i < n_columns; i++) {
+        const gsr_densify_column &c = columns[i];
+        if (c.kind < GSR_COLUMN_COPY || c.kind > GSR_COLUMN_STATE)
+            return fail(GSR_EINVAL, "%s: column %d: unknown kind %d", fn, i, c.kind);
+        if (c.width < 1 || c.width > 4096) return fail(GSR_EINVAL, "%s: column %d: width must be in 1..4096", fn, i);
+        if ((c.kind == GSR_COLUMN_MEANS || c.kind == GSR_COLUMN_LOG_SCALES) && c.width != 3)
+            return fail(GSR_EINVAL, "%s: column %d: means and log-scales have width 3", fn, i);
+        if (N > 0 && (!c.src || !c.dst)) return fail(GSR_EINVAL, "%s: column %d: NULL array", fn, i);
+        if (N > 0 && c.src == c.dst) return fail(GSR_EINVAL, "%s: column %d: dst must not be src", fn, i);
+        means |= c.kind == GSR_COLUMN_MEANS;
+        logs |= c.kind == GSR_COLUMN_LOG_SCALES;
+    }
+    if (N == 0 || n_columns == 0) return GSR_OK;
+    GSR_NEED(action); GSR_NEED(offsets);
+    if (means) { GSR_NEED(quats); GSR_NEED(log_scales); GSR_NEED(split_normals); }
+    if (logs && !(split_shrink > 0.0f && split_shrink < 3.0e38f))
+        return fail(GSR_EINVAL, "%s: split_shrink must be positive and finite", fn);
+    const float log_shrink = logs ? (float)log((double)split_shrink) : 0.0f;
+    return launch_densify_apply(N, action, offsets, quats, log_scales, split_normals, log_shrink, n_columns, columns,
+                                (hipStream_t)stream);
+}
+
+int gsr_opacity_reset(int N, float *logits, float *exp_avg, float *exp_avg_sq, float *opacities,
+                      float max_opacity, gsr_stream_t stream) {
+    static const char *fn = "gsr_opacity_reset";
+    if (N < 0) return fail(GSR_EINVAL, "%s: N < 0", fn);
+    if (!(max_opacity > 0.0f && max_opacity < 1.0f)) return fail(GSR_EINVAL, "%s: need 0 < max_opacity < 1", fn);
+    if (N == 0) return GSR_OK;
+    GSR_NEED(logits); GSR_NEED(exp_avg); GSR_NEED(exp_avg_sq);
+    const double v = max_opacity;
+    return launch_opacity_reset(N, logits, exp_avg, exp_avg_sq, opacities, (float)log(v / (1.0 - v)),
+                                (hipStream_t)stream);
+}
+
+int gsr_mcmc_noise(int N, float *means, const float *quats, const float *scales, const float *opacities,
+                   const float *normals, float coeff, float k, float t, gsr_stream_t stream) {
+    static const char *fn = "gsr_mcmc_noise";
+    if (N < 0) return fail(GSR_EINVAL, "%s: N < 0", fn);
+    if (!(fabsf(coeff) < 3.0e38f) || !(fabsf(k) < 3.0e38f) || !(fabsf(t) < 3.0e38f))
+        return fail(GSR_EINVAL, "%s: coeff, k and t must be finite", fn);
+    if (N == 0) return GSR_OK;
+    GSR_NEED(means); GSR_NEED(quats); GSR_NEED(scales); GSR_NEED(opacities); GSR_NEED(normals);
+    return launch_mcmc_noise(N, means, quats, scales, opacities, normals, coeff, k, t, (hipStream_t)stream);
+}

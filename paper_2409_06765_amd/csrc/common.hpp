@@ -91,6 +91,37 @@ int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D
 
 int launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
 
+// Exclusive prefix sums of int32 counts into int64 offsets, total to *total
+// (device); ws of scan_workspace_bytes(n).
+size_t scan_workspace_bytes(int64_t n);
+int launch_scan_i32(int64_t n, const int32_t *counts, int64_t *offsets, int64_t *total, void *ws, hipStream_t s);
+
+// Training-loop steps (train.hip).
+constexpr int kL1Blocks = 1024;
+int launch_l1_loss(int64_t n, const float *image, const float *target, float scale, float *v_image, float *loss,
+                   void *ws, hipStream_t s);
+struct AdamLaunch {
+    gsr_adam_group g[GSR_ADAM_MAX_GROUPS];
+    int n_groups;
+    float beta1, beta2, eps;
+    double inv_bc1, inv_bc2;   // 1 / (1 - beta^t)
+};
+int launch_adam(const AdamLaunch &a, hipStream_t s);
+int launch_activate(int64_t n, const float *raw, int kind, float *out, hipStream_t s);
+int launch_densify_stats(const CamTable &cams, int N, const int32_t *radii, const float *v_means2d, float scale,
+                         float *accum, int32_t *count, hipStream_t s);
+size_t densify_plan_bytes(int N);
+int launch_densify_plan(int N, const float *accum, const int32_t *count, const float *scales, const float *opacities,
+                        float grad_threshold, float scale_threshold, float prune_opacity, int32_t *action,
+                        int64_t *offsets, void *ws, hipStream_t s);
+int launch_densify_apply(int N, const int32_t *action, const int64_t *offsets, const float *quats,
+                         const float *log_scales, const float *normals, float log_shrink, int n_columns,
+                         const gsr_densify_column *columns, hipStream_t s);
+int launch_opacity_reset(int N, float *logits, float *exp_avg, float *exp_avg_sq, float *opacities, float cap,
+                         hipStream_t s);
+int launch_mcmc_noise(int N, float *means, const float *quats, const float *scales, const float *opacities,
+                      const float *normals, float coeff, float k, float t, hipStream_t s);
+
 // ---- device helpers ----------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

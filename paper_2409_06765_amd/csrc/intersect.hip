@@ -900,6 +900,13 @@ CullIn cull_inputs(const gsr_params &p, const float *conics, const float *opacit
 }
 }  // namespace
 
+size_t scan_workspace_bytes(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t); }
+
+int launch_scan_i32(int64_t n, const int32_t *counts, int64_t *offsets, int64_t *total, void *ws, hipStream_t s) {
+    if (n == 0) return launch_fill_zero(total, sizeof(int64_t), s);
+    return scan_counts(n, counts, (int64_t *)ws, offsets, total, s);
+}
+
 int launch_bin_prepare(const gsr_params &p, const CamTable &cams, int N, const float *means2d,
                        const int32_t *radii, const float *depths, const float *conics, const float *opacities,
                        const float *comps, void *ws_prep, int64_t *total_dev, hipStream_t s) {

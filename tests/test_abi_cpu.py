@@ -104,3 +104,61 @@ def test_sort_and_workspace_validation(L):
                                    None) == L.GSR_EWORKSPACE
     assert lib.gsr_intersect_emit(ctypes.byref(p), 1, 10, W, W, fake, fake, fake, fake, -5, fake, fake,
                                   None) == L.GSR_EINVAL
+
+
+def test_training_entry_points_reject_bad_arguments(L):
+    """The training-loop calls validate before any launch (fake pointers are
+    never dereferenced)."""
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.workspace_bytes(L.GSR_OP_L1_LOSS, 0, 0, 10) >= 8
+    assert L.workspace_bytes(L.GSR_OP_DENSIFY_PLAN, 0, 1_000_000, 0) >= 4_000_000
+    # L1: negative n, aliasing, small workspace
+    assert lib.gsr_l1_loss(-1, fake, fake, 1.0, fake, fake, fake, 1 << 20, None) == L.GSR_EINVAL
+    assert lib.gsr_l1_loss(8, fake, fake, 1.0, fake, fake, fake, 1 << 20, None) == L.GSR_EINVAL
+    assert lib.gsr_l1_loss(8, fake, ctypes.c_void_p(0x2000), 1.0, ctypes.c_void_p(0x3000), fake, fake, 8,
+                           None) == L.GSR_EWORKSPACE
+    # Adam: group count, step, betas, reg without an activation
+    g = (L.gsr_adam_group * 1)()
+    g[0].param = g[0].grad = g[0].exp_avg = g[0].exp_avg_sq = 0x1000
+    g[0].n, g[0].lr = 4, 0.1
+    assert lib.gsr_adam_step(L.GSR_ADAM_MAX_GROUPS + 1, g, 1, 0.9, 0.999, 1e-15, None) == L.GSR_EINVAL
+    assert lib.gsr_adam_step(1, g, 0, 0.9, 0.999, 1e-15, None) == L.GSR_EINVAL
+    assert lib.gsr_adam_step(1, g, 1, 1.0, 0.999, 1e-15, None) == L.GSR_EINVAL
+    g[0].reg = 0.5
+    assert lib.gsr_adam_step(1, g, 1, 0.9, 0.999, 1e-15, None) == L.GSR_EINVAL
+    assert "reg" in lib.gsr_last_error().decode()
+    g[0].reg, g[0].activation = 0.0, 7
+    assert lib.gsr_adam_step(1, g, 1, 0.9, 0.999, 1e-15, None) == L.GSR_EINVAL
+    g[0].activation, g[0].grad = L.GSR_ACT_EXP, None
+    assert lib.gsr_adam_step(1, g, 1, 0.9, 0.999, 1e-15, None) == L.GSR_EINVAL
+    # plan: N range, NaN thresholds, workspace
+    assert lib.gsr_densify_plan(-1, fake, fake, fake, fake, 2e-4, 0.01, 0.005, fake, fake, None, fake, 1 << 30,
+                                None) == L.GSR_EINVAL
+    assert lib.gsr_densify_plan(4, fake, fake, fake, fake, float("nan"), 0.01, 0.005, fake, fake, None, fake,
+                                1 << 30, None) == L.GSR_EINVAL
+    assert lib.gsr_densify_plan(4096, fake, fake, fake, fake, 2e-4, 0.01, 0.005, fake, fake, None, fake, 16,
+                                None) == L.GSR_EWORKSPACE
+    # apply: column kinds, widths, aliasing, split inputs
+    cols = (L.gsr_densify_column * 2)()
+    cols[0].src, cols[0].dst, cols[0].width, cols[0].kind = 0x1000, 0x2000, 3, L.GSR_COLUMN_MEANS
+    cols[1].src, cols[1].dst, cols[1].width, cols[1].kind = 0x3000, 0x4000, 2, L.GSR_COLUMN_LOG_SCALES
+    assert lib.gsr_densify_apply(4, fake, fake, fake, fake, fake, 1.6, 2, cols, None) == L.GSR_EINVAL
+    cols[1].width = 3
+    assert lib.gsr_densify_apply(4, fake, fake, None, fake, fake, 1.6, 2, cols, None) == L.GSR_EINVAL
+    assert lib.gsr_densify_apply(4, fake, fake, fake, fake, fake, 0.0, 2, cols, None) == L.GSR_EINVAL
+    cols[1].kind = 9
+    assert lib.gsr_densify_apply(4, fake, fake, fake, fake, fake, 1.6, 2, cols, None) == L.GSR_EINVAL
+    cols[1].kind, cols[1].dst = L.GSR_COLUMN_COPY, 0x3000
+    assert lib.gsr_densify_apply(4, fake, fake, fake, fake, fake, 1.6, 2, cols, None) == L.GSR_EINVAL
+    assert lib.gsr_densify_apply(4, fake, fake, fake, fake, fake, 1.6, L.GSR_DENSIFY_MAX_COLUMNS + 1, cols,
+                                 None) == L.GSR_EINVAL
+    # opacity reset and MCMC noise
+    assert lib.gsr_opacity_reset(4, fake, fake, fake, None, 1.0, None) == L.GSR_EINVAL
+    assert lib.gsr_opacity_reset(4, fake, None, fake, None, 0.01, None) == L.GSR_EINVAL
+    assert lib.gsr_mcmc_noise(4, fake, fake, fake, fake, None, 1.0, 100.0, 0.005, None) == L.GSR_EINVAL
+    assert lib.gsr_mcmc_noise(4, fake, fake, fake, fake, fake, float("inf"), 100.0, 0.005, None) == L.GSR_EINVAL
+    # zero sizes are no-ops
+    assert lib.gsr_opacity_reset(0, None, None, None, None, 0.01, None) == L.GSR_OK
+    assert lib.gsr_mcmc_noise(0, None, None, None, None, None, 1.0, 100.0, 0.005, None) == L.GSR_OK
+    assert lib.gsr_densify_apply(0, None, None, None, None, None, 1.6, 0, None, None) == L.GSR_OK
