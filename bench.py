@@ -54,24 +54,25 @@ WORKLOADS = {
 }
 
 
-def measured_traffic():
-    """HBM bytes per launch of the backward compositing kernel from the
-    committed counter summary, or None when the kernel's sources have changed
-    since the counters were taken (the summary records their sha256)."""
+def measured_traffic(summary="raster_bwd_clusters1m_sh3_1080p_traffic.md", sources=("raster_bwd.hip", "common.hpp"),
+                     key="traffic_bytes_per_launch"):
+    """HBM bytes per launch of a kernel from its committed counter summary,
+    or None when the kernel's sources have changed since the counters were
+    taken (the summary records their sha256)."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "raster_bwd_clusters1m_sh3_1080p_traffic.md")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    t = re.search(r"^traffic_bytes_per_launch: (\d+)$", text, re.M)
+    t = re.search(rf"^{key}: ([0-9.]+)$", text, re.M)
     h = re.search(r"^source_sha256: ([0-9a-f]{64})$", text, re.M)
     if not (t and h):
         return None
     sha = hashlib.sha256()
-    for f in ("raster_bwd.hip", "common.hpp"):
+    for f in sources:
         sha.update(open(os.path.join(ROOT, "paper_2409_06765_amd", "csrc", f), "rb").read())
-    return int(t.group(1)) if sha.hexdigest() == h.group(1) else None
+    return float(t.group(1)) if sha.hexdigest() == h.group(1) else None
 
 
 def log(msg):
@@ -87,6 +88,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-tiles", type=int, default=96, help="tiles of view 0 the oracle rasterizes")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--train-steps", type=int, default=200,
+                    help="timed steps of the training leg (0 skips it; 1M workload only)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (the reference for traffic counters)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -200,7 +203,10 @@ def main():
     fwd_tflops = fwd_flops / (stage_ms["rasterize_fwd"] * 1e-3) / 1e12
     roofline = {"kernel": "raster_bwd_rgb_kernel", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": measured_traffic() if args.workload == "clusters1m_sh3_1080p" else None}
+                "traffic": None}
+    if args.workload == "clusters1m_sh3_1080p":
+        t = measured_traffic()
+        roofline["traffic"] = None if t is None else int(t)
 
     out = {
         "metric": METRIC,
@@ -225,6 +231,8 @@ def main():
     }
     if not args.no_serve and args.workload == "clusters1m_sh3_1080p":
         out["serving"] = serving(d, p, args)
+    if args.train_steps > 0 and args.workload == "clusters1m_sh3_1080p":
+        out["training"] = training(sc, cams, wl, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, cams, wl, args, counts, views[0])
     print(json.dumps(out), flush=True)
@@ -260,6 +268,117 @@ def serving(d, p, args):
     return {"requests": args.serve_requests, "arrival_rate_per_s": round(rate, 2),
             "one_view_capacity_views_per_s": round(cap.views_per_s, 2),
             "batched": pick(batched), "one_view_per_launch": pick(single)}
+
+
+# Adam moves per element: param, exp_avg, exp_avg_sq read and written, the
+# gradient read (28 bytes), plus the activated value written for the scales
+# and opacities (4 bytes).
+ADAM_BYTES_PER_ELEM, ACT_BYTES_PER_ELEM = 28, 4
+
+
+def training(sc, cams, wl, args):
+    """Synthetic fit of the 1M-Gaussian scene: targets are renders of the
+    scene itself from the 16 views (untimed), the start is the scene with
+    jittered centres and colours.  One view per step; ADC statistics every
+    step and one refinement (plan, split / clone / prune, apply) at the last
+    timed step, so its cost is amortised over the window; then the same
+    window with the MCMC strategy.  The Adam launch is timed alone on the
+    final parameter set for its roofline."""
+    import torch
+    from paper_2409_06765_amd import _lib as L
+    from paper_2409_06765_amd.train import GaussianTrainer, TrainConfig
+
+    dev = "cuda:0"
+    raw = dict(means=sc["means"], quats=sc["quats"], log_scales=np.log(sc["scales"]),
+               logits=np.log(sc["opacities"] / (1.0 - sc["opacities"])), sh=sc["sh"])
+    V, H, W = len(cams["W"]), int(cams["H"][0]), int(cams["W"][0])
+    gt = GaussianTrainer(raw, cams, torch.zeros((V, H, W, 3)), TrainConfig(strategy="none"),
+                         sh_degree=wl["sh_degree"])
+    targets = torch.stack([gt.render([v])[-1]["image"].reshape(H, W, 3) for v in range(V)])
+    del gt
+    g = np.random.default_rng(7)
+    start = dict(raw)
+    start["means"] = (raw["means"] + g.normal(0, 0.01, raw["means"].shape)).astype(np.float32)
+    start["sh"] = raw["sh"].copy()
+    start["sh"][:, 0, :] += g.normal(0, 0.1, start["sh"][:, 0, :].shape).astype(np.float32)
+    warm, K = 10, args.train_steps
+    out = {"workload": f"fit of {args.workload} to its own renders from {V} views, one view per step",
+           "steps_timed": K, "warmup": warm}
+    for strategy in ("adc", "mcmc"):
+        # ADC: one refinement at the end of the warm-up (first launches of every kernel), none in the timed
+        # window, then one more refinement timed on its own
+        cfg = TrainConfig(strategy=strategy, refine_start=0, refine_every=warm, reset_every=10 ** 9,
+                          lr_decay_steps=30_000)
+        tr = GaussianTrainer(start, cams, targets, cfg, sh_degree=wl["sh_degree"])
+        for _ in range(warm):
+            tr.step()
+        tr.cfg.refine_every = 10 ** 9
+        torch.cuda.synchronize()
+        N0 = tr.N
+        losses = []
+        host = 0.0
+        t0 = time.perf_counter()
+        for _ in range(K):
+            th = time.perf_counter()
+            losses.append(tr.step())
+            host += time.perf_counter() - th
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ls = [float(x) for x in torch.cat(losses).cpu()]
+        res = {"ms_per_step": round(1e3 * dt / K, 4), "steps_per_s": round(K / dt, 2),
+               "host_ms_per_step": round(1e3 * host / K, 4), "n_gaussians": N0,
+               "loss_first": round(ls[0], 6), "loss_last": round(ls[-1], 6)}
+        if strategy == "adc":
+            t0 = time.perf_counter()
+            n_new = tr.densify()
+            torch.cuda.synchronize()
+            refine_ms = 1e3 * (time.perf_counter() - t0)
+            res.update(refine_ms=round(refine_ms, 3), refine_n=[N0, n_new],
+                       ms_per_step_refine_every_100=round(1e3 * dt / K + refine_ms / 100, 4))
+        out[strategy] = res
+        log(f"training {strategy}: {res}")
+    # the Adam launch alone, on the last trainer's parameters and gradients
+    names = ("means", "quats", "log_scales", "logits", "sh")
+    gk = dict(means="v_means", quats="v_quats", log_scales="v_scales", logits="v_opacities", sh="v_sh")
+    N = tr.N
+    grads = {k: torch.zeros_like(tr.raw[k]) for k in names}
+    groups = [dict(param=tr.raw[k], grad=grads[k], exp_avg=tr.m[k], exp_avg_sq=tr.v[k], lr=1e-4,
+                   activated=tr.scales if k == "log_scales" else (tr.opacities if k == "logits" else None),
+                   activation=L.GSR_ACT_EXP if k == "log_scales" else (L.GSR_ACT_SIGMOID if k == "logits" else 0),
+                   row=48 if k == "sh" else 0, row_first=3 if k == "sh" else 0, lr_rest=1e-4) for k in names]
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        L.gsr_adam_step(groups, 1000)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 20
+    ev[0].record(s)
+    for _ in range(reps):
+        L.gsr_adam_step(groups, 1000, stream=s)
+    ev[1].record(s)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    elems = sum(tr.raw[k].numel() for k in names)
+    nbytes = ADAM_BYTES_PER_ELEM * elems + ACT_BYTES_PER_ELEM * (tr.raw["log_scales"].numel() + N)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    traffic_per_elem = measured_traffic("adam_clusters1m_sh3_traffic.md", ("train.hip", "common.hpp"),
+                                        key="traffic_bytes_per_element")
+    # reference: a plain device copy moving about as many bytes (half read, half written)
+    src = torch.ones(nbytes // 8, device=dev, dtype=torch.float32)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev[0].record(s)
+    for _ in range(reps):
+        dst.copy_(src)
+    ev[1].record(s)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 4 / (ev[0].elapsed_time(ev[1]) / reps * 1e-3) / 1e9
+    del src, dst
+    out["adam"] = {"kernel": "adam_kernel", "bound": "hbm", "elements": elems, "bytes": nbytes, "ms": round(ms, 4),
+                   "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                   "copy_reference_GBs": round(copy_gbs, 1),
+                   "traffic": traffic_per_elem and int(round(traffic_per_elem * elems))}
+    log(f"adam: {elems} elements in {ms:.4f} ms = {gbs:.0f} GB/s (device copy {copy_gbs:.0f} GB/s)")
+    return out
 
 
 def cpu_baseline(sc, cams, wl, args, counts, v0):

@@ -8,6 +8,7 @@ library binds to the HIP runtime torch has already loaded.
 """
 import ctypes
 import os
+import threading
 
 import torch
 
@@ -131,6 +132,19 @@ def _ptr(t, dtype=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+_PINNED = threading.local()
+
+
+def _host_count():
+    """A pinned int64 the library copies a count into (a copy into pageable
+    host memory goes through a staging buffer and waits much longer)."""
+    t = getattr(_PINNED, "t", None)
+    if t is None:
+        t = _PINNED.t = torch.empty(1, dtype=torch.int64, pin_memory=True)
+    t[0] = -1
+    return t
+
+
 def _sizes(xs):
     xs = [int(v) for v in xs]
     return (ctypes.c_int32 * max(len(xs), 1))(*xs)
@@ -170,13 +184,13 @@ def gsr_project_fwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors
 def gsr_intersect_count(p, C, N, W, H, means2d, radii, tiles_per_gauss, offsets, total_dev, ws, sync=True,
                         stream=None):
     """Returns M when ``sync`` (the call then waits for the stream), else None."""
-    host = ctypes.c_int64(0)
+    host = _host_count()
     ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
     _check(lib().gsr_intersect_count(
         ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(radii, I32, "radii"),
         _ptr(tiles_per_gauss, I32, "tiles_per_gauss"), _ptr(offsets, I64, "offsets"), _ptr(total_dev, I64, "total"),
-        ctypes.byref(host) if sync else None, _ptr(ws, None, "workspace"), ws_bytes, _stream(stream)))
-    return int(host.value) if sync else None
+        ctypes.c_void_p(host.data_ptr()) if sync else None, _ptr(ws, None, "workspace"), ws_bytes, _stream(stream)))
+    return int(host[0]) if sync else None
 
 
 def gsr_intersect_emit(p, C, N, W, H, means2d, radii, depths, offsets, M_capacity, keys, ids, stream=None):
@@ -201,13 +215,13 @@ def gsr_tile_ranges(M, keys, total_tiles, ranges, stream=None):
 def gsr_bin_prepare(p, C, N, W, H, means2d, radii, depths, conics, opacities, compensations, total_dev, ws_prep,
                     sync=True, stream=None):
     """Returns M when ``sync`` (the call then waits for the stream), else None."""
-    host = ctypes.c_int64(0)
+    host = _host_count()
     _check(lib().gsr_bin_prepare(
         ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(radii, I32, "radii"),
         _ptr(depths, F32, "depths"), _ptr(conics, F32, "conics"), _ptr(opacities, F32, "opacities"),
         _ptr(compensations, F32, "compensations"), _ptr(total_dev, I64, "total"),
-        ctypes.byref(host) if sync else None, *_ws(ws_prep), _stream(stream)))
-    return int(host.value) if sync else None
+        ctypes.c_void_p(host.data_ptr()) if sync else None, *_ws(ws_prep), _stream(stream)))
+    return int(host[0]) if sync else None
 
 
 def gsr_bin_finish(p, C, N, W, H, means2d, radii, depths, conics, opacities, compensations, M, ids, ranges, keys,
@@ -318,13 +332,13 @@ def gsr_densify_stats(C, N, W, H, radii, v_means2d, scale, grad_accum, count, st
 def gsr_densify_plan(N, grad_accum, count, scales, opacities, grad_threshold, scale_threshold, prune_opacity,
                      action, offsets, ws, sync=True, stream=None):
     """Returns the new count when ``sync`` (the call then waits)."""
-    host = ctypes.c_int64(-1)
+    host = _host_count()
     _check(lib().gsr_densify_plan(N, _ptr(grad_accum, F32, "grad_accum"), _ptr(count, I32, "count"),
                                   _ptr(scales, F32, "scales"), _ptr(opacities, F32, "opacities"),
                                   float(grad_threshold), float(scale_threshold), float(prune_opacity),
                                   _ptr(action, I32, "action"), _ptr(offsets, I64, "offsets"),
-                                  ctypes.byref(host) if sync else None, *_ws(ws), _stream(stream)))
-    return int(host.value) if sync else None
+                                  ctypes.c_void_p(host.data_ptr()) if sync else None, *_ws(ws), _stream(stream)))
+    return int(host[0]) if sync else None
 
 
 def gsr_densify_apply(N, action, offsets, quats, log_scales, split_normals, split_shrink, columns, stream=None):

@@ -212,11 +212,19 @@ __global__ void __launch_bounds__(kThreads) densify_plan_kernel(int N, const flo
 }
 
 // ---- ADC apply -------------------------------------------------------------------------
+// One thread per (Gaussian, float) of each column, the columns concatenated
+// block-wise (first_block), so reads are coalesced for every width and the
+// writes of a kept Gaussian land next to its neighbours'.
+constexpr int kApplyItems = 4;
+constexpr int kApplyPerBlock = kThreads * kApplyItems;
+
 struct ColumnTable {
     const float *src[GSR_DENSIFY_MAX_COLUMNS];
     float *dst[GSR_DENSIFY_MAX_COLUMNS];
     int32_t width[GSR_DENSIFY_MAX_COLUMNS];
     int32_t kind[GSR_DENSIFY_MAX_COLUMNS];
+    int64_t first_block[GSR_DENSIFY_MAX_COLUMNS + 1];
+    int32_t n;
 };
 
 // Rotation of a quaternion (w, x, y, z), normalised here; row-major R.
@@ -234,56 +242,59 @@ __device__ __forceinline__ void quat_rot(const float *q4, float R[9]) {
     R[8] = 1.0f - 2.0f * (x * x + y * y);
 }
 
-// One thread per (Gaussian, column): blockIdx.y is the column.
+// Component j of split child k: mu_j + (R diag(exp(ls)) eta_k)_j.
+__device__ __forceinline__ float split_mean(float mu, int n, int j, int k, const float *quats, const float *log_scales,
+                                            const float *normals) {
+    float R[9];
+    quat_rot(quats + 4 * (int64_t)n, R);
+    const float *ls = log_scales + 3 * (int64_t)n;
+    const float *eta = normals + 6 * (int64_t)n + 3 * k;
+    return mu + (R[3 * j] * (expf(ls[0]) * eta[0]) + R[3 * j + 1] * (expf(ls[1]) * eta[1]) +
+                 R[3 * j + 2] * (expf(ls[2]) * eta[2]));
+}
+
+template <bool kWide>
 __global__ void __launch_bounds__(kThreads) densify_apply_kernel(int N, const int32_t *__restrict__ action,
         const int64_t *__restrict__ offsets, const float *__restrict__ quats, const float *__restrict__ log_scales,
         const float *__restrict__ normals, float log_shrink, ColumnTable t) {
-    const int n = blockIdx.x * kThreads + threadIdx.x;
-    if (n >= N) return;
-    const int a = action[n];
-    if (a == GSR_PRUNE) return;
-    const int col = blockIdx.y;
+    int col = 0;
+#pragma unroll
+    for (int k = 1; k < GSR_DENSIFY_MAX_COLUMNS; k++)
+        if (k < t.n && (int64_t)blockIdx.x >= t.first_block[k]) col = k;
     const int w = t.width[col];
     const int kind = t.kind[col];
-    const float *src = t.src[col] + (int64_t)n * w;
-    float *dst = t.dst[col] + offsets[n] * w;
-    if (a == GSR_KEEP) {
-        for (int j = 0; j < w; j++) dst[j] = src[j];
-        return;
-    }
-    if (a == GSR_CLONE) {
-        for (int j = 0; j < w; j++) {
-            const float x = src[j];
-            dst[j] = x;
-            dst[w + j] = kind == GSR_COLUMN_STATE ? 0.0f : x;
-        }
-        return;
-    }
-    // split
-    if (kind == GSR_COLUMN_MEANS) {
-        float R[9];
-        quat_rot(quats + 4 * (int64_t)n, R);
-        float s[3];
+    const float *src = t.src[col];
+    float *dst = t.dst[col];
+    const int64_t total = (int64_t)N * w;
+    const int64_t base = ((int64_t)blockIdx.x - t.first_block[col]) * kApplyPerBlock + threadIdx.x;
 #pragma unroll
-        for (int j = 0; j < 3; j++) s[j] = expf(log_scales[3 * (int64_t)n + j]);
-#pragma unroll
-        for (int k = 0; k < 2; k++) {
-            const float *eta = normals + 6 * (int64_t)n + 3 * k;
-            const float e0 = s[0] * eta[0], e1 = s[1] * eta[1], e2 = s[2] * eta[2];
-#pragma unroll
-            for (int j = 0; j < 3; j++) dst[3 * k + j] = src[j] + (R[3 * j] * e0 + R[3 * j + 1] * e1 + R[3 * j + 2] * e2);
+    for (int i = 0; i < kApplyItems; i++) {
+        const int64_t e = base + (int64_t)i * kThreads;
+        if (e >= total) break;
+        int n, j;
+        if (kWide) {
+            n = (int)(e / w);
+            j = (int)(e - (int64_t)n * w);
+        } else {
+            n = (int)((uint32_t)e / (uint32_t)w);
+            j = (int)((uint32_t)e - (uint32_t)n * (uint32_t)w);
         }
-    } else if (kind == GSR_COLUMN_LOG_SCALES) {
-        for (int j = 0; j < w; j++) {
-            const float x = src[j] - log_shrink;
-            dst[j] = x;
-            dst[w + j] = x;
-        }
-    } else {
-        for (int j = 0; j < w; j++) {
-            const float x = kind == GSR_COLUMN_STATE ? 0.0f : src[j];
-            dst[j] = x;
-            dst[w + j] = x;
+        const int a = action[n];
+        if (a == GSR_PRUNE) continue;
+        const float x = src[e];
+        float *d = dst + offsets[n] * w + j;
+        if (a == GSR_KEEP) {
+            d[0] = x;
+        } else if (a == GSR_CLONE) {
+            d[0] = x;
+            d[w] = kind == GSR_COLUMN_STATE ? 0.0f : x;
+        } else if (kind == GSR_COLUMN_MEANS) {
+            d[0] = split_mean(x, n, j, 0, quats, log_scales, normals);
+            d[w] = split_mean(x, n, j, 1, quats, log_scales, normals);
+        } else {
+            const float y = kind == GSR_COLUMN_STATE ? 0.0f : (kind == GSR_COLUMN_LOG_SCALES ? x - log_shrink : x);
+            d[0] = y;
+            d[w] = y;
         }
     }
 }
@@ -420,14 +431,26 @@ int launch_densify_apply(int N, const int32_t *action, const int64_t *offsets, c
     if (N == 0 || n_columns == 0) return GSR_OK;
     ColumnTable t;
     memset(&t, 0, sizeof(t));
+    int64_t blocks = 0, widest = 0;
     for (int i = 0; i < n_columns; i++) {
         t.src[i] = columns[i].src;
         t.dst[i] = columns[i].dst;
         t.width[i] = columns[i].width;
         t.kind[i] = columns[i].kind;
+        t.first_block[i] = blocks;
+        const int64_t total = (int64_t)N * columns[i].width;
+        blocks += (total + kApplyPerBlock - 1) / kApplyPerBlock;
+        widest = total > widest ? total : widest;
     }
-    densify_apply_kernel<<<dim3(blocks_for(N), (unsigned)n_columns), kThreads, 0, s>>>(N, action, offsets, quats,
-                                                                                       log_scales, normals, log_shrink, t);
+    for (int i = n_columns; i <= GSR_DENSIFY_MAX_COLUMNS; i++) t.first_block[i] = blocks;
+    t.n = n_columns;
+    if (blocks > INT32_MAX) return fail(GSR_EINVAL, "gsr_densify_apply: too many elements");
+    if (widest > INT32_MAX)
+        densify_apply_kernel<true><<<(unsigned)blocks, kThreads, 0, s>>>(N, action, offsets, quats, log_scales,
+                                                                         normals, log_shrink, t);
+    else
+        densify_apply_kernel<false><<<(unsigned)blocks, kThreads, 0, s>>>(N, action, offsets, quats, log_scales,
+                                                                          normals, log_shrink, t);
     return launch_check("densify_apply");
 }
 

@@ -59,11 +59,23 @@ class TrainConfig:
     noise_t: float = 0.005
     opacity_reg: float = 0.01      # MCMC only
     scale_reg: float = 0.01        # MCMC only
+    capacity_factor: float = 1.5   # ADC: parameter rows allocated per starting Gaussian
     seed: int = 0
 
 
 def _dev(x, device):
     return torch.as_tensor(x, dtype=torch.float32).to(device).contiguous()
+
+
+class _ParamStore:
+    """Raw parameters and Adam moments of every tensor at a fixed row
+    capacity; the trainer works on views of the first N rows, so a
+    refinement writes into the other store instead of allocating."""
+
+    def __init__(self, rows, cap, device):
+        self.cap = cap
+        mk = lambda: {k: torch.zeros((cap,) + shape, device=device, dtype=torch.float32) for k, shape in rows.items()}
+        self.raw, self.m, self.v = mk(), mk(), mk()
 
 
 class GaussianTrainer:
@@ -96,29 +108,59 @@ class GaussianTrainer:
         self.gen = torch.Generator(device=self.device)
         self.gen.manual_seed(int(self.cfg.seed))
         self.l1_ws = torch.empty(L.workspace_bytes(L.GSR_OP_L1_LOSS, 0, 0, 0), device=self.device, dtype=torch.uint8)
-        self._reset_state()
+        self.M_cap = 0                 # intersection-list capacity learned from earlier steps
+        N = self.raw["means"].shape[0]
+        self._rows = {k: tuple(v.shape[1:]) for k, v in self.raw.items()}
+        grow = self.cfg.capacity_factor if self.cfg.strategy == "adc" else 1.0
+        first = _ParamStore(self._rows, max(int(N * grow), N, 1), self.device)
+        for k in PARAMS:
+            first.raw[k][:N].copy_(self.raw[k])
+        # ADC refinements write into the second store: allocate it (and the
+        # plan's scratch) now, so a refinement step allocates nothing
+        second = _ParamStore(self._rows, first.cap, self.device) if self.cfg.strategy == "adc" else None
+        self._stores, self._cur = [first, second], 0
+        self._act_scales = self._act_opac = None
+        self._scratch(first.cap)
+        self._bind(N)
 
     # ---- state -----------------------------------------------------------------------
     @property
     def N(self):
         return self.raw["means"].shape[0]
 
-    def _reset_state(self):
-        z = {k: torch.zeros_like(v) for k, v in self.raw.items()}
-        self.m = z
-        self.v = {k: torch.zeros_like(v) for k, v in self.raw.items()}
-        self._activate()
-        self._reset_stats()
-
-    def _activate(self):
-        self.scales = torch.empty_like(self.raw["log_scales"])
-        self.opacities = torch.empty_like(self.raw["logits"])
+    def _bind(self, N):
+        """Point the working tensors at the first N rows of the current
+        store, recompute the activated values and clear the statistics."""
+        st = self._stores[self._cur]
+        self.raw = {k: st.raw[k][:N] for k in PARAMS}
+        self.m = {k: st.m[k][:N] for k in PARAMS}
+        self.v = {k: st.v[k][:N] for k in PARAMS}
+        if self._act_scales is None or self._act_scales.shape[0] < N:
+            cap = st.cap
+            self._act_scales = torch.empty((cap, 3), device=self.device, dtype=torch.float32)
+            self._act_opac = torch.empty(cap, device=self.device, dtype=torch.float32)
+            self._accum = torch.zeros(cap, device=self.device, dtype=torch.float32)
+            self._count = torch.zeros(cap, device=self.device, dtype=torch.int32)
+        self.scales, self.opacities = self._act_scales[:N], self._act_opac[:N]
+        self.accum, self.count = self._accum[:N], self._count[:N]
         L.gsr_activate(self.raw["log_scales"], L.GSR_ACT_EXP, self.scales)
         L.gsr_activate(self.raw["logits"], L.GSR_ACT_SIGMOID, self.opacities)
+        self._reset_stats()
+
+    def _scratch(self, cap):
+        """Per-Gaussian scratch of the refinement and noise draws."""
+        d = self.device
+        self._normals = torch.empty((cap, 2, 3), device=d, dtype=torch.float32)
+        if self.cfg.strategy == "adc":
+            self._action = torch.empty(cap, device=d, dtype=torch.int32)
+            self._offsets = torch.empty(cap + 1, device=d, dtype=torch.int64)
+            self._plan_ws = torch.empty(max(L.workspace_bytes(L.GSR_OP_DENSIFY_PLAN, 0, cap, 0), 1), device=d,
+                                        dtype=torch.uint8)
+        self._scratch_cap = cap
 
     def _reset_stats(self):
-        self.accum = torch.zeros(self.N, device=self.device, dtype=torch.float32)
-        self.count = torch.zeros(self.N, device=self.device, dtype=torch.int32)
+        self.accum.zero_()
+        self.count.zero_()
 
     def activated_scene(self):
         return dict(means=self.raw["means"], quats=self.raw["quats"], scales=self.scales, opacities=self.opacities,
@@ -136,45 +178,64 @@ class GaussianTrainer:
         return [((step - 1) * k + j) % self.V for j in range(k)]
 
     # ---- one step ----------------------------------------------------------------------------
-    def render(self, views):
-        vm = self.viewmats[views].contiguous()
-        Ks = self.Ks[views].contiguous()
+    def _pick(self, t, views):
+        """Rows of a per-view tensor: a view of it when the views are
+        consecutive (no gather launch)."""
+        if views == list(range(views[0], views[0] + len(views))):
+            return t[views[0]:views[0] + len(views)]
+        return t[views].contiguous()
+
+    def render(self, views, check=True):
+        vm = self._pick(self.viewmats, views)
+        Ks = self._pick(self.Ks, views)
         C = len(views)
         W, H = [self.W[0]] * C, [self.H[0]] * C
         sc = self.activated_scene()
         proj = R.project(self.p, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], vm, Ks, W, H)
-        isect = R.intersect(self.p, proj, W, H)
+        isect = R.intersect(self.p, proj, W, H, capacity=self.M_cap or None)
         fwd = R.rasterize_forward(self.p, proj, sc["opacities"], isect, W, H)
-        if isect.check():
+        if check and isect.check():
             fwd = R.rasterize_forward(self.p, proj, sc["opacities"], isect, W, H)
         return vm, Ks, W, H, proj, isect, fwd
 
+    def _gradients(self, views, vm, Ks, W, H, proj, isect, fwd):
+        sc = self.activated_scene()
+        image = fwd["image"]
+        target = self._pick(self.targets, views).reshape(image.shape)
+        v_image = torch.empty_like(image)
+        loss = torch.empty(1, device=self.device, dtype=torch.float32)
+        L.gsr_l1_loss(image, target, 1.0 / image.numel(), v_image, loss, self.l1_ws)
+        g2 = R.rasterize_backward(self.p, proj, sc["opacities"], isect, W, H, fwd, v_image,
+                                  absgrad=self.cfg.absgrad and self.cfg.strategy == "adc")
+        g3 = R.project_backward(self.p, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], vm, Ks, W,
+                                H, proj, g2)
+        return loss, g2, g3
+
     def step(self):
         """One optimisation step; returns the step's L1 loss as a device
-        scalar (no host wait)."""
+        scalar.  The host does not wait inside the step: the intersection
+        count is resolved once the backward is queued, and only a list that
+        overflowed its buffer (rebuilt with the true count) sends the
+        forward and backward again, before anything is updated."""
         c = self.cfg
         self.step_no += 1
         t = self.step_no
         views = self.views_of(t)
         C = len(views)
-        vm, Ks, W, H, proj, isect, fwd = self.render(views)
-        image = fwd["image"]
-        target = self.targets[views].reshape(image.shape)
-        v_image = torch.empty_like(image)
-        loss = torch.empty(1, device=self.device, dtype=torch.float32)
-        L.gsr_l1_loss(image, target, 1.0 / image.numel(), v_image, loss, self.l1_ws)
-        sc = self.activated_scene()
-        g2 = R.rasterize_backward(self.p, proj, sc["opacities"], isect, W, H, fwd, v_image,
-                                  absgrad=c.absgrad and c.strategy == "adc")
-        g3 = R.project_backward(self.p, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], vm, Ks, W,
-                                H, proj, g2)
+        vm, Ks, W, H, proj, isect, fwd = self.render(views, check=False)
+        loss, g2, g3 = self._gradients(views, vm, Ks, W, H, proj, isect, fwd)
+        if isect.check():
+            fwd = R.rasterize_forward(self.p, proj, self.opacities, isect, W, H)
+            loss, g2, g3 = self._gradients(views, vm, Ks, W, H, proj, isect, fwd)
+        self.M_cap = max(self.M_cap, int(isect["M"] * 1.25) + 1024)
         self.last_grads = g3
         if c.strategy == "adc" and t < c.refine_stop:
             v2 = g2["v_means2d_abs"] if c.absgrad else g2["v_means2d"]
             L.gsr_densify_stats(C, self.N, W, H, proj["radii"], v2, float(C), self.accum, self.count)
         self._adam(t, g3)
         if c.strategy == "mcmc":
-            eta = torch.randn((self.N, 3), generator=self.gen, device=self.device, dtype=torch.float32)
+            eta = self._normals.view(-1, 3)[:self.N]
+            torch.randn(eta.shape, generator=self.gen, device=self.device, dtype=torch.float32, out=eta)
             L.gsr_mcmc_noise(self.N, self.raw["means"], self.raw["quats"], self.scales, self.opacities, eta,
                              c.noise_lr * self.lr_means(t), c.noise_k, c.noise_t)
         if c.strategy == "adc" and t < c.refine_stop:
@@ -210,29 +271,30 @@ class GaussianTrainer:
         new count), then clear the statistics."""
         c = self.cfg
         N = self.N
-        action = torch.empty(N, device=self.device, dtype=torch.int32)
-        offsets = torch.empty(N + 1, device=self.device, dtype=torch.int64)
-        ws = torch.empty(max(L.workspace_bytes(L.GSR_OP_DENSIFY_PLAN, 0, N, 0), 1), device=self.device,
-                         dtype=torch.uint8)
+        if self._scratch_cap < N:
+            self._scratch(self._stores[self._cur].cap)
+        action, offsets = self._action[:N], self._offsets[:N + 1]
         n_new = L.gsr_densify_plan(N, self.accum, self.count, self.scales, self.opacities, c.grad_threshold,
-                                   c.scale_threshold * self.extent, c.prune_opacity, action, offsets, ws)
+                                   c.scale_threshold * self.extent, c.prune_opacity, action, offsets, self._plan_ws)
         self.last_plan = (action, offsets)
-        normals = torch.randn((N, 2, 3), generator=self.gen, device=self.device, dtype=torch.float32)
+        normals = self._normals[:N]
+        torch.randn(normals.shape, generator=self.gen, device=self.device, dtype=torch.float32, out=normals)
         kinds = dict(means=L.GSR_COLUMN_MEANS, quats=L.GSR_COLUMN_COPY, log_scales=L.GSR_COLUMN_LOG_SCALES,
                      logits=L.GSR_COLUMN_COPY, sh=L.GSR_COLUMN_COPY)
-        new_raw = {k: torch.empty((n_new,) + tuple(v.shape[1:]), device=self.device, dtype=torch.float32)
-                   for k, v in self.raw.items()}
-        new_m = {k: torch.empty_like(v) for k, v in new_raw.items()}
-        new_v = {k: torch.empty_like(v) for k, v in new_raw.items()}
-        cols = [(self.raw[k], new_raw[k], kinds[k]) for k in PARAMS]
-        cols += [(self.m[k], new_m[k], L.GSR_COLUMN_STATE) for k in PARAMS]
-        cols += [(self.v[k], new_v[k], L.GSR_COLUMN_STATE) for k in PARAMS]
+        nxt = 1 - self._cur
+        st = self._stores[nxt]
+        if st is None or st.cap < n_new:
+            self._stores[nxt] = None
+            st = self._stores[nxt] = _ParamStore(self._rows, max(int(n_new * c.capacity_factor), n_new, 1),
+                                                 self.device)
+        cols = [(self.raw[k], st.raw[k][:n_new], kinds[k]) for k in PARAMS]
+        cols += [(self.m[k], st.m[k][:n_new], L.GSR_COLUMN_STATE) for k in PARAMS]
+        cols += [(self.v[k], st.v[k][:n_new], L.GSR_COLUMN_STATE) for k in PARAMS]
         if n_new > 0:
             L.gsr_densify_apply(N, action, offsets, self.raw["quats"], self.raw["log_scales"], normals,
                                 c.split_shrink, cols)
-        self.raw, self.m, self.v = new_raw, new_m, new_v
-        self._activate()
-        self._reset_stats()
+        self._cur = nxt
+        self._bind(n_new)
         return n_new
 
     def reset_opacities(self):
