@@ -227,7 +227,8 @@ class GaussianTrainer:
         if isect.check():
             fwd = R.rasterize_forward(self.p, proj, self.opacities, isect, W, H)
             loss, g2, g3 = self._gradients(views, vm, Ks, W, H, proj, isect, fwd)
-        self.M_cap = max(self.M_cap, int(isect["M"] * 1.25) + 1024)
+        self.last_M = isect["M"]
+        self.M_cap = max(self.M_cap, int(self.last_M * 1.25) + 1024)
         self.last_grads = g3
         if c.strategy == "adc" and t < c.refine_stop:
             v2 = g2["v_means2d_abs"] if c.absgrad else g2["v_means2d"]

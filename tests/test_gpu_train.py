@@ -482,3 +482,43 @@ def test_full_size_adam_and_l1_sampled():
     idx = g.choice(n, 20_000, replace=False)
     _, ref_v = T.l1_loss(a[idx], b[idx], scale)
     np.testing.assert_array_equal(np_(vi)[idx], ref_v.astype(np.float32))
+
+
+def test_store_growth_and_list_rebuild_paths():
+    """A refinement that outgrows the parameter stores (capacity factor 1)
+    reallocates them and gives the same Gaussians as a run with room to
+    spare; a step whose intersection buffer is too small rebuilds the lists
+    and sends the forward and backward again, giving the same update as a
+    step with the right capacity."""
+    from _gpu import np_
+    deg = 0
+    sc = scenes.scene_tiny(600, sh_degree=deg, seed=83, log_scale_mean=-2.0)
+    cams = scenes.cams_tiny(W=64, H=64, f=60.0, n_cams=2, seed=83)
+    raw = _raw_from_scene(sc)
+    g = np.random.default_rng(83)
+    targets = g.uniform(0, 1, (2, 64, 64, 3)).astype(np.float32)
+    kw = dict(strategy="adc", views_per_step=2, refine_start=0, refine_every=1, grad_threshold=2e-5,
+              scale_threshold=0.08, reset_every=10 ** 9)
+    tight = _trainer(raw, cams, targets, deg, capacity_factor=1.0, **kw)
+    roomy = _trainer(raw, cams, targets, deg, capacity_factor=3.0, **kw)
+    cap0 = tight._stores[0].cap
+    tight.step()
+    roomy.step()
+    torch.cuda.synchronize()
+    assert tight.N > cap0 and tight._stores[tight._cur].cap >= tight.N
+    assert tight.N == roomy.N
+    for k in tight.raw:
+        np.testing.assert_allclose(np_(tight.raw[k]), np_(roomy.raw[k]), rtol=0, atol=1e-6, err_msg=k)
+    # list rebuild: a capacity far below the count
+    a = _trainer(raw, cams, targets, deg, strategy="none", views_per_step=2)
+    b = _trainer(raw, cams, targets, deg, strategy="none", views_per_step=2)
+    a.step()
+    b.step()
+    b.M_cap = 1024
+    la = float(np_(a.step())[0])
+    lb = float(np_(b.step())[0])
+    torch.cuda.synchronize()
+    assert b.last_M > 1024, b.last_M
+    assert abs(la - lb) <= 1e-6 * la
+    for k in a.raw:
+        np.testing.assert_allclose(np_(b.raw[k]), np_(a.raw[k]), rtol=0, atol=1e-6, err_msg=k)
