@@ -184,7 +184,7 @@ def gsr_project_fwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors
 def gsr_intersect_count(p, C, N, W, H, means2d, radii, tiles_per_gauss, offsets, total_dev, ws, sync=True,
                         stream=None):
     """Returns M when ``sync`` (the call then waits for the stream), else None."""
-    host = _host_count()
+    host = _host_count() if sync else None
     ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
     _check(lib().gsr_intersect_count(
         ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(radii, I32, "radii"),
@@ -215,7 +215,7 @@ def gsr_tile_ranges(M, keys, total_tiles, ranges, stream=None):
 def gsr_bin_prepare(p, C, N, W, H, means2d, radii, depths, conics, opacities, compensations, total_dev, ws_prep,
                     sync=True, stream=None):
     """Returns M when ``sync`` (the call then waits for the stream), else None."""
-    host = _host_count()
+    host = _host_count() if sync else None
     _check(lib().gsr_bin_prepare(
         ctypes.byref(p), C, N, _sizes(W), _sizes(H), _ptr(means2d, F32, "means2d"), _ptr(radii, I32, "radii"),
         _ptr(depths, F32, "depths"), _ptr(conics, F32, "conics"), _ptr(opacities, F32, "opacities"),
@@ -332,7 +332,7 @@ def gsr_densify_stats(C, N, W, H, radii, v_means2d, scale, grad_accum, count, st
 def gsr_densify_plan(N, grad_accum, count, scales, opacities, grad_threshold, scale_threshold, prune_opacity,
                      action, offsets, ws, sync=True, stream=None):
     """Returns the new count when ``sync`` (the call then waits)."""
-    host = _host_count()
+    host = _host_count() if sync else None
     _check(lib().gsr_densify_plan(N, _ptr(grad_accum, F32, "grad_accum"), _ptr(count, I32, "count"),
                                   _ptr(scales, F32, "scales"), _ptr(opacities, F32, "opacities"),
                                   float(grad_threshold), float(scale_threshold), float(prune_opacity),

@@ -164,7 +164,8 @@ __global__ void __launch_bounds__(kScanThreads) block_sums_kernel(int64_t n_tota
 
 // One block turns the block sums into exclusive block offsets.
 __global__ void __launch_bounds__(kScanThreads) scan_sums_kernel(int64_t *__restrict__ sums, int64_t nb,
-                                                                 int64_t *__restrict__ total_out) {
+                                                                 int64_t *__restrict__ total_out,
+                                                                 int64_t *__restrict__ total_copy) {
     int64_t carry = 0;
     for (int64_t start = 0; start < nb; start += kScanThreads) {
         const int64_t i = start + threadIdx.x;
@@ -174,7 +175,10 @@ __global__ void __launch_bounds__(kScanThreads) scan_sums_kernel(int64_t *__rest
         if (i < nb) sums[i] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) *total_out = carry;
+    if (threadIdx.x == 0) {
+        *total_out = carry;
+        if (total_copy) *total_copy = carry;
+    }
 }
 
 // Per-element exclusive offsets.
@@ -811,10 +815,10 @@ size_t fin_bytes(int64_t M) {
 }
 
 int scan_counts(int64_t n, const int32_t *counts, int64_t *block_sums, int64_t *offsets, int64_t *total,
-                hipStream_t s) {
+                hipStream_t s, int64_t *total_copy = nullptr) {
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     block_sums_kernel<<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(n, counts, block_sums);
-    scan_sums_kernel<<<1, kScanThreads, 0, s>>>(block_sums, nb, total);
+    scan_sums_kernel<<<1, kScanThreads, 0, s>>>(block_sums, nb, total, total_copy);
     offsets_kernel<<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(n, counts, block_sums, offsets);
     return launch_check("scan");
 }
@@ -835,7 +839,7 @@ int launch_intersect_count(const gsr_params &p, const CamTable &cams, int N, con
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     int64_t *sums = (int64_t *)ws;
     count_kernel<<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(cams, N, n, means2d, radii, counts, sums);
-    scan_sums_kernel<<<1, kScanThreads, 0, s>>>(sums, nb, total_dev);
+    scan_sums_kernel<<<1, kScanThreads, 0, s>>>(sums, nb, total_dev, nullptr);
     offsets_kernel<<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(n, counts, sums, offsets);
     return launch_check("intersect_count");
 }
@@ -912,17 +916,19 @@ int launch_bin_prepare(const gsr_params &p, const CamTable &cams, int N, const f
                        const float *comps, void *ws_prep, int64_t *total_dev, hipStream_t s) {
     const int64_t n = (int64_t)cams.C * N;
     BinPrep b = carve_prep(ws_prep, n);
-    if (n == 0) return launch_fill_zero(b.total, sizeof(int64_t), s);
+    if (n == 0) {
+        int rc = launch_fill_zero(b.total, sizeof(int64_t), s);
+        if (rc == GSR_OK && total_dev) rc = launch_fill_zero(total_dev, sizeof(int64_t), s);
+        return rc;
+    }
     const unsigned nb = (unsigned)((n + 255) / 256);
     bin_keys_kernel<<<nb, 256, 0, s>>>(cams, N, n, means2d, radii, depths, cull_inputs(p, conics, opacities, comps),
                                        b.counts, b.dkeys, b.order);
     int rc = radix_sort<uint32_t>(n, 32, b.dkeys, b.order, b.dkeys_alt, b.order_alt, b.sort_ws, s);
     if (rc != GSR_OK) return rc;
     gather_counts_kernel<<<nb, 256, 0, s>>>(n, b.order, b.counts, b.counts_sorted);
-    rc = scan_counts(n, b.counts_sorted, b.block_sums, b.offsets_sorted, b.total, s);
-    if (rc == GSR_OK && total_dev)
-        rc = hip_check(hipMemcpyAsync(total_dev, b.total, sizeof(int64_t), hipMemcpyDeviceToDevice, s), "bin_prepare");
-    return rc;
+    // the scan writes the count into the workspace and, when asked, into total_dev (no copy node)
+    return scan_counts(n, b.counts_sorted, b.block_sums, b.offsets_sorted, b.total, s, total_dev);
 }
 
 int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const float *means2d,

@@ -25,6 +25,9 @@ namespace gsr {
 namespace {
 
 constexpr int kThreads = 256;
+// Fewer tiles than the 1024 SIMDs of an MI355X (256 CUs x 4): the RGB
+// backward then runs the four-waves-per-tile kernel.
+constexpr int kFewTiles = 1024;
 constexpr int kBatch = 256;
 
 // DPP controls (GFX9 encoding): quad_perm [1,0,3,2] and [2,3,0,1], rotate a
@@ -508,7 +511,14 @@ int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D
                     v_means2d_abs};
     const dim3 grid((unsigned)cams.total_tiles), block(kThreads);
     switch (channel_capacity(p, D)) {
-        case 3: raster_bwd_rgb_kernel<<<grid, dim3(kWave), 0, s>>>(a, cams); break;
+        case 3:
+            // one wave per tile leaves SIMDs idle when the views have fewer tiles than the GPU has
+            // SIMDs; then a block of four quad waves per tile finishes sooner
+            if (cams.total_tiles < kFewTiles)
+                raster_bwd_kernel<4><<<grid, block, 0, s>>>(a, cams);
+            else
+                raster_bwd_rgb_kernel<<<grid, dim3(kWave), 0, s>>>(a, cams);
+            break;
         case 4: raster_bwd_kernel<4><<<grid, block, 0, s>>>(a, cams); break;
         case 8: raster_bwd_kernel<8><<<grid, block, 0, s>>>(a, cams); break;
         case 16: raster_bwd_kernel<16><<<grid, block, 0, s>>>(a, cams); break;

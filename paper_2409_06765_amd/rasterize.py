@@ -134,7 +134,7 @@ class _Capacity:
 _CAPACITY = _Capacity()
 
 
-def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None, capacity=None):
+def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None, capacity=None, defer=False):
     """Per-tile depth-sorted lists.
 
     method="bin" (default): depth order of the projected Gaussians, then a
@@ -143,7 +143,9 @@ def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None, capacit
     host does not wait for the intersection count: the lists are built in a
     buffer of ``capacity`` entries (default: from earlier calls of the same
     shape; the first call of a shape waits for the count) and the count is
-    checked when M is read.  method="keys64": count (waits for it), emit
+    checked when M is read.  ``defer`` (with a capacity): no count check at
+    all; the count stays in ``total_dev`` for the caller to compare with the
+    capacity (what a captured graph needs).  method="keys64": count (waits for it), emit
     64-bit keys, stable radix sort, ranges of whole squares.  Without tile
     culling both give the same ids and ranges."""
     C, N = proj["radii"].shape
@@ -177,6 +179,9 @@ def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None, capacit
                             **build(cap))
         if M_known is not None:
             out._set_count(M_known)
+            return out
+        if defer:
+            out["capacity"] = cap
             return out
         s = stream if stream is not None else torch.cuda.current_stream(d)
         pinned = torch.empty(1, dtype=torch.int64, pin_memory=True)
@@ -275,15 +280,16 @@ def rasterize_forward(p, proj, opacities, isect, W, H, background=None, n_eval=F
     return out
 
 
-def grad_buffers(C, N, device, absgrad=False, D=3, shared=False, depth=False):
-    """Zeroed per-camera gradient buffers of the compositing backward, carved
-    from one allocation (one fill): v_colors is [N,D] for shared features,
-    else [C,N,D]; v_depths [C,N] when depth is rendered."""
+def grad_buffers(C, N, device, absgrad=False, D=3, shared=False, depth=False, zero=True):
+    """Per-camera gradient buffers of the compositing backward, carved from
+    one allocation (zeroed with one fill unless ``zero`` is False): v_colors
+    is [N,D] for shared features, else [C,N,D]; v_depths [C,N] when depth is
+    rendered."""
     n = C * N
     nf = (N if shared else n) * D
     sizes = dict(v_means2d=2 * n, v_conics=3 * n, v_colors=nf, v_opacities=n, v_depths=n if depth else 0,
                  v_means2d_abs=2 * n if absgrad else 0)
-    flat = torch.zeros(sum(sizes.values()), device=device, dtype=torch.float32)
+    flat = (torch.zeros if zero else torch.empty)(sum(sizes.values()), device=device, dtype=torch.float32)
     shapes = dict(v_means2d=(C, N, 2), v_conics=(C, N, 3), v_colors=(N, D) if shared else (C, N, D),
                   v_opacities=(C, N), v_depths=(C, N), v_means2d_abs=(C, N, 2))
     out, o = {}, 0
@@ -294,19 +300,23 @@ def grad_buffers(C, N, device, absgrad=False, D=3, shared=False, depth=False):
 
 
 def rasterize_backward(p, proj, opacities, isect, W, H, fwd, v_image, v_alpha=None, background=None,
-                       absgrad=False, grads=None, features=None, stream=None):
+                       absgrad=False, grads=None, features=None, stream=None, overwrite=False):
     """Gradients of the compositing.  ``grads`` (from ``grad_buffers``) are
-    added to; by default fresh zeroed buffers are used.  The records the
-    forward packed into its workspace are reused."""
+    added to; by default fresh zeroed buffers are used.  ``overwrite``: fresh
+    uninitialised buffers that the library zeroes itself (no torch fill).
+    The records the forward packed into its workspace are reused."""
     C, N = proj["radii"].shape
     d = proj["radii"].device
     pf, D, feat = _features(p, proj, features)
     depth = p.render_depth != L.GSR_DEPTH_NONE
-    g = grad_buffers(C, N, d, absgrad, D, bool(pf.colors_shared), depth) if grads is None else grads
+    if overwrite and grads is not None:
+        raise ValueError("overwrite makes its own buffers")
+    g = grad_buffers(C, N, d, absgrad, D, bool(pf.colors_shared), depth, zero=not overwrite) if grads is None \
+        else grads
     if absgrad and g["v_means2d_abs"] is None:
         raise ValueError("absgrad needs grad buffers made with absgrad=True")
     ws = fwd.get("ws")
-    flags = L.GSR_BWD_ACCUMULATE
+    flags = 0 if overwrite else L.GSR_BWD_ACCUMULATE
     if ws is None:
         ws = raster_workspace(C, N, d)
     else:

@@ -32,6 +32,16 @@ CASES = {
                     lambda: scenes.cams_tiny(W=97, H=61, f=70.0, n_cams=2, seed=2), 3, True, None),
     "tiny_sh1": (lambda: scenes.scene_tiny(200, sh_degree=1, seed=3, log_scale_mean=-2.0),
                  lambda: scenes.cams_tiny(W=48, H=48, f=40.0, seed=3), 1, False, None),
+    # views of 1,024 tiles or more take the one-wave-per-tile RGB backward, fewer the four-wave one
+    "ragged_3cams_bg_1065tiles": (lambda: scenes.scene_tiny(1500, seed=4, log_scale_mean=-2.6, spread=1.2),
+                                  lambda: scenes.cameras(
+                                      [scenes.look_at(e) for e in ([0, 0, 4.0], [3.0, 1.0, 2.5], [-1.0, 3.5, 1.0])],
+                                      [scenes.intrinsics(f, w, h) for f, w, h in ((400, 512, 512), (90, 100, 75),
+                                                                                  (25, 33, 17))],
+                                      [512, 100, 33], [512, 75, 17]),
+                                  -1, False, [[0.2, 0.3, 0.4], [0.0, 0.0, 0.0], [1.0, 0.5, 0.25]]),
+    "sh3_aa_1050tiles": (lambda: scenes.scene_tiny(1500, sh_degree=3, seed=5, log_scale_mean=-2.7),
+                         lambda: scenes.cams_tiny(W=400, H=330, f=300.0, n_cams=2, seed=5), 3, True, None),
     "uniform10k_256": (scenes.scene_uniform10k_256, scenes.cams_uniform10k_256, -1, False, None),
     "uniform100k_sh3_800": (scenes.scene_uniform100k_sh3_800, scenes.cams_uniform100k_sh3_800, 3, False, None),
 }
