@@ -430,11 +430,7 @@ int gsr_adam_step(int n_groups, const gsr_adam_group *groups, int32_t step, floa
         a.g[i] = g;
     }
     a.n_groups = n_groups;
-    a.beta1 = beta1;
-    a.beta2 = beta2;
-    a.eps = eps;
-    a.inv_bc1 = 1.0 / (1.0 - pow((double)beta1, (double)step));
-    a.inv_bc2 = 1.0 / (1.0 - pow((double)beta2, (double)step));
+    a.c = adam_consts(beta1, beta2, eps, step);
     return launch_adam(a, (hipStream_t)stream);
 }
 

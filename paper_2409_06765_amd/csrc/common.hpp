@@ -27,6 +27,31 @@ struct CamTable {
     CamInfo cam[GSR_MAX_CAMERAS];
 };
 
+// Adam constants of one step: betas, 1 - betas, reciprocal bias corrections.
+struct AdamConsts {
+    float beta1, beta2, omb1, omb2, inv_bc1, inv_bc2, eps;
+};
+
+// One Adam element: the chain
+// rule through the activation, with the L1 penalty reg on the activated value,
+// then the moments and the update; a = act(p) afterwards.  Contraction is off
+// here, so the rounding does not depend on the translation unit's flags.
+__device__ __forceinline__ void adam_update(const AdamConsts &c, int kind, float reg, float lr, float &p, float g,
+                                            float &m, float &v, float &a) {
+#pragma clang fp contract(off)
+    if (kind == GSR_ACT_EXP) {
+        g = (g + reg) * expf(p);
+    } else if (kind == GSR_ACT_SIGMOID) {
+        const float o = 1.0f / (1.0f + expf(-p));
+        g = (g + reg) * (o * (1.0f - o));
+    }
+    m = c.beta1 * m + c.omb1 * g;
+    v = c.beta2 * v + c.omb2 * (g * g);
+    const float mh = m * c.inv_bc1;
+    const float vh = v * c.inv_bc2;
+    p = p - lr * mh / (sqrtf(vh) + c.eps);
+    a = kind == GSR_ACT_EXP ? expf(p) : (kind == GSR_ACT_SIGMOID ? 1.0f / (1.0f + expf(-p)) : p);
+}
 // Status handling (abi.hip): records a message for gsr_last_error().
 int fail(int code, const char *fmt, ...);
 int hip_check(hipError_t e, const char *what);
@@ -96,6 +121,8 @@ int launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
 size_t scan_workspace_bytes(int64_t n);
 int launch_scan_i32(int64_t n, const int32_t *counts, int64_t *offsets, int64_t *total, void *ws, hipStream_t s);
 
+AdamConsts adam_consts(float beta1, float beta2, float eps, int32_t step);
+
 // Training-loop steps (train.hip).
 constexpr int kL1Blocks = 1024;
 int launch_l1_loss(int64_t n, const float *image, const float *target, float scale, float *v_image, float *loss,
@@ -103,8 +130,7 @@ int launch_l1_loss(int64_t n, const float *image, const float *target, float sca
 struct AdamLaunch {
     gsr_adam_group g[GSR_ADAM_MAX_GROUPS];
     int n_groups;
-    float beta1, beta2, eps;
-    double inv_bc1, inv_bc2;   // 1 / (1 - beta^t)
+    AdamConsts c;
 };
 int launch_adam(const AdamLaunch &a, hipStream_t s);
 int launch_activate(int64_t n, const float *raw, int kind, float *out, hipStream_t s);

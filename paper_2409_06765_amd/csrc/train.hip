@@ -94,7 +94,7 @@ struct AdamTable {
     AdamGroupK g[GSR_ADAM_MAX_GROUPS];
     int64_t first_block[GSR_ADAM_MAX_GROUPS + 1];
     int32_t n_groups;
-    float beta1, beta2, omb1, omb2, inv_bc1, inv_bc2, eps;
+    AdamConsts c;
 };
 
 __device__ __forceinline__ float activate(float x, int kind) {
@@ -103,21 +103,9 @@ __device__ __forceinline__ float activate(float x, int kind) {
     return x;
 }
 
-// One element: chain rule through the activation, moments, update.
 __device__ __forceinline__ void adam_one(const AdamTable &t, const AdamGroupK &G, float lr, float &p, float g,
                                          float &m, float &v, float &a) {
-    if (G.kind == GSR_ACT_EXP) {
-        g = (g + G.reg) * expf(p);
-    } else if (G.kind == GSR_ACT_SIGMOID) {
-        const float o = 1.0f / (1.0f + expf(-p));
-        g = (g + G.reg) * (o * (1.0f - o));
-    }
-    m = t.beta1 * m + t.omb1 * g;
-    v = t.beta2 * v + t.omb2 * (g * g);
-    const float mh = m * t.inv_bc1;
-    const float vh = v * t.inv_bc2;
-    p = p - lr * mh / (sqrtf(vh) + t.eps);
-    a = activate(p, G.kind);
+    adam_update(t.c, G.kind, G.reg, lr, p, g, m, v, a);
 }
 
 __global__ void __launch_bounds__(kThreads) adam_kernel(AdamTable t) {
@@ -351,6 +339,18 @@ int launch_l1_loss(int64_t n, const float *image, const float *target, float sca
     return launch_check("l1_loss");
 }
 
+AdamConsts adam_consts(float beta1, float beta2, float eps, int32_t step) {
+    AdamConsts c;
+    c.beta1 = beta1;
+    c.beta2 = beta2;
+    c.omb1 = (float)(1.0 - (double)beta1);
+    c.omb2 = (float)(1.0 - (double)beta2);
+    c.inv_bc1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
+    c.inv_bc2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
+    c.eps = eps;
+    return c;
+}
+
 int launch_adam(const AdamLaunch &a, hipStream_t s) {
     AdamTable t;
     memset(&t, 0, sizeof(t));
@@ -382,13 +382,7 @@ int launch_adam(const AdamLaunch &a, hipStream_t s) {
     if (ng == 0) return GSR_OK;
     if (blocks > INT32_MAX) return fail(GSR_EINVAL, "gsr_adam_step: too many elements");
     t.n_groups = ng;
-    t.beta1 = a.beta1;
-    t.beta2 = a.beta2;
-    t.omb1 = (float)(1.0 - (double)a.beta1);
-    t.omb2 = (float)(1.0 - (double)a.beta2);
-    t.inv_bc1 = (float)a.inv_bc1;
-    t.inv_bc2 = (float)a.inv_bc2;
-    t.eps = a.eps;
+    t.c = a.c;
     adam_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(t);
     return launch_check("adam_step");
 }
