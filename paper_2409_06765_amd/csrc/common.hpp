@@ -115,6 +115,8 @@ int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D
                          hipStream_t s);
 
 int launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
+// Zeroes up to 8 buffers in one launch (NULL or empty entries are skipped).
+int launch_fill_zero_multi(int n, void *const *ptrs, const size_t *bytes, hipStream_t s);
 
 // Exclusive prefix sums of int32 counts into int64 offsets, total to *total
 // (device); ws of scan_workspace_bytes(n).

@@ -162,6 +162,27 @@ __global__ void __launch_bounds__(kScanThreads) block_sums_kernel(int64_t n_tota
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
+// The counts gathered into depth order (counts_sorted[i] = counts[order[i]])
+// and their per-block sums, in one pass.
+__global__ void __launch_bounds__(kScanThreads) gather_block_sums_kernel(int64_t n_total,
+        const int32_t *__restrict__ order, const int32_t *__restrict__ counts, int32_t *__restrict__ counts_sorted,
+        int64_t *__restrict__ block_sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t local = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        if (base + i < n_total) {
+            const int32_t g = order[base + i];
+            const int32_t c = (g >= 0 && g < n_total) ? counts[g] : 0;
+            counts_sorted[base + i] = c;
+            local += c;
+        }
+    }
+    int64_t total;
+    block_exclusive_scan<int64_t>(local, total);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
 // One block turns the block sums into exclusive block offsets.
 __global__ void __launch_bounds__(kScanThreads) scan_sums_kernel(int64_t *__restrict__ sums, int64_t nb,
                                                                  int64_t *__restrict__ total_out,
@@ -426,6 +447,21 @@ __global__ void fill_zero_kernel(uint32_t *__restrict__ p, int64_t n_words) {
         p[i] = 0u;
 }
 
+// Up to kFillMax buffers zeroed by one launch: blockIdx.y picks the buffer.
+constexpr int kFillMax = 8;
+struct FillList {
+    uint32_t *p[kFillMax];
+    int64_t words[kFillMax];
+};
+
+__global__ void fill_zero_multi_kernel(FillList f) {
+    const int b = blockIdx.y;
+    uint32_t *p = f.p[b];
+    const int64_t n = f.words[b];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 template <typename K>
 __device__ __forceinline__ int32_t tile_of(K key) { return (int32_t)(sizeof(K) == 8 ? (uint64_t)key >> 32 : key); }
 
@@ -452,16 +488,6 @@ __global__ void __launch_bounds__(256) bin_keys_kernel(CamTable cams, int N, int
     counts[g] = k;
     dkeys[g] = k > 0 ? __float_as_uint(depths[g]) : 0xFFFFFFFFu;
     dvals[g] = (int32_t)g;
-}
-
-// Counts in depth order.
-__global__ void __launch_bounds__(256) gather_counts_kernel(int64_t n_total, const int32_t *__restrict__ order,
-                                                            const int32_t *__restrict__ counts,
-                                                            int32_t *__restrict__ counts_sorted) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_total) return;
-    const int32_t g = order[s];
-    counts_sorted[s] = (g >= 0 && g < n_total) ? counts[g] : 0;
 }
 
 // 64-bit keys of the sorted lists (only when a caller asks for them).
@@ -867,6 +893,26 @@ int launch_fill_zero(void *ptr, size_t bytes, hipStream_t s) {
     return launch_check("fill_zero");
 }
 
+int launch_fill_zero_multi(int n, void *const *ptrs, const size_t *bytes, hipStream_t s) {
+    FillList f;
+    int k = 0;
+    int64_t most = 0;
+    for (int i = 0; i < n; i++) {
+        const int64_t words = (int64_t)(bytes[i] / 4);
+        if (!ptrs[i] || words == 0) continue;
+        if (k == kFillMax) return fail(GSR_EINVAL, "fill_zero_multi: more than %d buffers", kFillMax);
+        f.p[k] = (uint32_t *)ptrs[i];
+        f.words[k] = words;
+        most = words > most ? words : most;
+        k++;
+    }
+    if (k == 0) return GSR_OK;
+    int64_t blocks = (most + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    fill_zero_multi_kernel<<<dim3((unsigned)blocks, (unsigned)k), dim3(256), 0, s>>>(f);
+    return launch_check("fill_zero");
+}
+
 int launch_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_t *ranges, hipStream_t s) {
     int rc = launch_fill_zero(ranges, (size_t)total_tiles * 2 * sizeof(int32_t), s);
     if (rc != GSR_OK || M == 0) return rc;
@@ -926,9 +972,15 @@ int launch_bin_prepare(const gsr_params &p, const CamTable &cams, int N, const f
                                        b.counts, b.dkeys, b.order);
     int rc = radix_sort<uint32_t>(n, 32, b.dkeys, b.order, b.dkeys_alt, b.order_alt, b.sort_ws, s);
     if (rc != GSR_OK) return rc;
-    gather_counts_kernel<<<nb, 256, 0, s>>>(n, b.order, b.counts, b.counts_sorted);
-    // the scan writes the count into the workspace and, when asked, into total_dev (no copy node)
-    return scan_counts(n, b.counts_sorted, b.block_sums, b.offsets_sorted, b.total, s, total_dev);
+    // gather + block sums, then the scan of the block sums, which writes the count into the workspace
+    // and, when asked, into total_dev (no copy node), then the offsets
+    const int64_t nbs = (n + kScanTile - 1) / kScanTile;
+    gather_block_sums_kernel<<<dim3((unsigned)nbs), dim3(kScanThreads), 0, s>>>(n, b.order, b.counts,
+                                                                             b.counts_sorted, b.block_sums);
+    scan_sums_kernel<<<1, kScanThreads, 0, s>>>(b.block_sums, nbs, b.total, total_dev);
+    offsets_kernel<<<dim3((unsigned)nbs), dim3(kScanThreads), 0, s>>>(n, b.counts_sorted, b.block_sums,
+                                                                    b.offsets_sorted);
+    return launch_check("bin_prepare");
 }
 
 int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const float *means2d,

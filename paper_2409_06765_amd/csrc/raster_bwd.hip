@@ -489,13 +489,12 @@ int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D
     const size_t CN = (size_t)cams.C * (size_t)N;
     const size_t FN = p.colors_shared ? (size_t)N : CN;
     int rc = GSR_OK;
-    if (!(flags & GSR_BWD_ACCUMULATE)) {
-        rc = launch_fill_zero(v_means2d, CN * 2 * sizeof(float), s);
-        if (rc == GSR_OK) rc = launch_fill_zero(v_conics, CN * 3 * sizeof(float), s);
-        if (rc == GSR_OK && D > 0) rc = launch_fill_zero(v_colors, FN * (size_t)D * sizeof(float), s);
-        if (rc == GSR_OK && p.render_depth != GSR_DEPTH_NONE) rc = launch_fill_zero(v_depths, CN * sizeof(float), s);
-        if (rc == GSR_OK) rc = launch_fill_zero(v_opac, CN * sizeof(float), s);
-        if (rc == GSR_OK && v_means2d_abs) rc = launch_fill_zero(v_means2d_abs, CN * 2 * sizeof(float), s);
+    if (!(flags & GSR_BWD_ACCUMULATE)) {   // one launch zeroes every output
+        void *const ptrs[6] = {v_means2d, v_conics, D > 0 ? v_colors : nullptr,
+                               p.render_depth != GSR_DEPTH_NONE ? v_depths : nullptr, v_opac, v_means2d_abs};
+        const size_t bytes[6] = {CN * 2 * sizeof(float), CN * 3 * sizeof(float), FN * (size_t)D * sizeof(float),
+                                 CN * sizeof(float), CN * sizeof(float), CN * 2 * sizeof(float)};
+        rc = launch_fill_zero_multi(6, ptrs, bytes, s);
     }
     if (rc != GSR_OK || cams.total_tiles == 0 || N == 0) return rc;
     const int cn = cams.C * N;

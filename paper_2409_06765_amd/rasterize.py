@@ -218,9 +218,17 @@ def intersect(p, proj, W, H, method="bin", want_keys=False, stream=None, capacit
                 order=tile_order(ranges, total_tiles, stream))
 
 
+# Below this many tiles every compositing block of a launch runs at once on
+# the 256 CUs, so the dispatch order changes nothing and is not computed.
+ORDER_MIN_TILES = 1024
+
+
 def tile_order(ranges, total_tiles, stream=None):
     """Launch order of the compositing blocks: tiles by list length, longest
-    first (gsr_tile_order)."""
+    first (gsr_tile_order); None (tile id order) for fewer than
+    ORDER_MIN_TILES tiles."""
+    if total_tiles < ORDER_MIN_TILES:
+        return None
     d = ranges.device
     order = torch.empty(max(total_tiles, 1), device=d, dtype=torch.int32)
     ws = torch.empty(max(L.workspace_bytes(L.GSR_OP_TILE_ORDER, 0, 0, 0), 1), device=d, dtype=torch.uint8)
