@@ -301,3 +301,16 @@ class GaussianTrainer:
     def reset_opacities(self):
         L.gsr_opacity_reset(self.N, self.raw["logits"], self.m["logits"], self.v["logits"], self.opacities,
                             self.cfg.reset_value)
+
+
+def densify_stats_from_meta(meta, accum, count, absgrad=False, views_in_loss=None):
+    """ADC statistics from the ``meta`` of ``rasterize.rasterization`` after
+    the backward pass (the way a training loop built on the autograd function
+    gathers them): adds to ``accum`` [N] and ``count`` [N] (int32) through
+    gsr_densify_stats.  ``views_in_loss``: the number of views the loss
+    averaged over (default: the views rendered)."""
+    radii = meta["radii"]
+    C, N = radii.shape
+    v2 = meta["means2d_absgrad"] if absgrad else meta["means2d_grad"]
+    scale = float(C if views_in_loss is None else views_in_loss)
+    L.gsr_densify_stats(C, N, meta["width"], meta["height"], radii, v2, scale, accum, count)

@@ -522,3 +522,37 @@ def test_store_growth_and_list_rebuild_paths():
     assert abs(la - lb) <= 1e-6 * la
     for k in a.raw:
         np.testing.assert_allclose(np_(b.raw[k]), np_(a.raw[k]), rtol=0, atol=1e-6, err_msg=k)
+
+
+@pytest.mark.parametrize("absgrad", [False, True])
+def test_densify_stats_from_rasterization_meta(absgrad):
+    """The autograd entry point's meta feeds the ADC statistics: after
+    rasterization() and backward, densify_stats_from_meta against the
+    oracle's statistics of the oracle's backward."""
+    from _gpu import np_, to_dev
+    from paper_2409_06765_amd.rasterize import rasterization
+    from paper_2409_06765_amd.train import densify_stats_from_meta
+    sc = scenes.scene_tiny(700, sh_degree=1, seed=121, log_scale_mean=-2.3)
+    cams = scenes.cams_tiny(W=72, H=56, f=55.0, n_cams=2, seed=121)
+    t = {k: to_dev(sc[k]).requires_grad_(True) for k in ("means", "quats", "scales", "opacities", "sh")}
+    img, alpha, meta = rasterization(t["means"], t["quats"], t["scales"], t["opacities"], t["sh"],
+                                     to_dev(cams["viewmats"]), to_dev(cams["Ks"]), 72, 56, sh_degree=1,
+                                     absgrad=absgrad, tile_cull=0)
+    P = OracleParams(sh_degree=1)
+    proj, isect, ras = O32.forward(P, sc, cams)
+    g = np.random.default_rng(122)
+    v_image = g.normal(size=ras["image"].shape).astype(np.float32)
+    v_image[ras["flags"] != 0] = 0
+    (img.reshape(-1, 3) * to_dev(v_image)).sum().backward()
+    N = sc["means"].shape[0]
+    accum = torch.zeros(N, device="cuda:0")
+    count = torch.zeros(N, device="cuda:0", dtype=torch.int32)
+    densify_stats_from_meta(meta, accum, count, absgrad=absgrad)
+    torch.cuda.synchronize()
+    o2 = O32.rasterize_bwd(P, proj, sc["opacities"], isect["ranges"], isect["ids"], cams["W"], cams["H"],
+                           ras["final_T"], ras["last_ids"], v_image, absgrad=absgrad)
+    v2 = o2["v_means2d_abs"] if absgrad else o2["v_means2d"]
+    acc_ref, cnt_ref = T.densify_stats(proj["radii"], v2, cams["W"], cams["H"], 2.0, np.zeros(N),
+                                       np.zeros(N, np.int64))
+    np.testing.assert_array_equal(np_(count), cnt_ref)
+    np.testing.assert_allclose(np_(accum), acc_ref, rtol=2e-3, atol=2e-3 * acc_ref.max())
