@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clusters1m_sh3_1080p", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-tiles", type=int, default=96, help="tiles of view 0 the oracle rasterizes")
+    ap.add_argument("--cpu-sample-tiles", type=int, default=1800, help="tiles of view 0 the oracle rasterizes")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--graph", action="store_true",
                     help="also time the step captured as one HIP graph; value and ms_per_step then come from it")
