@@ -210,6 +210,19 @@ def main():
         t = measured_traffic()
         roofline["traffic"] = None if t is None else int(t)
 
+    # device memory: the resident scene, and the peak one forward + backward view adds on top of what
+    # is allocated before it (projected arrays, lists, records, images, gradients, workspaces)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    step(views[0])
+    torch.cuda.synchronize()
+    memory = {"scene_bytes": int(sum(v.numel() * v.element_size() for v in d.values())),
+              "per_view_peak_bytes": int(torch.cuda.max_memory_allocated() - base),
+              "device_bytes": int(torch.cuda.get_device_properties(0).total_memory)}
+    log(f"memory: scene {memory['scene_bytes'] / 2**20:.0f} MiB, one fwd+bwd view adds "
+        f"{memory['per_view_peak_bytes'] / 2**20:.0f} MiB at its peak")
+
     graph = None
     if args.graph:
         from paper_2409_06765_amd.graph import CapturedStep
@@ -252,6 +265,7 @@ def main():
         "evals_per_s_raster": (E_fwd + E_bwd) / (1e-3 * args.steps * (stage_ms["rasterize_fwd"] + stage_ms["rasterize_bwd"])),
         "raster_fwd_tflops": round(fwd_tflops, 3),
         "roofline": roofline,
+        "memory": memory,
     }
     if graph is not None:
         out["graph"] = graph
