@@ -295,9 +295,13 @@ def serving(d, p, args):
     serve_one_at_a_time(be, probe)                           # warm up: every size (capacity, allocations)
     torch.cuda.synchronize()
     _, cap = serve_one_at_a_time(be, probe)
+    Server(be, max_batch=16, mem_budget=24 << 30).run(probe)   # warm up the batched shapes too
+    torch.cuda.synchronize()
+    _, bcap = Server(be, max_batch=16, mem_budget=24 << 30).run(probe)
     rate = args.serve_load * cap.views_per_s
     trace = scenes.serving_trace(rate, n_requests=args.serve_requests, seed=0)
-    log(f"serving: one-view capacity {cap.views_per_s:.1f} views/s, trace at {rate:.1f} req/s")
+    log(f"serving: capacity {cap.views_per_s:.1f} views/s one at a time, {bcap.views_per_s:.1f} batched; "
+        f"trace at {rate:.1f} req/s")
     _, single = serve_one_at_a_time(be, trace)
     torch.cuda.synchronize()
     _, batched = Server(be, max_batch=16, mem_budget=24 << 30).run(trace)
@@ -307,6 +311,7 @@ def serving(d, p, args):
                        "done": st.n_done, "rejected": st.n_rejected}
     return {"requests": args.serve_requests, "arrival_rate_per_s": round(rate, 2),
             "one_view_capacity_views_per_s": round(cap.views_per_s, 2),
+            "batched_capacity_views_per_s": round(bcap.views_per_s, 2),
             "batched": pick(batched), "one_view_per_launch": pick(single)}
 
 
