@@ -672,6 +672,104 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__
     }
 }
 
+// Small inputs (up to kSmallSort pairs of 32-bit keys): every pass in one block, the pairs in
+// LDS between passes, the same stable ranking as radix_scatter_kernel (wave-striped positions,
+// per-wave digit counts, prefix over waves then digits), so one launch replaces three per pass.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallItems = 16;
+constexpr int kSmallSort = kSmallThreads * kSmallItems;
+constexpr int kSmallWaves = kSmallThreads / kWave;
+
+__global__ void __launch_bounds__(kSmallThreads) radix_sort_small_kernel(uint32_t *__restrict__ keys,
+                                                                         int32_t *__restrict__ ids, int M,
+                                                                         int key_bits) {
+    __shared__ uint32_t s_keys[kSmallSort];
+    __shared__ int32_t s_ids[kSmallSort];
+    __shared__ int32_t s_wcnt[kSmallWaves][kBins];
+    __shared__ int32_t s_dstart[kBins];
+    __shared__ int32_t s_wtot[kBins / kWave];
+    const int t = threadIdx.x, lane = __lane_id(), w = t / kWave;
+    const uint64_t lt = lanemask_lt();
+    uint32_t key[kSmallItems];
+    int32_t val[kSmallItems];
+    // position of item i of this lane: w * 1024 + i * 64 + lane (wave-striped)
+#pragma unroll
+    for (int i = 0; i < kSmallItems; i++) {
+        const int idx = w * (kWave * kSmallItems) + i * kWave + lane;
+        key[i] = idx < M ? keys[idx] : 0u;
+        val[i] = idx < M ? ids[idx] : 0;
+    }
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        const int bits = min(8, key_bits - shift);
+        const uint32_t mask = (1u << bits) - 1u;
+        for (int k = t; k < kSmallWaves * kBins; k += kSmallThreads) (&s_wcnt[0][0])[k] = 0;
+        __syncthreads();
+        int32_t rank[kSmallItems];
+#pragma unroll
+        for (int i = 0; i < kSmallItems; i++) {
+            const int idx = w * (kWave * kSmallItems) + i * kWave + lane;
+            const bool valid = idx < M;
+            const uint32_t d = (key[i] >> shift) & mask;
+            const uint64_t peers = match_digit(d, bits, __ballot(valid));
+            rank[i] = -1;
+            if (valid) {
+                const int32_t before = s_wcnt[w][d];
+                rank[i] = before + (int32_t)__popcll(peers & lt);
+                if ((peers & lt) == 0) s_wcnt[w][d] = before + (int32_t)__popcll(peers);
+            }
+        }
+        __syncthreads();
+        // per digit: exclusive prefix over the waves, then over the digits (threads 0..255)
+        int32_t run = 0;
+        if (t < kBins) {
+#pragma unroll
+            for (int k = 0; k < kSmallWaves; k++) {
+                const int32_t c = s_wcnt[k][t];
+                s_wcnt[k][t] = run;
+                run += c;
+            }
+        }
+        const int32_t inc = wave_inclusive_scan<int32_t>(run);
+        if (lane == kWave - 1 && w < kBins / kWave) s_wtot[w] = inc;
+        __syncthreads();
+        if (t < kBins) {
+            int32_t before = 0;
+            for (int k = 0; k < w; k++) before += s_wtot[k];
+            s_dstart[t] = before + inc - run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSmallItems; i++) {
+            if (rank[i] >= 0) {
+                const uint32_t d = (key[i] >> shift) & mask;
+                const int pos = s_dstart[d] + s_wcnt[w][d] + rank[i];
+                if (pos >= 0 && pos < kSmallSort) {   // always true; keeps a ranking bug from writing out of bounds
+                    s_keys[pos] = key[i];
+                    s_ids[pos] = val[i];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSmallItems; i++) {
+            const int idx = w * (kWave * kSmallItems) + i * kWave + lane;
+            if (idx < M) {
+                key[i] = s_keys[idx];
+                val[i] = s_ids[idx];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < kSmallItems; i++) {
+        const int idx = w * (kWave * kSmallItems) + i * kWave + lane;
+        if (idx < M) {
+            keys[idx] = key[i];
+            ids[idx] = val[i];
+        }
+    }
+}
+
 // ---- dispatch order of the compositing blocks ---------------------------------
 // Tiles sorted by list length, longest first, so that the blocks that run
 // longest start first and the short ones fill in behind them (longest
@@ -755,6 +853,12 @@ template <typename K>
 int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int32_t *ids_alt, void *ws,
                hipStream_t s, const int64_t *count_dev = nullptr) {
     if (M <= 1) return GSR_OK;
+    if constexpr (sizeof(K) == 4) {
+        if (!count_dev && M <= kSmallSort) {   // the whole sort in one block
+            radix_sort_small_kernel<<<1, kSmallThreads, 0, s>>>(keys, ids, (int)M, key_bits);
+            return launch_check("radix_sort");
+        }
+    }
     int passes = (key_bits + 7) / 8;
     if (passes % 2) passes++;
     const int width = (key_bits + passes - 1) / passes;
