@@ -96,14 +96,16 @@ __device__ __forceinline__ float add_xor32(float v) {
     return a + b;
 }
 
-// Sum over all 64 lanes, result in every lane.
-__device__ __forceinline__ float wave_total(float v) {
+// Sum over the lane's 16-lane row, result in every lane of the row.
+__device__ __forceinline__ float row_total(float v) {
     v += dpp<kDppXor1>(v);
     v += dpp<kDppXor2>(v);
     v += dpp<kDppRor4>(v);
-    v += dpp<kDppRor8>(v);
-    return add_xor32(add_xor16(v));
+    return v + dpp<kDppRor8>(v);
 }
+
+// Sum over all 64 lanes, result in every lane.
+__device__ __forceinline__ float wave_total(float v) { return add_xor32(add_xor16(row_total(v))); }
 
 // Where the gradient of composited channel d of Gaussian g (id n within its
 // camera) goes: a feature channel of v_colors, or v_depths for the depth
@@ -331,7 +333,8 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
     const int start = a.ranges[2 * tile];
     const float amin = a.p.alpha_min, amax = a.p.alpha_max;
 
-    // per pixel (one per quad): T restored back to front, SV = S . v_C, v_alpha final_T, v_C, last index
+    // per pixel (one per quad): T restored back to front, R = v_alpha final_T - S . v_C with S the colour
+    // composited behind the current entry (background included), v_C, last index
     float T[4], SV[4], vATf[4], vC[4][3];
     int last[4], qlast[4];
     int stop = -1;
@@ -359,7 +362,7 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
         stop = max(stop, qlast[q]);
     }
     const bool want_abs = a.v_means2d_abs != nullptr;
-    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
     const int nslots = want_abs ? 11 : 9;
     float *dst_base = nullptr;
     int dst_mul = 0;
@@ -370,7 +373,8 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
     else if (lane == 8) { dst_base = a.v_opac; dst_mul = 1; }
     else if (lane < 11 && want_abs) { dst_base = a.v_means2d_abs + (lane - 9); dst_mul = 2; }
     const int cam_base = c * a.N;
-    const float lscale = (lane == 2 || lane == 4) ? 0.5f : 1.0f;
+    // lanes 2, 4: dL/da, dL/dc are half the dx^2, dy^2 moments; lanes 9, 10: |dL/dmu'| carries log2(e)
+    const float lscale = (lane == 2 || lane == 4) ? 0.5f : (lane == 9 || lane == 10) ? 1.0f / kLog2e : 1.0f;
 
     for (int hi = stop + 1; hi > start; hi -= kTileBatch) {
         const int base = max(start, hi - kTileBatch);
@@ -445,7 +449,9 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
                 }
             }
             if (!any) continue;
-            // transposing butterfly: 8 values -> lane holds the total of value (lane & 7)
+            // Transposing butterfly: lanes 0-7 of each 16-lane row end with the row's total of value
+            // (lane & 7); lanes 8-15 then take the row totals of the v_sigma sum (lane 8) and of the two
+            // |dL/dmu'| sums (lanes 9, 10), and one pair of cross-row exchanges finishes all of them.
             const float w0 = bfly<kDppXor1>(acc[0], acc[1], b0);
             const float w1 = bfly<kDppXor1>(acc[2], acc[3], b0);
             const float w2 = bfly<kDppXor1>(acc[4], acc[5], b0);
@@ -454,17 +460,18 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
             const float x1 = bfly<kDppXor2>(w2, w3, b1);
             float y = bfly<kDppRor4>(x0, x1, b2);
             y += dpp<kDppRor8>(y);
+            float side = row_total(acc_o);
+            if (want_abs) {
+                const float zx = row_total(acc_ax), zy = row_total(acc_ay);
+                side = b0 ? zx : b1 ? zy : side;          // lane 9 (1001b), lane 10 (1010b), lane 8
+            }
+            y = b3 ? side : y;
             y = add_xor32(add_xor16(y));
             // lanes 0, 1: dL/dmu' = (2 A' S_dx + B' S_dy, B' S_dx + 2 C' S_dy) / log2(e) with the scaled
-            // conic (A', B', C'); lanes 2, 4: dL/da, dL/dc are half the dx^2, dy^2 moments
+            // conic (A', B', C'); lane 8: dL/do = -(sum of v_sigma) / o
             const float yo = dpp<kDppXor1>(y);            // lane 0 <-> lane 1
             const float mean = fmaf(2.0f * (lane == 0 ? con.x : con.z), y, con.y * yo) * (1.0f / kLog2e);
-            const float zo = wave_total(acc_o) * -__builtin_amdgcn_rcpf(xyo.z);
-            float val = lane < 2 ? mean : lane < 8 ? y * lscale : zo;
-            if (want_abs) {
-                const float zx = wave_total(acc_ax), zy = wave_total(acc_ay);
-                val = lane == 9 ? zx * (1.0f / kLog2e) : lane == 10 ? zy * (1.0f / kLog2e) : val;
-            }
+            const float val = lane < 2 ? mean : y * (lane == 8 ? -__builtin_amdgcn_rcpf(xyo.z) : lscale);
             if (lane < nslots && dst_base) {
                 const int g = __builtin_amdgcn_readfirstlane(s_id[e]);   // uniform: scalar index arithmetic
                 int n = g - cam_base;
