@@ -10,6 +10,11 @@ integer (radius, tile rectangle, depth key bits, skip/stop) is taken.
 ``Oracle(np.float64)`` is the same source in double precision, used by the
 pins (invariants, closed forms, finite differences).
 
+Rasterization outputs carry per-pixel ``flags`` (FLAG_* bits: a decision
+within the error bound of an accurate float32 implementation, so that one may
+take it the other way) and ``margin`` (the smallest |ln(value / threshold)|
+over the pixel's skip, clamp and stop decisions).
+
 Images are packed per camera: pixel (c, y, x) lives at ``pix_off[c] + y*W_c + x``
 of a flat [P, 3] / [P] array; for cameras of equal size that is [C, H, W, ...].
 """
@@ -59,12 +64,16 @@ _LIBS = {}
 
 
 def _load(kind):
+    """The oracle build of one precision; GSORACLE_VARIANT=asan loads the
+    sanitizer build (make -C oracle asan) instead."""
     if kind in _LIBS:
         return _LIBS[kind]
-    path = os.path.join(_HERE, f"libgsoracle_{kind}.so")
+    variant = os.environ.get("GSORACLE_VARIANT", "")
+    suffix = "_asan" if variant == "asan" else ""
+    path = os.path.join(_HERE, f"libgsoracle_{kind}{suffix}.so")
     src = os.path.join(_HERE, "gsoracle.c")
     if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
-        build()
+        subprocess.check_call(["make", "-s", "-C", _HERE] + (["asan"] if suffix else []))
     lib = ctypes.CDLL(path)
     lib.orc_intersect_count.restype = ctypes.c_int64
     _LIBS[kind] = lib
@@ -94,6 +103,23 @@ def _nch(proj):
 def _ints(xs):
     a = np.ascontiguousarray(np.asarray(xs, dtype=np.int32))
     return a
+
+
+# Per-pixel decision flags of the compositing (one bit per kind of decision
+# that lies within an accurate float32 implementation's error bound).
+FLAG_SIGN, FLAG_SKIP, FLAG_CLAMP, FLAG_STOP = 1, 2, 4, 8
+
+
+def set_threads(n):
+    """Threads of the oracle's loops over tiles (both precisions; 1 by
+    default).  For timing on every host core and for whole-frame tests;
+    forward results do not depend on it."""
+    for kind in ("f32", "f64"):
+        _load(kind).orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(_load("f32").orc_get_threads())
 
 
 def camera_layout(W, H, tile=16):
@@ -227,7 +253,7 @@ class Oracle:
         return dict(image=np.zeros((npix, D), dt), alpha=np.zeros(npix, dt), final_T=np.zeros(npix, dt),
                     n_eval=np.zeros(npix, np.int32), n_comp=np.zeros(npix, np.int32),
                     flags=np.zeros(npix, np.uint8),
-                    trace=np.zeros(npix, np.uint32))
+                    trace=np.zeros(npix, np.uint32), margin=np.full(npix, np.inf))
 
     def rasterize_fwd(self, P, proj, opacities, ranges, ids, W, H, background=None, tile_mask=None):
         _p = _Keep()
@@ -244,7 +270,7 @@ class Oracle:
                                    _p(np.ascontiguousarray(ranges, np.int32)), _p(np.ascontiguousarray(ids, np.int32)),
                                    _p(tm), _p(out["image"]), _p(out["alpha"]), _p(out["final_T"]),
                                    _p(out["last_ids"]), _p(out["n_eval"]), _p(out["n_comp"]), _p(out["flags"]),
-                                   _p(out["trace"]))
+                                   _p(out["trace"]), _p(out["margin"]))
         return out
 
     def rasterize_bwd(self, P, proj, opacities, ranges, ids, W, H, final_T, last_ids, v_image,
@@ -379,7 +405,7 @@ class Oracle:
                                       tiles.shape[0], _p(tiles), int(bool(untiled)), _p(out["image"]),
                                       _p(out["alpha"]), _p(out["final_T"]), _p(out["last_gid"]),
                                       _p(out["last_pos"]), _p(out["n_eval"]), _p(out["n_comp"]),
-                                      _p(out["flags"]), _p(out["trace"]), _p(out["list_len"]))
+                                      _p(out["flags"]), _p(out["trace"]), _p(out["list_len"]), _p(out["margin"]))
         return out
 
     def render_tiles_bwd(self, P, proj, opacities, tiles, W, H, v_image, v_alpha=None, background=None,

@@ -111,7 +111,11 @@ def project(P, means, quats, scales, sh_or_colors, viewmat, K, W, H):
 def render(P, proj, opacities, W, H, background=None, mode="untiled"):
     """Plain definition; vectorised over pixels, looping over Gaussians in
     (depth, id) order.  Returns image [H,W,3], final_T [H,W], last [H,W]
-    (Gaussian id of the last composited one, -1) and n_comp [H,W]."""
+    (Gaussian id of the last composited one, -1), n_comp [H,W] and margin
+    [H,W]: the smallest |ln(value / threshold)| over the pixel's decisions
+    against alpha_min and alpha_max (o exp(-sigma) of every entry it
+    evaluates) and against T_min (the transmittance after every entry that
+    passes the skip test, composited or stopping)."""
     ys, xs = np.mgrid[0:H, 0:W]
     px, py = xs + 0.5, ys + 0.5
     tx_of, ty_of = xs // P.tile, ys // P.tile
@@ -120,6 +124,7 @@ def render(P, proj, opacities, W, H, background=None, mode="untiled"):
     done = np.zeros((H, W), bool)
     last = np.full((H, W), -1, np.int64)
     n_comp = np.zeros((H, W), np.int64)
+    margin = np.full((H, W), np.inf)
     valid = np.nonzero(proj["valid"])[0]
     order = valid[np.lexsort((valid, proj["depth"][valid]))]
     for n in order:
@@ -128,12 +133,18 @@ def render(P, proj, opacities, W, H, background=None, mode="untiled"):
         dy = proj["mean2d"][n, 1] - py
         sigma = 0.5 * (a * dx * dx + c * dy * dy) + b * dx * dy
         o = opacities[n] * proj["comp"][n]
-        alpha = np.minimum(P.alpha_max, o * np.exp(-sigma))
-        use = (~done) & (sigma >= 0) & (alpha >= P.alpha_min)
+        araw = o * np.exp(-sigma)
+        alpha = np.minimum(P.alpha_max, araw)
+        seen = ~done
         if mode == "rect":
             x0, x1, y0, y1 = proj["rect"][n]
-            use &= (tx_of >= x0) & (tx_of < x1) & (ty_of >= y0) & (ty_of < y1)
+            seen &= (tx_of >= x0) & (tx_of < x1) & (ty_of >= y0) & (ty_of < y1)
+        use = seen & (sigma >= 0) & (alpha >= P.alpha_min)
         Tn = T * (1.0 - alpha)
+        with np.errstate(divide="ignore"):
+            m = np.minimum(np.abs(np.log(araw / P.alpha_min)), np.abs(np.log(araw / P.alpha_max)))
+            margin = np.where(seen & (sigma >= 0) & (araw > 0), np.minimum(margin, m), margin)
+            margin = np.where(use, np.minimum(margin, np.abs(np.log(Tn / P.T_min))), margin)
         stop = use & (Tn < P.T_min)
         done |= stop
         comp = use & ~stop
@@ -143,4 +154,4 @@ def render(P, proj, opacities, W, H, background=None, mode="untiled"):
         n_comp += comp
     if background is not None:
         Cimg += T[..., None] * np.asarray(background, np.float64)
-    return dict(image=Cimg, final_T=T, last=last, n_comp=n_comp)
+    return dict(image=Cimg, final_T=T, last=last, n_comp=n_comp, margin=margin)

@@ -27,6 +27,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef REAL
 #define REAL double
@@ -473,10 +476,17 @@ typedef struct {
     int D;
 } scene2d_t;
 
-/* Per-pixel decision flags: set when a skip/stop/sign decision lies so close
- * to its threshold that an implementation with a different (but accurate)
- * exp or evaluation order could take it the other way. */
-#define FLAG_AMBIG 1u
+/* Per-pixel decision flags (reading R24 of the design notes: several
+ * results are correct).  A pixel is flagged when one of its decisions -- the
+ * sign test on sigma, the alpha < alpha_min skip, the alpha_max clamp, the
+ * T < T_min stop -- lies within the error bound of an accurate float32
+ * implementation of the compositing, so that such an implementation may
+ * decide it the other way; everything downstream of that decision may then
+ * differ.  One bit per kind of decision. */
+#define FLAG_SIGN  1u
+#define FLAG_SKIP  2u
+#define FLAG_CLAMP 4u
+#define FLAG_STOP  8u
 
 typedef struct {
     REAL color[ORC_MAX_D], T;
@@ -485,6 +495,8 @@ typedef struct {
     int n_comp;          /* entries composited                                     */
     uint32_t trace;      /* hash of the composited positions and their clamp states */
     uint32_t flags;
+    double margin;       /* smallest |ln(value / threshold)| over the skip, clamp and
+                            stop decisions (the double-precision values)            */
 } pix_out_t;
 
 static REAL gauss_opacity(const scene2d_t *S, int g)
@@ -494,12 +506,43 @@ static REAL gauss_opacity(const scene2d_t *S, int g)
     return o;
 }
 
-/* alpha = o exp(-sigma) with sigma known to within tol: an accurate
- * evaluation lies within a factor exp(+-tol) of v, so a decision against thr
- * is open when thr is inside that interval. */
+/* v lies within a factor exp(+-tol) of thr. */
 static int within_factor(double v, double thr, double tol)
 {
     return v >= thr * exp(-tol) && v <= thr * exp(tol);
+}
+
+/* sigma = 1/2 (a dx^2 + c dy^2) + b dx dy (Rasterization of Gaussians) of the
+ * offsets dx, dy as REAL values, evaluated in double precision: for float32
+ * inputs the products a dx, b dx, c dy are exact and the result is within a
+ * few double ulps of the magnitude of its terms, so even where the terms
+ * cancel (a needle-like Gaussian seen along its long axis) the value is the
+ * definition's to far better than float32 resolution.  The REAL result is
+ * that value rounded once.  *smag: the sum of the terms' magnitudes. */
+static double sigma_of(double a, double b, double c, double dx, double dy, double *smag)
+{
+    *smag = 0.5 * (fabs(a * dx * dx) + fabs(c * dy * dy)) + fabs(b * dx * dy);
+    return 0.5 * ((a * dx) * dx + (c * dy) * dy) + (b * dx) * dy;
+}
+
+/* The accuracy bound the flags assume of the implementation being compared:
+ * its sigma is within
+ *     es = u (8 S + |b u_c dy|)
+ * of the definition, u the unit roundoff, S = 1/2 (a u_c^2 + |c - b^2/a| dy^2)
+ * with u_c = dx + (b/a) dy: a few ulps of sigma written as a sum of two
+ * squares (which does not cancel) plus one ulp of b/a carried through dy.
+ * That is what evaluating the completed square achieves; the naive sum of
+ * the three terms does not meet it where they cancel, and its decisions are
+ * then genuinely open (an error of many ulps of the largest term).  Its
+ * alpha = o exp(-sigma) is then within a factor exp(+-(es + 4u)), which also
+ * covers the rounding of the exponential and of the product with o. */
+static double sigma_budget(double a, double b, double c, double dx, double dy, double u)
+{
+    if (!(a > 0.0)) return u * 16.0 * (0.5 * (fabs(a * dx * dx) + fabs(c * dy * dy)) + fabs(b * dx * dy));
+    const double uc = dx + (b / a) * dy;
+    const double q = (a * c - b * b) / a;
+    const double S = 0.5 * (a * uc * uc + fabs(q) * dy * dy);
+    return u * (8.0 * S + fabs(b * uc * dy));
 }
 
 static void composite_pixel(const scene2d_t *S, const int32_t *list, int len, REAL px, REAL py,
@@ -511,33 +554,47 @@ static void composite_pixel(const scene2d_t *S, const int32_t *list, int len, RE
     for (int ch = 0; ch < D; ch++) Cacc[ch] = K(0);
     int last = -1, n_eval = 0, n_comp = 0;
     uint32_t trace = 0, flags = 0;
-    double eT = 0.0;               /* relative error budget of T (for flags) */
-    const double ulp = (sizeof(REAL) == 4) ? 5.96e-8 : 1.11e-16;
+    /* Tt: the transmittance from the double-precision alphas of the entries
+     * composited so far; eT: a bound on |ln T - ln Tt| for an implementation
+     * within the budget above (each factor 1 - alpha is known to alpha /
+     * (1 - alpha) times alpha's relative error, plus the two roundings of
+     * 1 - alpha and of the product). */
+    double Tt = 1.0, eT = 0.0, margin = INFINITY;
+    const double u = (sizeof(REAL) == 4) ? 0x1p-24 : 0x1p-53;
+    const double amin = (double)(REAL)P->alpha_min, amax = (double)(REAL)P->alpha_max, tmin = (double)(REAL)P->T_min;
     for (int k = 0; k < len; k++) {
         int g = list[k];
         n_eval++;
         REAL dx = S->means2d[2 * g] - px, dy = S->means2d[2 * g + 1] - py;
-        REAL a = S->conics[3 * g], b = S->conics[3 * g + 1], c = S->conics[3 * g + 2];
-        REAL sigma = K(0.5) * ((a * dx) * dx + (c * dy) * dy) + (b * dx) * dy;
-        double smag = 0.5 * (fabs((double)a * dx * dx) + fabs((double)c * dy * dy)) + fabs((double)b * dx * dy);
-        double tol_s = 16.0 * ulp * smag + 1e-30;
-        if (fabs((double)sigma) <= tol_s) flags |= FLAG_AMBIG;
+        double a = S->conics[3 * g], b = S->conics[3 * g + 1], c = S->conics[3 * g + 2];
+        double smag;
+        double sd = sigma_of(a, b, c, dx, dy, &smag);
+        REAL sigma = (REAL)sd;
+        /* the double evaluation's own error (a few double ulps of smag) joins the budget */
+        double es = sigma_budget(a, b, c, dx, dy, u) + 4.0 * 0x1p-53 * smag;
+        if (fabs(sd) < es) flags |= FLAG_SIGN;
         if (sigma < K(0)) continue;
         REAL o = gauss_opacity(S, g);
         REAL araw = o * r_exp(-sigma);
         REAL alpha = r_min((REAL)P->alpha_max, araw);
-        double tol_a = tol_s + 8.0 * ulp;   /* relative error budget of alpha */
-        if (within_factor(araw, P->alpha_min, tol_a)) flags |= FLAG_AMBIG;
-        if (within_factor(araw, P->alpha_max, tol_a)) flags |= FLAG_AMBIG;
+        double at = (double)o * exp(-sd);    /* alpha from the double sigma, before the clamp */
+        double ea = es + 4.0 * u;            /* its relative error bound in an implementation */
+        if (within_factor(at, amin, ea)) flags |= FLAG_SKIP;
+        if (within_factor(at, amax, ea)) flags |= FLAG_CLAMP;
+        if (at > 0.0) margin = fmin(margin, fmin(fabs(log(at / amin)), fabs(log(at / amax))));
         if (alpha < (REAL)P->alpha_min) continue;
+        double alt = at < amax ? at : amax;
+        double Ttn = Tt * (1.0 - alt);
+        double eTn = eT + (at < amax ? ea * alt / (1.0 - alt) : 0.0) + 2.0 * u;
+        if (within_factor(Ttn, tmin, eTn)) flags |= FLAG_STOP;
+        margin = fmin(margin, fabs(log(Ttn / tmin)));
         REAL Tn = T * (K(1) - alpha);
-        double eTn = eT + (alpha < (REAL)P->alpha_max ? tol_a * alpha / (1.0 - alpha) : 0.0) + 2.0 * ulp;
-        if (fabs((double)Tn - P->T_min) <= eTn * P->T_min) flags |= FLAG_AMBIG;
         if (Tn < (REAL)P->T_min) break;
         REAL w = alpha * T;
         const REAL *col = S->colors + (size_t)D * g;
         for (int ch = 0; ch < D; ch++) Cacc[ch] += col[ch] * w;
         T = Tn;
+        Tt = Ttn;
         eT = eTn;
         last = k;
         n_comp++;
@@ -545,7 +602,7 @@ static void composite_pixel(const scene2d_t *S, const int32_t *list, int len, RE
     }
     for (int ch = 0; ch < D; ch++) out->color[ch] = Cacc[ch] + T * (bg ? bg[ch] : K(0));
     out->T = T; out->last = last; out->n_eval = n_eval; out->n_comp = n_comp;
-    out->trace = trace; out->flags = flags;
+    out->trace = trace; out->flags = flags; out->margin = margin;
 }
 
 /* Reverse recursion (Depth Compositing Gradients) for one pixel.  Gradient
@@ -603,7 +660,8 @@ static void composite_pixel_bwd(const scene2d_t *S, const int32_t *list, int las
         int g = list[k];
         REAL dx = S->means2d[2 * g] - px, dy = S->means2d[2 * g + 1] - py;
         REAL a = S->conics[3 * g], b = S->conics[3 * g + 1], c = S->conics[3 * g + 2];
-        REAL sigma = K(0.5) * ((a * dx) * dx + (c * dy) * dy) + (b * dx) * dy;
+        double smag;
+        REAL sigma = (REAL)sigma_of(a, b, c, dx, dy, &smag);    /* as in the forward */
         if (sigma < K(0)) continue;
         REAL o = gauss_opacity(S, g);
         REAL e = r_exp(-sigma);
@@ -662,47 +720,99 @@ static void camera_offsets(const orc_params *P, int C, const int *W, const int *
     pix_off[C] = po; tile_off[C] = to;
 }
 
+/* Threads of the loops over tiles (OpenMP; 1 by default).  Used only to time
+ * the oracle on every host core and to run whole frames in the tests: the
+ * tiles are independent, so the forward results do not depend on it; the
+ * backward's per-thread double sums are added in thread order at the end. */
+static int g_threads = 1;
+void orc_set_threads(int n) { g_threads = n > 0 ? n : 1; }
+int orc_get_threads(void) { return g_threads; }
+
+/* (camera, tile x, tile y) of global tile t */
+static void tile_coords(const orc_params *P, int C, const int *W, const int64_t *tile_off, int64_t t,
+                        int *c, int *tx, int *ty)
+{
+    int cc = 0;
+    while (cc + 1 < C && t >= tile_off[cc + 1]) cc++;
+    int TX = (W[cc] + P->tile - 1) / P->tile;
+    int64_t lt = t - tile_off[cc];
+    *c = cc; *ty = (int)(lt / TX); *tx = (int)(lt % TX);
+}
+
+static void store_pixel(const pix_out_t *po, int D, int64_t p, REAL *image, REAL *alpha, REAL *final_T,
+                        int32_t *n_eval, int32_t *n_comp, uint8_t *flags, uint32_t *trace, double *margin)
+{
+    for (int ch = 0; ch < D; ch++) image[(size_t)D * p + ch] = po->color[ch];
+    alpha[p] = K(1) - po->T;
+    final_T[p] = po->T;
+    if (n_eval) n_eval[p] = po->n_eval;
+    if (n_comp) n_comp[p] = po->n_comp;
+    if (flags) flags[p] = (uint8_t)po->flags;
+    if (trace) trace[p] = po->trace;
+    if (margin) margin[p] = po->margin;
+}
+
 /* Render every pixel of every (selected) tile from the sorted list.
  * Images are packed per camera: pixel (c, y, x) at pix_off[c] + y W_c + x.
- * last_ids holds the global position in the sorted list (-1: none). */
+ * last_ids holds the global position in the sorted list (-1: none).
+ * margin (nullable): per pixel the smallest |ln(value / threshold)| over its
+ * skip, clamp and stop decisions. */
 int orc_rasterize_fwd(const orc_params *P, int C, int N, int D, const int *W, const int *H,
                       const REAL *means2d, const REAL *conics, const REAL *colors, const REAL *opacities,
                       const REAL *comps, const REAL *background, const int32_t *ranges, const int32_t *ids,
                       const uint8_t *tile_mask, REAL *image, REAL *alpha, REAL *final_T, int32_t *last_ids,
-                      int32_t *n_eval, int32_t *n_comp, uint8_t *flags, uint32_t *trace)
+                      int32_t *n_eval, int32_t *n_comp, uint8_t *flags, uint32_t *trace, double *margin)
 {
     if (D < 1 || D > ORC_MAX_D) return -1;
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     camera_offsets(P, C, W, H, pix_off, tile_off);
     scene2d_t S = {P, N, means2d, conics, colors, opacities, comps, D};
-    int ts = P->tile;
-    for (int c = 0; c < C; c++) {
-        int TX = (W[c] + ts - 1) / ts, TY = (H[c] + ts - 1) / ts;
+    const int ts = P->tile;
+    const int64_t nt = tile_off[C];
+#pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
+    for (int64_t t = 0; t < nt; t++) {
+        if (tile_mask && !tile_mask[t]) continue;
+        int c, tx, ty;
+        tile_coords(P, C, W, tile_off, t, &c, &tx, &ty);
         const REAL *bg = background ? background + (size_t)D * c : NULL;
-        for (int ty = 0; ty < TY; ty++)
-            for (int tx = 0; tx < TX; tx++) {
-                int64_t t = tile_off[c] + (int64_t)ty * TX + tx;
-                if (tile_mask && !tile_mask[t]) continue;
-                int start = ranges[2 * t], end = ranges[2 * t + 1];
-                for (int y = ty * ts; y < (ty + 1) * ts && y < H[c]; y++)
-                    for (int x = tx * ts; x < (tx + 1) * ts && x < W[c]; x++) {
-                        pix_out_t po;
-                        composite_pixel(&S, ids + start, end - start, (REAL)x + K(0.5), (REAL)y + K(0.5), bg, &po);
-                        int64_t p = pix_off[c] + (int64_t)y * W[c] + x;
-                        for (int ch = 0; ch < D; ch++) image[(size_t)D * p + ch] = po.color[ch];
-                        alpha[p] = K(1) - po.T;
-                        final_T[p] = po.T;
-                        last_ids[p] = po.last >= 0 ? start + po.last : -1;
-                        if (n_eval) n_eval[p] = po.n_eval;
-                        if (n_comp) n_comp[p] = po.n_comp;
-                        if (flags) flags[p] = (uint8_t)po.flags;
-                        if (trace) trace[p] = po.trace;
-                    }
+        int start = ranges[2 * t], end = ranges[2 * t + 1];
+        for (int y = ty * ts; y < (ty + 1) * ts && y < H[c]; y++)
+            for (int x = tx * ts; x < (tx + 1) * ts && x < W[c]; x++) {
+                pix_out_t po;
+                composite_pixel(&S, ids + start, end - start, (REAL)x + K(0.5), (REAL)y + K(0.5), bg, &po);
+                int64_t p = pix_off[c] + (int64_t)y * W[c] + x;
+                store_pixel(&po, D, p, image, alpha, final_T, n_eval, n_comp, flags, trace, margin);
+                last_ids[p] = po.last >= 0 ? start + po.last : -1;
             }
     }
     free(pix_off); free(tile_off);
     return 0;
+}
+
+/* One gradient accumulator per thread, added into the first in thread order. */
+static grad2d_t *grads_per_thread(size_t CN, int D, int want_abs, int want_absgrad, int n)
+{
+    grad2d_t *G = (grad2d_t *)malloc(sizeof(grad2d_t) * (size_t)n);
+    for (int i = 0; i < n; i++) grad2d_alloc(&G[i], CN, D, want_abs, want_absgrad);
+    return G;
+}
+
+static void grads_merge(grad2d_t *G, int n, size_t CN)
+{
+    for (int i = 1; i < n; i++) {
+        const int D = G[0].D;
+        for (size_t j = 0; j < 2 * CN; j++) G[0].v_means2d[j] += G[i].v_means2d[j];
+        for (size_t j = 0; j < 3 * CN; j++) G[0].v_conics[j] += G[i].v_conics[j];
+        for (size_t j = 0; j < (size_t)D * CN; j++) G[0].v_colors[j] += G[i].v_colors[j];
+        for (size_t j = 0; j < CN; j++) G[0].v_opac[j] += G[i].v_opac[j];
+        if (G[0].abs)
+            for (size_t j = 0; j < (size_t)G[0].nslot * CN; j++) G[0].abs[j] += G[i].abs[j];
+        if (G[0].v_means2d_abs)
+            for (size_t j = 0; j < 2 * CN; j++) G[0].v_means2d_abs[j] += G[i].v_means2d_abs[j];
+        free(G[i].v_means2d); free(G[i].v_conics); free(G[i].v_colors); free(G[i].v_opac); free(G[i].abs);
+        free(G[i].v_means2d_abs);
+    }
 }
 
 int orc_rasterize_bwd(const orc_params *P, int C, int N, int D, const int *W, const int *H,
@@ -718,29 +828,37 @@ int orc_rasterize_bwd(const orc_params *P, int C, int N, int D, const int *W, co
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     camera_offsets(P, C, W, H, pix_off, tile_off);
     size_t CN = (size_t)C * N;
-    grad2d_t G;
-    grad2d_alloc(&G, CN, D, abs_sums != NULL, v_means2d_abs != NULL);
+    const int nth = g_threads;
+    grad2d_t *G = grads_per_thread(CN, D, abs_sums != NULL, v_means2d_abs != NULL, nth);
     scene2d_t S = {P, N, means2d, conics, colors, opacities, comps, D};
-    int ts = P->tile;
-    for (int c = 0; c < C; c++) {
-        int TX = (W[c] + ts - 1) / ts, TY = (H[c] + ts - 1) / ts;
-        const REAL *bg = background ? background + (size_t)D * c : NULL;
-        for (int ty = 0; ty < TY; ty++)
-            for (int tx = 0; tx < TX; tx++) {
-                int64_t t = tile_off[c] + (int64_t)ty * TX + tx;
-                if (tile_mask && !tile_mask[t]) continue;
-                int start = ranges[2 * t];
-                for (int y = ty * ts; y < (ty + 1) * ts && y < H[c]; y++)
-                    for (int x = tx * ts; x < (tx + 1) * ts && x < W[c]; x++) {
-                        int64_t p = pix_off[c] + (int64_t)y * W[c] + x;
-                        if (last_ids[p] < 0) continue;
-                        composite_pixel_bwd(&S, ids + start, last_ids[p] - start, (REAL)x + K(0.5), (REAL)y + K(0.5),
-                                            bg, final_T[p], v_image + (size_t)D * p, v_alpha ? v_alpha[p] : K(0), &G);
-                    }
-            }
+    const int ts = P->tile;
+    const int64_t nt = tile_off[C];
+#pragma omp parallel num_threads(nth)
+    {
+#ifdef _OPENMP
+        grad2d_t *Gt = &G[omp_get_thread_num()];
+#else
+        grad2d_t *Gt = &G[0];
+#endif
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t t = 0; t < nt; t++) {
+            if (tile_mask && !tile_mask[t]) continue;
+            int c, tx, ty;
+            tile_coords(P, C, W, tile_off, t, &c, &tx, &ty);
+            const REAL *bg = background ? background + (size_t)D * c : NULL;
+            int start = ranges[2 * t];
+            for (int y = ty * ts; y < (ty + 1) * ts && y < H[c]; y++)
+                for (int x = tx * ts; x < (tx + 1) * ts && x < W[c]; x++) {
+                    int64_t p = pix_off[c] + (int64_t)y * W[c] + x;
+                    if (last_ids[p] < 0) continue;
+                    composite_pixel_bwd(&S, ids + start, last_ids[p] - start, (REAL)x + K(0.5), (REAL)y + K(0.5),
+                                        bg, final_T[p], v_image + (size_t)D * p, v_alpha ? v_alpha[p] : K(0), Gt);
+                }
+        }
     }
-    grad2d_store(&G, CN, v_means2d, v_conics, v_colors, v_opacities, abs_sums, v_means2d_abs);
-    free(pix_off); free(tile_off);
+    grads_merge(G, nth, CN);
+    grad2d_store(&G[0], CN, v_means2d, v_conics, v_colors, v_opacities, abs_sums, v_means2d_abs);
+    free(G); free(pix_off); free(tile_off);
     return 0;
 }
 
@@ -800,38 +918,38 @@ int orc_render_tiles_fwd(const orc_params *P, int C, int N, int D, const int *W,
                          const REAL *comps, const int32_t *radii, const REAL *depths, const REAL *background,
                          int ntiles, const int32_t *tiles, int untiled,
                          REAL *image, REAL *alpha, REAL *final_T, int32_t *last_gid, int32_t *last_pos,
-                         int32_t *n_eval, int32_t *n_comp, uint8_t *flags, uint32_t *trace, int32_t *list_len)
+                         int32_t *n_eval, int32_t *n_comp, uint8_t *flags, uint32_t *trace, int32_t *list_len,
+                         double *margin)
 {
     if (D < 1 || D > ORC_MAX_D) return -1;
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     camera_offsets(P, C, W, H, pix_off, tile_off);
-    int32_t *list = (int32_t *)malloc(sizeof(int32_t) * (N > 0 ? N : 1));
-    did_t *tmp = (did_t *)malloc(sizeof(did_t) * (N > 0 ? N : 1));
     scene2d_t S = {P, N, means2d, conics, colors, opacities, comps, D};
-    int ts = P->tile;
-    for (int i = 0; i < ntiles; i++) {
-        int c = tiles[3 * i], tx = tiles[3 * i + 1], ty = tiles[3 * i + 2];
-        const REAL *bg = background ? background + (size_t)D * c : NULL;
-        int len = build_tile_list(P, N, c, W[c], H[c], tx, ty, means2d, radii, depths, untiled, list, tmp);
-        if (list_len) list_len[i] = len;
-        for (int y = ty * ts; y < (ty + 1) * ts && y < H[c]; y++)
-            for (int x = tx * ts; x < (tx + 1) * ts && x < W[c]; x++) {
-                pix_out_t po;
-                composite_pixel(&S, list, len, (REAL)x + K(0.5), (REAL)y + K(0.5), bg, &po);
-                int64_t p = pix_off[c] + (int64_t)y * W[c] + x;
-                for (int ch = 0; ch < D; ch++) image[(size_t)D * p + ch] = po.color[ch];
-                alpha[p] = K(1) - po.T;
-                final_T[p] = po.T;
-                if (last_gid) last_gid[p] = po.last >= 0 ? list[po.last] : -1;
-                if (last_pos) last_pos[p] = po.last;
-                if (n_eval) n_eval[p] = po.n_eval;
-                if (n_comp) n_comp[p] = po.n_comp;
-                if (flags) flags[p] = (uint8_t)po.flags;
-                if (trace) trace[p] = po.trace;
-            }
+    const int ts = P->tile;
+#pragma omp parallel num_threads(g_threads)
+    {
+        int32_t *list = (int32_t *)malloc(sizeof(int32_t) * (N > 0 ? N : 1));
+        did_t *tmp = (did_t *)malloc(sizeof(did_t) * (N > 0 ? N : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int i = 0; i < ntiles; i++) {
+            int c = tiles[3 * i], tx = tiles[3 * i + 1], ty = tiles[3 * i + 2];
+            const REAL *bg = background ? background + (size_t)D * c : NULL;
+            int len = build_tile_list(P, N, c, W[c], H[c], tx, ty, means2d, radii, depths, untiled, list, tmp);
+            if (list_len) list_len[i] = len;
+            for (int y = ty * ts; y < (ty + 1) * ts && y < H[c]; y++)
+                for (int x = tx * ts; x < (tx + 1) * ts && x < W[c]; x++) {
+                    pix_out_t po;
+                    composite_pixel(&S, list, len, (REAL)x + K(0.5), (REAL)y + K(0.5), bg, &po);
+                    int64_t p = pix_off[c] + (int64_t)y * W[c] + x;
+                    store_pixel(&po, D, p, image, alpha, final_T, n_eval, n_comp, flags, trace, margin);
+                    if (last_gid) last_gid[p] = po.last >= 0 ? list[po.last] : -1;
+                    if (last_pos) last_pos[p] = po.last;
+                }
+        }
+        free(list); free(tmp);
     }
-    free(list); free(tmp); free(pix_off); free(tile_off);
+    free(pix_off); free(tile_off);
     return 0;
 }
 
@@ -848,30 +966,41 @@ int orc_render_tiles_bwd(const orc_params *P, int C, int N, int D, const int *W,
     int64_t *pix_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     int64_t *tile_off = (int64_t *)malloc(sizeof(int64_t) * (C + 1));
     camera_offsets(P, C, W, H, pix_off, tile_off);
-    int32_t *list = (int32_t *)malloc(sizeof(int32_t) * (N > 0 ? N : 1));
-    did_t *tmp = (did_t *)malloc(sizeof(did_t) * (N > 0 ? N : 1));
     size_t CN = (size_t)C * N;
-    grad2d_t G;
-    grad2d_alloc(&G, CN, D, abs_sums != NULL, v_means2d_abs != NULL);
+    const int nth = g_threads;
+    grad2d_t *G = grads_per_thread(CN, D, abs_sums != NULL, v_means2d_abs != NULL, nth);
     scene2d_t S = {P, N, means2d, conics, colors, opacities, comps, D};
-    int ts = P->tile;
-    for (int i = 0; i < ntiles; i++) {
-        int c = tiles[3 * i], tx = tiles[3 * i + 1], ty = tiles[3 * i + 2];
-        const REAL *bg = background ? background + (size_t)D * c : NULL;
-        int len = build_tile_list(P, N, c, W[c], H[c], tx, ty, means2d, radii, depths, 0, list, tmp);
-        for (int y = ty * ts; y < (ty + 1) * ts && y < H[c]; y++)
-            for (int x = tx * ts; x < (tx + 1) * ts && x < W[c]; x++) {
-                pix_out_t po;
-                REAL px = (REAL)x + K(0.5), py = (REAL)y + K(0.5);
-                composite_pixel(&S, list, len, px, py, bg, &po);
-                if (po.last < 0) continue;
-                int64_t p = pix_off[c] + (int64_t)y * W[c] + x;
-                composite_pixel_bwd(&S, list, po.last, px, py, bg, po.T, v_image + (size_t)D * p,
-                                    v_alpha ? v_alpha[p] : K(0), &G);
-            }
+    const int ts = P->tile;
+#pragma omp parallel num_threads(nth)
+    {
+#ifdef _OPENMP
+        grad2d_t *Gt = &G[omp_get_thread_num()];
+#else
+        grad2d_t *Gt = &G[0];
+#endif
+        int32_t *list = (int32_t *)malloc(sizeof(int32_t) * (N > 0 ? N : 1));
+        did_t *tmp = (did_t *)malloc(sizeof(did_t) * (N > 0 ? N : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int i = 0; i < ntiles; i++) {
+            int c = tiles[3 * i], tx = tiles[3 * i + 1], ty = tiles[3 * i + 2];
+            const REAL *bg = background ? background + (size_t)D * c : NULL;
+            int len = build_tile_list(P, N, c, W[c], H[c], tx, ty, means2d, radii, depths, 0, list, tmp);
+            for (int y = ty * ts; y < (ty + 1) * ts && y < H[c]; y++)
+                for (int x = tx * ts; x < (tx + 1) * ts && x < W[c]; x++) {
+                    pix_out_t po;
+                    REAL px = (REAL)x + K(0.5), py = (REAL)y + K(0.5);
+                    composite_pixel(&S, list, len, px, py, bg, &po);
+                    if (po.last < 0) continue;
+                    int64_t p = pix_off[c] + (int64_t)y * W[c] + x;
+                    composite_pixel_bwd(&S, list, po.last, px, py, bg, po.T, v_image + (size_t)D * p,
+                                        v_alpha ? v_alpha[p] : K(0), Gt);
+                }
+        }
+        free(list); free(tmp);
     }
-    grad2d_store(&G, CN, v_means2d, v_conics, v_colors, v_opacities, abs_sums, v_means2d_abs);
-    free(list); free(tmp); free(pix_off); free(tile_off);
+    grads_merge(G, nth, CN);
+    grad2d_store(&G[0], CN, v_means2d, v_conics, v_colors, v_opacities, abs_sums, v_means2d_abs);
+    free(G); free(pix_off); free(tile_off);
     return 0;
 }
 
