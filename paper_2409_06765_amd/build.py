@@ -40,17 +40,31 @@ def _hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False, units=None):
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build of the library
+# (argument checking, layout tables, launch set-up; device code is built as
+# usual): python -m paper_2409_06765_amd.build --sanitize writes
+# libgsraster_san.so, which the binding loads when GSR_LIB_VARIANT=san; run
+# the CPU tests of the boundary with clang's ASan runtime preloaded:
+#   LD_PRELOAD=$(ls /opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so) \
+#   ASAN_OPTIONS=detect_leaks=0 GSR_LIB_VARIANT=san python -m pytest tests/test_abi_cpu.py
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+SAN_LIB = os.path.join(PKG, "libgsraster_san.so")
+
+
+def build(verbose=False, units=None, sanitize=False):
     os.makedirs(OUT_DIR, exist_ok=True)
     hipcc = _hipcc()
+    lib_path = SAN_LIB if sanitize else LIB
+    tag = "_san" if sanitize else ""
     procs = []
     objs = []
     for src, extra in UNITS.items():
-        obj = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
+        obj = os.path.join(OUT_DIR, src.replace(".hip", f"{tag}.o"))
         objs.append(obj)
         if units is not None and src not in units and os.path.exists(obj):
             continue
-        cmd = [hipcc, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + extra
+        cmd = [hipcc, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + extra + (SAN_FLAGS if sanitize else [])
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -67,17 +81,18 @@ def build(verbose=False, units=None):
             print("\n".join(lines))
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    tmp = lib_path + ".tmp"
+    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp] + \
+        (["-fsanitize=address,undefined", "-shared-libsan"] if sanitize else [])
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     if r.returncode != 0:
         print(r.stdout.decode(errors="replace"), file=sys.stderr)
         raise RuntimeError("link failed")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":
     t0 = time.time()
-    path = build(verbose="-v" in sys.argv)
+    path = build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv)
     print(f"built {path} in {time.time() - t0:.1f}s")
