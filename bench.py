@@ -4,15 +4,21 @@ Workload (default): 1,000,000 Gaussians in 32 clusters with degree-3 SH,
 rendered at 1920x1080 (fx = fy = 1500) from 16 viewpoints on a radius-6
 sphere; a step is the whole hot path for one view: projection, tile binning
 (depth order, counts and scan, key emission, radix sort on the tile bits,
-tile ranges), forward compositing, backward compositing and the projection
-backward.  The intersection count stays on the device (the lists are built in
-a buffer sized from earlier views; the count is checked after the loop), so
-the host never waits inside a step.  Inputs are resident in HBM before timing
-starts.
+tile ranges, dispatch order), forward compositing, backward compositing and
+the projection backward.  Every buffer of the step is allocated before the
+timed loop (pipeline.ViewPipeline); a step only enqueues library calls, and
+the intersection count stays on the device (the lists are built in a buffer
+sized from an untimed pass over the same views, and every step's count is
+checked after the loop), so the host never waits inside a step.  Inputs are
+resident in HBM before timing starts.
 
-Prints one JSON line.  value = Gaussian-pixel evaluations per second over the
-whole step (forward evaluations + backward evaluations, counted exactly by an
-untimed pass of the same views); ms_per_step = ms per forward+backward view.
+Prints one JSON line.  ms_per_step = wall-clock ms per forward+backward view
+(eager launches); value = forward + backward Gaussian-pixel evaluations the
+timed kernels execute, per second of wall time (counted exactly by an untimed
+pass of the same views); the paper-equivalent rate (every pixel walking its
+tile's whole 3-sigma list until it stops) is reported beside it, as are the
+per-view GPU times (median, p10, p90), the host time of each stage and the
+same step replayed as one captured HIP graph.
 """
 import argparse
 import json
@@ -27,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ms per fwd+bwd view and Gaussian-pixel evals/s @1M Gaussians 1080p; p99 serve latency"
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 4 SIMD x 16 lanes x 2 FMA x 2 packed x 2.4 GHz)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6   # the same without packed FP32, which these kernels are built without
 PEAK_HBM_GBS = 8000.0
 # Algorithmic floating-point operations of the compositing formulas (an exp,
 # a min and a reciprocal count as one each; compares count as none):
@@ -88,8 +95,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-tiles", type=int, default=1800, help="tiles of view 0 the oracle rasterizes")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--graph", action="store_true",
-                    help="also time the step captured as one HIP graph; value and ms_per_step then come from it")
+    ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph leg")
     ap.add_argument("--train-steps", type=int, default=200,
                     help="timed steps of the training leg (0 skips it; 1M workload only)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -124,49 +130,71 @@ def main():
     p = R.make_params(sh_degree=wl["sh_degree"])               # the pipeline's defaults (culled binning)
     p_square = R.make_params(sh_degree=wl["sh_degree"], tile_cull=0)   # the paper's whole 3-sigma squares
 
-    def step(v, timing=None, n_eval=False, p=p):
+    def counting_pass(v, pp):
+        """Untimed: the same view through the allocating entry points with the
+        forward's work counters (n_eval, five per pixel)."""
         vm, Ks = vms[v:v + 1], Kss[v:v + 1]
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)] if timing is not None else None
-        if ev: ev[0].record()
-        proj = R.project(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, [W], [H])
-        if ev: ev[1].record()
-        isect = R.intersect(p, proj, [W], [H])
-        if ev: ev[2].record()
-        fwd = R.rasterize_forward(p, proj, d["opacities"], isect, [W], [H], None, n_eval=n_eval)
-        if ev: ev[3].record()
-        grads = R.grad_buffers(1, N, dev)
-        if ev: ev[4].record()
-        # the compositing backward alone: records reused from the forward, buffers already zero
-        g2 = R.rasterize_backward(p, proj, d["opacities"], isect, [W], [H], fwd, v_image, grads=grads)
-        if ev: ev[5].record()
-        g3 = R.project_backward(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, [W], [H],
-                                proj, g2)
-        if ev:
-            ev[6].record()
-            timing.append((ev, isect))
-        return proj, isect, fwd, g2, g3
-
-    # exact evaluation counts (untimed pass over the views the timed loop uses)
-    views = [i % n_views for i in range(args.steps)]
-    counts = {}
-    for v in sorted(set(views)):
-        # the algorithmic work: evaluations over the paper's square lists (the timed steps composite
-        # the culled lists, which hold every entry a pixel can composite, in the same order)
-        proj, isect, fwd, _, _ = step(v, n_eval=True, p=p_square)
-        M_culled = step(v, p=p)[1]["M"]
+        proj = R.project(pp, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, [W], [H])
+        isect = R.intersect(pp, proj, [W], [H])
+        fwd = R.rasterize_forward(pp, proj, d["opacities"], isect, [W], [H], None, n_eval=True)
+        if isect.check():
+            fwd = R.rasterize_forward(pp, proj, d["opacities"], isect, [W], [H], None, n_eval=True)
         ne = fwd["n_eval"].to(torch.int64)
         last = fwd["last_ids"].to(torch.int64)
         pix = torch.arange(npix, device=dev)
         tile = (pix // W // 16) * ((W + 15) // 16) + (pix % W) // 16
         start = isect["ranges"][tile, 0].to(torch.int64)
         e_bwd = torch.where(last >= 0, last - start + 1, torch.zeros_like(last)).sum()
-        counts[v] = dict(E_fwd=int(ne[:, 0].sum()), C=int(ne[:, 1].sum()), E_bwd=int(e_bwd), M=isect["M"],
-                         M_culled=M_culled)
+        return dict(E_fwd=int(ne[:, 0].sum()), C=int(ne[:, 1].sum()), E_bwd=int(e_bwd), M=isect["M"],
+                    E_fwd_exec=int(ne[:, 2].sum()), E_bwd_exec=int(ne[:, 3].sum()), E_fwd_issued=int(ne[:, 4].sum()))
+
+    # Work counts of every view the timed loop runs (untimed).  Two
+    # definitions: the paper's square 3-sigma tile lists, every pixel walking
+    # its tile's list until it stops ("paper-equivalent"), and the work the
+    # timed kernels really do: the culled lists, each pixel evaluating only
+    # the entries of its 8x8 quad's list while it is live (forward), or up to
+    # its last composited entry (backward).
+    views = [i % n_views for i in range(args.steps)]
+    counts = {}
+    for v in sorted(set(views)):
+        sq = counting_pass(v, p_square)
+        cu = counting_pass(v, p)
+        counts[v] = dict(E_fwd=sq["E_fwd"], E_bwd=sq["E_bwd"], C=sq["C"], M=sq["M"], M_culled=cu["M"],
+                         E_fwd_lists=cu["E_fwd"], E_fwd_exec=cu["E_fwd_exec"], E_bwd_exec=cu["E_bwd_exec"],
+                         E_fwd_issued=cu["E_fwd_issued"], C_culled=cu["C"])
+        assert cu["C"] == sq["C"], "culled and square lists composite different entries"
     torch.cuda.synchronize()
-    log(f"counts view 0: {counts[views[0]]}")
+    log(f"counts view {views[0]}: {counts[views[0]]}")
+
+    # The timed step: every buffer allocated once, the step only enqueues library calls.
+    from paper_2409_06765_amd.pipeline import ViewPipeline
+    cap = int(1.25 * max(c["M_culled"] for c in counts.values())) + 1024
+    nslots = args.warmup + args.steps
+    pipe = ViewPipeline(p, d, [W], [H], cap, slots=nslots)
+    stream = torch.cuda.current_stream()
+    stage_names = ["project_fwd", "intersect", "rasterize_fwd", "zero_grads", "rasterize_bwd", "project_bwd"]
+    stages = [pipe.project, pipe.bin, pipe.rasterize_forward, pipe.zero_grads,
+              lambda: pipe.rasterize_backward(v_image), pipe.project_backward]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] for _ in range(args.steps)]
+    host = np.zeros((args.steps, len(stages)))
+
+    def run(i, v, timed):
+        pipe.set_cameras(vms[v:v + 1], Kss[v:v + 1], copy=False)
+        ev = events[i] if timed else None
+        if ev:
+            ev[0].record(stream)
+        for k, f in enumerate(stages):
+            t0 = time.perf_counter()
+            if k == 1:
+                pipe.bin(slot=i + (args.warmup if timed else 0))
+            else:
+                f()
+            if ev:
+                host[i, k] = time.perf_counter() - t0
+                ev[k + 1].record(stream)
 
     for i in range(args.warmup):
-        step(views[i % len(views)])
+        run(i, views[i % len(views)], False)
     torch.cuda.synchronize()
     if args.calibrate_copy:
         src = torch.ones(64 << 20, device=dev, dtype=torch.float32)
@@ -175,59 +203,56 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    timing = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for v in views:
-        step(v, timing)
+    for i, v in enumerate(views):
+        run(i, v, True)
+    t_host = time.perf_counter() - t_start
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_start
 
-    # every timed view's lists fitted the capacity learned in the untimed passes (no rebuild, no host wait)
-    rebuilt = [isect.check() for _, isect in timing]
-    assert not any(rebuilt), "intersection capacity exceeded in the timed loop"
-    stage_names = ["project_fwd", "intersect", "rasterize_fwd", "zero_grads", "rasterize_bwd", "project_bwd"]
-    stage_ms = {k: 0.0 for k in stage_names}
-    for ev, _ in timing:
-        for i, k in enumerate(stage_names):
-            stage_ms[k] += ev[i].elapsed_time(ev[i + 1]) / len(timing)
+    # every timed view's lists fitted the capacity (no host wait inside the loop; checked after)
+    got = pipe.counts()
+    assert max(got) <= cap, "intersection capacity exceeded in the timed loop"
+    assert [got[args.warmup + i] for i in range(args.steps)] == [counts[v]["M_culled"] for v in views], \
+        "timed steps built other lists than the counting pass"
+    per_stage = np.array([[ev[k].elapsed_time(ev[k + 1]) for k in range(len(stages))] for ev in events])
+    per_view = np.array([ev[0].elapsed_time(ev[-1]) for ev in events])
+    stage_ms = {k: round(float(per_stage[:, i].mean()), 4) for i, k in enumerate(stage_names)}
+    host_ms = {k: round(1e3 * float(host[:, i].mean()), 4) for i, k in enumerate(stage_names)}
     ms_per_step = 1e3 * t_wall / args.steps
-    E_fwd = sum(counts[v]["E_fwd"] for v in views)
-    E_bwd = sum(counts[v]["E_bwd"] for v in views)
-    C_tot = sum(counts[v]["C"] for v in views)
-    value = (E_fwd + E_bwd) / t_wall
+    tot = lambda key: sum(counts[v][key] for v in views)
+    E_fwd, E_bwd, C_tot = tot("E_fwd"), tot("E_bwd"), tot("C")
+    E_fwd_x, E_bwd_x = tot("E_fwd_exec"), tot("E_bwd_exec")
+    value = (E_fwd_x + E_bwd_x) / t_wall
 
-    # dominant kernel: the backward compositing (VALU-bound)
-    bwd_flops = (FLOPS_EVAL * E_bwd + FLOPS_BWD_COMP * C_tot) / args.steps
+    # dominant kernel: the backward compositing (bound by vector-instruction issue)
     bwd_ms = stage_ms["rasterize_bwd"]
-    achieved = bwd_flops / (bwd_ms * 1e-3) / 1e12
-    fwd_flops = (FLOPS_EVAL * E_fwd + FLOPS_FWD_COMP * C_tot) / args.steps
-    fwd_tflops = fwd_flops / (stage_ms["rasterize_fwd"] * 1e-3) / 1e12
+    bwd_flops_x = (FLOPS_EVAL * E_bwd_x + FLOPS_BWD_COMP * C_tot) / args.steps
+    bwd_flops_p = (FLOPS_EVAL * E_bwd + FLOPS_BWD_COMP * C_tot) / args.steps
+    achieved = bwd_flops_x / (bwd_ms * 1e-3) / 1e12
+    achieved_p = bwd_flops_p / (bwd_ms * 1e-3) / 1e12
+    fwd_tflops = (FLOPS_EVAL * E_fwd_x + FLOPS_FWD_COMP * C_tot) / args.steps / (stage_ms["rasterize_fwd"] * 1e-3) / 1e12
     roofline = {"kernel": "raster_bwd_rgb_kernel", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": None}
+                "traffic": None, "work": "executed (quad lists, live lanes)",
+                "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
+                "achieved_paper_equivalent": round(achieved_p, 3),
+                "frac_paper_equivalent": round(achieved_p / PEAK_FP32_TFLOPS, 4)}
     if args.workload == "clusters1m_sh3_1080p":
         t = measured_traffic()
         roofline["traffic"] = None if t is None else int(t)
 
-    # device memory: the resident scene, and the peak one forward + backward view adds on top of what
-    # is allocated before it (projected arrays, lists, records, images, gradients, workspaces)
-    torch.cuda.synchronize()
-    base = torch.cuda.memory_allocated()
-    torch.cuda.reset_peak_memory_stats()
-    step(views[0])
-    torch.cuda.synchronize()
+    # device memory: the resident scene, and what the preallocated forward + backward state of one view takes
     memory = {"scene_bytes": int(sum(v.numel() * v.element_size() for v in d.values())),
-              "per_view_peak_bytes": int(torch.cuda.max_memory_allocated() - base),
+              "per_view_state_bytes": int(_device_bytes(pipe)),
               "device_bytes": int(torch.cuda.get_device_properties(0).total_memory)}
-    log(f"memory: scene {memory['scene_bytes'] / 2**20:.0f} MiB, one fwd+bwd view adds "
-        f"{memory['per_view_peak_bytes'] / 2**20:.0f} MiB at its peak")
+    log(f"memory: scene {memory['scene_bytes'] / 2**20:.0f} MiB, one fwd+bwd view's state "
+        f"{memory['per_view_state_bytes'] / 2**20:.0f} MiB")
 
     graph = None
-    if args.graph:
+    if not args.no_graph:
         from paper_2409_06765_amd.graph import CapturedStep
-        # list capacity for every view the loop replays (the counting pass gave their counts)
-        cap = int(1.25 * max(counts[v]["M_culled"] for v in set(views))) + 1024
         cs = CapturedStep(p, d, [W], [H], v_image, (vms[0:1], Kss[0:1]), capacity=cap)
         for i in range(args.warmup):
             cs.replay(vms[views[i % len(views)]:views[i % len(views)] + 1], Kss[views[i % len(views)]:views[i % len(views)] + 1])
@@ -240,10 +265,10 @@ def main():
         torch.cuda.synchronize()
         tg = time.perf_counter() - tg
         assert int(seen.max()) <= cs.capacity, "a replay's lists exceeded the captured capacity"
-        graph = {"ms_per_view": 1e3 * tg / args.steps, "value": (E_fwd + E_bwd) / tg, "capacity": cs.capacity,
-                 "eager_ms_per_view": ms_per_step, "eager_value": value}
+        graph = {"ms_per_view": round(1e3 * tg / args.steps, 4), "value": (E_fwd_x + E_bwd_x) / tg,
+                 "capacity": cs.capacity}
         log(f"graph: {graph['ms_per_view']:.4f} ms/view (eager {ms_per_step:.4f})")
-        ms_per_step, value, t_wall = graph["ms_per_view"], graph["value"], tg
+        del cs
 
     out = {
         "metric": METRIC,
@@ -255,20 +280,33 @@ def main():
         "dtype": "f32", "data": "synthetic (seeded generators, activated parameters)",
         "config": {"workload": f"{args.workload}: {wl['desc']}", "views_timed": args.steps, "width": W, "height": H,
                    "n_gaussians": int(sc["means"].shape[0])},
+        "value_definition": "forward + backward evaluations the timed kernels execute (culled lists, each pixel's "
+                            "quad list while live / up to its last composited entry) per second of wall time",
         "ms_per_view": ms_per_step,
+        "ms_per_view_gpu": {"median": round(float(np.median(per_view)), 4),
+                            "p10": round(float(np.percentile(per_view, 10)), 4),
+                            "p90": round(float(np.percentile(per_view, 90)), 4)},
         "views_per_s": args.steps / t_wall,
-        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "stage_ms": stage_ms,
+        "stage_ms_median": {k: round(float(np.median(per_stage[:, i])), 4) for i, k in enumerate(stage_names)},
+        "host_ms_per_stage": host_ms,
+        "host_ms_per_step": round(1e3 * t_host / args.steps, 4),
         "evals": {"E_fwd_per_view": E_fwd / args.steps, "E_bwd_per_view": E_bwd / args.steps,
                   "composited_per_view": C_tot / args.steps,
-                  "M_per_view": sum(counts[v]["M"] for v in views) / args.steps,
-                  "M_culled_per_view": sum(counts[v]["M_culled"] for v in views) / args.steps},
-        "evals_per_s_raster": (E_fwd + E_bwd) / (1e-3 * args.steps * (stage_ms["rasterize_fwd"] + stage_ms["rasterize_bwd"])),
-        "raster_fwd_tflops": round(fwd_tflops, 3),
+                  "E_fwd_exec_per_view": E_fwd_x / args.steps, "E_bwd_exec_per_view": E_bwd_x / args.steps,
+                  "E_fwd_culled_lists_per_view": tot("E_fwd_lists") / args.steps,
+                  "E_fwd_issued_per_view": tot("E_fwd_issued") / args.steps,
+                  "E_fwd_issued_over_exec": round(tot("E_fwd_issued") / max(E_fwd_x, 1), 4),
+                  "M_per_view": tot("M") / args.steps, "M_culled_per_view": tot("M_culled") / args.steps},
+        "evals_paper_equivalent_per_s": (E_fwd + E_bwd) / t_wall,
+        "raster_fwd_tflops_executed": round(fwd_tflops, 3),
         "roofline": roofline,
         "memory": memory,
     }
     if graph is not None:
         out["graph"] = graph
+    del pipe
+    torch.cuda.empty_cache()
     if not args.no_serve and args.workload == "clusters1m_sh3_1080p":
         out["serving"] = serving(d, p, args)
     if args.train_steps > 0 and args.workload == "clusters1m_sh3_1080p":
@@ -276,6 +314,23 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, cams, wl, args, counts, views[0])
     print(json.dumps(out), flush=True)
+
+
+def _device_bytes(obj, skip=("scene", "cam")):
+    """Bytes of the distinct device buffers an object holds (its attributes
+    and the values of its dict attributes), leaving out ``skip``."""
+    import torch
+    seen, total = set(), 0
+    for name, v in vars(obj).items():
+        if name in skip:
+            continue
+        for t in (v.values() if isinstance(v, dict) else [v]):
+            if isinstance(t, torch.Tensor) and t.is_cuda:
+                st = t.untyped_storage()
+                if st.data_ptr() not in seen:
+                    seen.add(st.data_ptr())
+                    total += st.nbytes()
+    return total
 
 
 def serving(d, p, args):

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 7
+#define GSR_ABI_VERSION 8
 #define GSR_MAX_CAMERAS 64
 
 enum gsr_status {
@@ -224,6 +224,11 @@ int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const in
 int gsr_tile_order(int32_t total_tiles, const int32_t *ranges, int32_t *order, void *ws, size_t ws_bytes,
                    gsr_stream_t stream);
 
+/* Zeroes bytes (a multiple of 4) of device memory at ptr (4-byte aligned)
+ * with a kernel on the stream: a captured graph replays it like any other
+ * launch, where a memset node may not be. */
+int gsr_fill_zero(void *ptr, size_t bytes, gsr_stream_t stream);
+
 /* Front-to-back compositing (Rasterization of Gaussians).  For every pixel
  * with centre p = (x + 0.5, y + 0.5), over its tile's sorted list:
  *   Delta = mu' - p;  sigma = 0.5 (a Dx^2 + c Dy^2) + b Dx Dy (skipped if < 0);
@@ -246,8 +251,13 @@ int gsr_tile_order(int32_t total_tiles, const int32_t *ranges, int32_t *order, v
  * tile index order; an index out of range skips that block).
  * Outputs: image [P,Dt], alpha [P] = 1 - T, final_T [P] = T, last_ids [P] int32
  * (position in the sorted list of the last composited entry, -1 if none),
- * n_eval [P,2] int32 (nullable): per pixel, the entries evaluated (including
- * the one that stopped it) and the entries composited.
+ * n_eval [P,5] int32 (nullable; work counters, slower): per pixel, (0) the
+ * entries of its tile's list up to and including the one that stopped it (the
+ * whole list if none did), (1) the entries composited, (2) the entries of the
+ * pixel's 8x8 quad list (the tile-list entries whose alpha >= alpha_min
+ * support reaches the quad) that it evaluated while not yet stopped, (3) the
+ * entries of that quad list up to its last composited one, (4) the quad-list
+ * entries its wave stepped through, stopped lanes included.
  * ws: workspace of gsr_workspace_bytes(GSR_OP_RASTERIZE, C, N, 0). */
 int gsr_rasterize_fwd(const gsr_params *p, int C, int N, int D, const int32_t *W, const int32_t *H,
                       const float *means2d, const float *conics, const float *colors, const float *depths,

@@ -13,7 +13,8 @@ import threading
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libgsraster.so")
+# GSR_LIB_VARIANT=san: the host-side sanitizer build (python -m paper_2409_06765_amd.build --sanitize)
+LIB_PATH = os.path.join(_PKG, "libgsraster_san.so" if os.environ.get("GSR_LIB_VARIANT") == "san" else "libgsraster.so")
 
 GSR_OK, GSR_EINVAL, GSR_EOVERFLOW, GSR_EWORKSPACE, GSR_EHIP = 0, 1, 2, 3, 4
 GSR_OP_INTERSECT_COUNT, GSR_OP_SORT, GSR_OP_RASTERIZE, GSR_OP_BIN_PREPARE, GSR_OP_BIN_FINISH = 1, 2, 3, 4, 5
@@ -27,7 +28,7 @@ GSR_COLUMN_COPY, GSR_COLUMN_MEANS, GSR_COLUMN_LOG_SCALES, GSR_COLUMN_STATE = 0, 
 GSR_MAX_CAMERAS = 64
 GSR_BWD_ACCUMULATE, GSR_BWD_PACKED = 1, 2
 GSR_DEPTH_NONE, GSR_DEPTH_ACCUMULATED, GSR_DEPTH_EXPECTED = 0, 1, 2
-ABI_VERSION = 7                 # the signatures below
+ABI_VERSION = 8                 # the signatures below
 _NAMES = {0: "GSR_OK", 1: "GSR_EINVAL", 2: "GSR_EOVERFLOW", 3: "GSR_EWORKSPACE", 4: "GSR_EHIP"}
 
 
@@ -74,6 +75,7 @@ _SIGS = {
     "gsr_bin_finish": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp, _sz,
                         _vp], _i),
     "gsr_tile_order": ([ctypes.c_int32, _vp, _vp, _vp, _sz, _vp], _i),
+    "gsr_fill_zero": ([_vp, _sz, _vp], _i),
     "gsr_rasterize_fwd": ([_P, _i, _i, _i, _vp, _vp] + [_vp] * 10 + [_vp] * 5 + [_vp, _sz, _vp], _i),
     "gsr_rasterize_bwd": ([_P, _i, _i, _i, _vp, _vp] + [_vp] * 15 + [_vp] * 6 + [_vp, _sz, _i, _vp], _i),
     "gsr_project_bwd": ([_P, _i, _i, _vp, _vp] + [_vp] * 9 + [_vp] * 5 + [_vp] * 5 + [_vp, _vp, _sz, _vp], _i),
@@ -240,6 +242,12 @@ def _ws(ws):
 def gsr_tile_order(total_tiles, ranges, order, ws, stream=None):
     _check(lib().gsr_tile_order(int(total_tiles), _ptr(ranges, I32, "ranges"), _ptr(order, I32, "order"), *_ws(ws),
                                 _stream(stream)))
+
+
+def gsr_fill_zero(t, stream=None):
+    """Zeroes the whole of tensor ``t`` (contiguous, on the GPU) with the
+    library's fill kernel."""
+    _check(lib().gsr_fill_zero(_ptr(t, None, "tensor"), t.numel() * t.element_size(), _stream(stream)))
 
 
 def gsr_rasterize_fwd(p, C, N, D, W, H, means2d, conics, colors, depths, opacities, compensations, background,

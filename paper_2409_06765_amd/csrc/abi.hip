@@ -273,6 +273,15 @@ int gsr_bin_finish(const gsr_params *p, int C, int N, const int32_t *W, const in
                              ws_fin, ids, ranges, keys, (hipStream_t)stream);
 }
 
+int gsr_fill_zero(void *ptr, size_t bytes, gsr_stream_t stream) {
+    static const char *fn = "gsr_fill_zero";
+    if (bytes == 0) return GSR_OK;
+    GSR_NEED(ptr);
+    if (bytes % 4 != 0 || ((uintptr_t)ptr & 3u) != 0)
+        return fail(GSR_EINVAL, "%s: ptr must be 4-byte aligned and bytes a multiple of 4", fn);
+    return launch_fill_zero(ptr, bytes, (hipStream_t)stream);
+}
+
 // The channel count: D features (0 .. 32) plus the depth channel, 1 .. 32 in all.
 static int check_channels(const char *fn, const gsr_params *p, int D) {
     const int Dt = D + (p->render_depth != GSR_DEPTH_NONE ? 1 : 0);

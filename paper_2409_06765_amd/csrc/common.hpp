@@ -223,12 +223,21 @@ __device__ __forceinline__ uint32_t quad_mask(float mx, float my, float hx, floa
 
 // Per projected Gaussian record read by the compositing kernels:
 // {mean x, mean y, opacity (times compensation), support half-width x},
-// {a/2, b, c/2 scaled by log2(e), support half-width y},
-// {colour r, g, b, log2(opacity / alpha_min)}, with (a, b, c) the conic.  The
-// scaling gives log2(e) sigma directly (scaled_sigma), the argument of the
-// hardware base-2 exponential; alpha >= alpha_min exactly where
-// log2(e) sigma <= log2(opacity / alpha_min).
+// {A, r, Q, support half-width y}, {colour r, g, b, log2(opacity / alpha_min)},
+// where, with (a, b, c) the conic, sigma = 1/2 (a dx^2 + c dy^2) + b dx dy is
+// held as the completed square
+//     log2(e) sigma = A (dx + r dy)^2 + Q dy^2,
+//     A = log2(e) a / 2,  r = b / a,  Q = log2(e) (a c - b^2) / (2 a)
+// (a > 0 for every projected Gaussian: Sigma' is positive definite).  Both
+// terms are non-negative, so unlike the three-term sum it does not cancel
+// for needle-like Gaussians: its float32 value is within a few ulps of the
+// definition's (plus one ulp of r carried through dy), which is what keeps
+// the skip/stop decisions the same as an exact evaluation's everywhere but
+// on a hair's breadth of the thresholds.  The scaling gives log2(e) sigma
+// directly (scaled_sigma), the argument of the hardware base-2 exponential;
+// alpha >= alpha_min exactly where log2(e) sigma <= log2(opacity / alpha_min).
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr double kLog2eD = 1.4426950408889634074;
 
 // min(alpha, alpha_max) for a non-NaN alpha in one instruction: the median of
 // (alpha, -inf, alpha_max).
@@ -237,7 +246,15 @@ __device__ __forceinline__ float min_alpha(float alpha, float alpha_max) {
 }
 
 __device__ __forceinline__ float scaled_sigma(float4 con, float dx, float dy) {
-    return fmaf(dx, fmaf(con.x, dx, con.y * dy), con.z * dy * dy);
+    const float u = fmaf(con.y, dy, dx);               // dx + (b / a) dy
+    return fmaf(con.x * u, u, con.z * dy * dy);        // A u^2 + Q dy^2
+}
+
+// The scaled conic (A', B', C') = log2(e) (a/2, b, c/2) of a record's
+// completed square: B' = 2 A r, C' = Q + A r^2.
+__device__ __forceinline__ float3 scaled_conic(float4 con) {
+    const float ar = con.x * con.y;
+    return make_float3(con.x, 2.0f * ar, fmaf(ar, con.y, con.z));
 }
 
 // The quadratic q(u, v) = A u^2 + B u v + C v^2 (A, C > 0, 4AC > B^2) on the
@@ -256,7 +273,8 @@ __device__ __forceinline__ float edge_min(float A, float B, float C, float r, fl
 // the convex quadratic is 0 if the rectangle holds d = 0, else on an edge.
 __device__ __forceinline__ uint32_t refine_quad_mask(uint32_t m, float4 xyoh, float4 conh, float Lq,
                                                     float tile_x0, float tile_y0) {
-    const float A = conh.x, B = conh.y, C = conh.z;
+    const float3 k = scaled_conic(conh);
+    const float A = k.x, B = k.y, C = k.z;
     if (m == 0u || !(A > 0.0f) || !(C > 0.0f) || !(4.0f * A * C > B * B)) return m;
     const float ru = -B / (2.0f * C), rv = -B / (2.0f * A);
 #pragma unroll

@@ -265,10 +265,12 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
             v_al = (use && araw <= amax) ? v_al : 0.0f;   // clamped alpha: no gradient to o or sigma
             const float v_sig = -araw * v_al;
             const float h = 0.5f * v_sig;
-            // d sigma / d mean = (a dx + b dy, b dx + c dy) = (2 con.x dx + con.y dy, con.y dx + 2 con.z dy) / log2(e)
-            const float u = v_sig * (1.0f / kLog2e);
-            const float g_mx = u * fmaf(2.0f * con.x, dx, con.y * dy);
-            const float g_my = u * fmaf(2.0f * con.z, dy, con.y * dx);
+            // d sigma / d mean = (a dx + b dy, b dx + c dy) = (a u_c, b u_c + (c - b^2/a) dy) with
+            // u_c = dx + (b/a) dy: in the record's terms (2 A u_c, 2 A r u_c + 2 Q dy) / log2(e)
+            const float u = v_sig * (2.0f / kLog2e);
+            const float uc = fmaf(con.y, dy, dx);
+            const float g_mx = u * (con.x * uc);
+            const float g_my = u * fmaf(con.x * con.y, uc, con.z * dy);
             // transposing butterfly: 8 values -> lane holds value (lane & 7)
             const float w0 = bfly<kDppXor1>(g_mx, g_my, b0);
             const float w1 = bfly<kDppXor1>(h * dx * dx, v_sig * dx * dy, b0);
@@ -444,8 +446,9 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
                 acc[7] = fmaf(wgt, vC[q][2], acc[7]);
                 acc_o += v_sig;
                 if (want_abs) {                                   // per-pixel |dL/dmu'|, log2(e) folded in
-                    acc_ax += fabsf(fmaf(2.0f * con.x, t, con.y * sy));
-                    acc_ay += fabsf(fmaf(2.0f * con.z, sy, con.y * t));
+                    const float tc = fmaf(con.y, sy, t);          // v_sigma u_c, u_c = dx + r dy
+                    acc_ax += fabsf(2.0f * con.x * tc);
+                    acc_ay += fabsf(2.0f * fmaf(con.x * con.y, tc, con.z * sy));
                 }
             }
             if (!any) continue;
@@ -468,9 +471,12 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
             y = b3 ? side : y;
             y = add_xor32(add_xor16(y));
             // lanes 0, 1: dL/dmu' = (2 A' S_dx + B' S_dy, B' S_dx + 2 C' S_dy) / log2(e) with the scaled
-            // conic (A', B', C'); lane 8: dL/do = -(sum of v_sigma) / o
+            // conic (A', B', C') = (A, 2 A r, Q + A r^2), i.e. 2 (A s_c, A r s_c + Q S_dy) / log2(e) with
+            // s_c = S_dx + r S_dy; lane 8: dL/do = -(sum of v_sigma) / o
             const float yo = dpp<kDppXor1>(y);            // lane 0 <-> lane 1
-            const float mean = fmaf(2.0f * (lane == 0 ? con.x : con.z), y, con.y * yo) * (1.0f / kLog2e);
+            const float sdx = lane == 0 ? y : yo, sdy = lane == 0 ? yo : y;
+            const float sc = fmaf(con.y, sdy, sdx);
+            const float mean = (lane == 0 ? con.x * sc : fmaf(con.x * con.y, sc, con.z * sdy)) * (2.0f / kLog2e);
             const float val = lane < 2 ? mean : y * (lane == 8 ? -__builtin_amdgcn_rcpf(xyo.z) : lscale);
             if (lane < nslots && dst_base) {
                 const int g = __builtin_amdgcn_readfirstlane(s_id[e]);   // uniform: scalar index arithmetic

@@ -33,7 +33,15 @@ __global__ void __launch_bounds__(256) pack_kernel(int CN, int N, bool rgb, bool
     const float2 h = support_extent(ca, cb, cc, o, alpha_min);
     PackedGauss r;
     r.xyoh = make_float4(means2d[2 * g], means2d[2 * g + 1], o, h.x);
-    r.conh = make_float4(0.5f * kLog2e * ca, kLog2e * cb, 0.5f * kLog2e * cc, h.y);
+    // the completed square of sigma (see PackedGauss): A, r, Q in double, each rounded once
+    float A = 0.5f * kLog2e * ca, rb = 0.0f, Q = 0.5f * kLog2e * cc;
+    if (ca > 0.0f) {
+        const double ad = ca, bd = cb, cd = cc;
+        A = (float)(0.5 * kLog2eD * ad);
+        rb = cb / ca;
+        Q = (float)(0.5 * kLog2eD * ((ad * cd - bd * bd) / ad));
+    }
+    r.conh = make_float4(A, rb, Q, h.y);
     const float Lq = o >= alpha_min ? log2f(o / alpha_min) : -1.0f;
     const int f = shared ? n : g;
     r.col = rgb ? make_float4(colors[3 * f], colors[3 * f + 1], colors[3 * f + 2], Lq)
@@ -94,6 +102,7 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
 #pragma unroll
     for (int d = 0; d < DM; d++) Cacc[d] = 0.0f;
     int last = -1, ncomp = 0, stop_at = -1;
+    int nq = 0, nq_last = 0, nit = 0;        // counts: quad-list entries evaluated live, up to the last, stepped
     bool done = !inside;
     for (int b0 = start; b0 < end; b0 += kBatch) {
         if (__syncthreads_count(done) == kThreads) break;
@@ -124,7 +133,12 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
             const bool use = !done && sig >= 0.0f && al >= amin;
             const bool stop = use && Tn < tmin;
             const bool comp = use && !stop;
-            if (kCount) stop_at = stop ? b0 + e : stop_at;
+            if (kCount) {
+                stop_at = stop ? b0 + e : stop_at;
+                nit++;
+                nq += done ? 0 : 1;
+                nq_last = comp ? nq : nq_last;
+            }
             done = done || stop;
             const float wgt = comp ? al * T : 0.0f;
             if (kRGB) {
@@ -158,8 +172,12 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     a.last_ids[pix] = last;
     if (kCount) {
         // entries evaluated: up to and including the one that stopped the pixel, else the whole list
-        a.n_eval[2 * pix] = stop_at >= 0 ? stop_at - start + 1 : end - start;
-        a.n_eval[2 * pix + 1] = ncomp;
+        int32_t *ne = a.n_eval + 5 * pix;
+        ne[0] = stop_at >= 0 ? stop_at - start + 1 : end - start;
+        ne[1] = ncomp;
+        ne[2] = nq;          // entries of the quad's list this pixel evaluated (the stopping one included)
+        ne[3] = nq_last;     // entries of the quad's list up to its last composited one (a backward's walk)
+        ne[4] = nit;         // entries its wave stepped through (evaluations issued for this lane)
     }
 }
 

@@ -278,7 +278,7 @@ def rasterize_forward(p, proj, opacities, isect, W, H, background=None, n_eval=F
     f = dict(device=d, dtype=torch.float32)
     out = dict(image=torch.empty((P, channels(p, D)), **f), alpha=torch.empty(P, **f), final_T=torch.empty(P, **f),
                last_ids=torch.empty(P, device=d, dtype=torch.int32),
-               n_eval=torch.empty((P, 2), device=d, dtype=torch.int32) if n_eval else None)
+               n_eval=torch.empty((P, 5), device=d, dtype=torch.int32) if n_eval else None)
     # the workspace keeps the packed per-Gaussian records for the backward
     out["ws"] = raster_workspace(C, N, d)
     L.gsr_rasterize_fwd(pf, C, N, D, W, H, proj["means2d"], proj["conics"], feat, proj["depths"], opacities,

@@ -104,6 +104,11 @@ def test_sort_and_workspace_validation(L):
                                    None) == L.GSR_EWORKSPACE
     assert lib.gsr_intersect_emit(ctypes.byref(p), 1, 10, W, W, fake, fake, fake, fake, -5, fake, fake,
                                   None) == L.GSR_EINVAL
+    # the fill kernel's entry point: whole aligned words only, empty is a no-op
+    assert lib.gsr_fill_zero(fake, 6, None) == L.GSR_EINVAL
+    assert lib.gsr_fill_zero(ctypes.c_void_p(0x1002), 8, None) == L.GSR_EINVAL
+    assert lib.gsr_fill_zero(None, 8, None) == L.GSR_EINVAL
+    assert lib.gsr_fill_zero(None, 0, None) == L.GSR_OK
 
 
 def test_training_entry_points_reject_bad_arguments(L):

@@ -41,7 +41,7 @@ def _pixels(tiles, W, H):
 # Share of sampled pixels the oracle may flag as undecidable at float32 (the
 # share grows with the entries a pixel evaluates: ~500 on the 1M scene, ~1,400
 # with many needle-shaped Gaussians on the 3M scene seen from inside).
-FLAG_BAR = {"clusters1m_sh3_1080p": 0.01, "box3m_sh3_1080p": 0.10}
+FLAG_BAR = {"clusters1m_sh3_1080p": 1e-3, "box3m_sh3_1080p": 3e-3}
 
 
 @pytest.mark.parametrize("wl", ["clusters1m_sh3_1080p", "box3m_sh3_1080p"])
