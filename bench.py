@@ -353,21 +353,31 @@ def serving(d, p, args):
     Server(be, max_batch=16, mem_budget=24 << 30).run(probe)   # warm up the batched shapes too
     torch.cuda.synchronize()
     _, bcap = Server(be, max_batch=16, mem_budget=24 << 30).run(probe)
-    rate = args.serve_load * cap.views_per_s
-    trace = scenes.serving_trace(rate, n_requests=args.serve_requests, seed=0)
-    log(f"serving: capacity {cap.views_per_s:.1f} views/s one at a time, {bcap.views_per_s:.1f} batched; "
-        f"trace at {rate:.1f} req/s")
-    _, single = serve_one_at_a_time(be, trace)
-    torch.cuda.synchronize()
-    _, batched = Server(be, max_batch=16, mem_budget=24 << 30).run(trace)
-    torch.cuda.synchronize()
+    log(f"serving: capacity {cap.views_per_s:.1f} views/s one at a time, {bcap.views_per_s:.1f} batched")
     pick = lambda st: {"views_per_s": round(st.views_per_s, 2), "p50_ms": round(st.p50_ms, 3),
                        "p99_ms": round(st.p99_ms, 3), "mean_batch": round(st.mean_batch, 2),
                        "done": st.n_done, "rejected": st.n_rejected}
-    return {"requests": args.serve_requests, "arrival_rate_per_s": round(rate, 2),
+
+    def at(load):
+        """Both policies on one trace of Poisson arrivals at load x the one-view capacity."""
+        rate = load * cap.views_per_s
+        trace = scenes.serving_trace(rate, n_requests=args.serve_requests, seed=0)
+        _, single = serve_one_at_a_time(be, trace)
+        torch.cuda.synchronize()
+        _, batched = Server(be, max_batch=16, mem_budget=24 << 30).run(trace)
+        torch.cuda.synchronize()
+        log(f"serving at {load}x ({rate:.0f} req/s): batched p50/p99 {batched.p50_ms:.2f}/{batched.p99_ms:.2f} ms, "
+            f"mean batch {batched.mean_batch:.2f}; one view per launch {single.p50_ms:.2f}/{single.p99_ms:.2f} ms")
+        return {"load": load, "arrival_rate_per_s": round(rate, 2), "batched": pick(batched),
+                "one_view_per_launch": pick(single)}
+
+    head = at(args.serve_load)
+    sweep = [head if abs(x - args.serve_load) < 1e-9 else at(x) for x in (0.5, 0.8, 1.0, 1.5)]
+    return {"requests": args.serve_requests, "arrival_rate_per_s": head["arrival_rate_per_s"],
             "one_view_capacity_views_per_s": round(cap.views_per_s, 2),
             "batched_capacity_views_per_s": round(bcap.views_per_s, 2),
-            "batched": pick(batched), "one_view_per_launch": pick(single)}
+            "batched": head["batched"], "one_view_per_launch": head["one_view_per_launch"],
+            "sweep": sweep}
 
 
 # Adam moves per element: param, exp_avg, exp_avg_sq read and written, the
@@ -481,10 +491,24 @@ def training(sc, cams, wl, args):
     return out
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(sc, cams, wl, args, counts, v0):
-    """The oracle (single-threaded C, float32) on view 0: full projection,
-    binning and sort, then forward + backward compositing of a sample of
-    tiles; the compositing time is scaled by the evaluation counts."""
+    """The oracle (C, float32, gcc -O2) on view 0: full projection, binning
+    and sort, then forward + backward compositing of tiles, on one thread (a
+    sample of tiles, scaled by the evaluation counts) and on every host core
+    this process may use (its loops over tiles on OpenMP threads, the whole
+    frame).  The all-core figure is the reported value."""
+    import oracle
     from oracle import Oracle, OracleParams
     from paper_2409_06765_amd import scenes
 
@@ -492,42 +516,58 @@ def cpu_baseline(sc, cams, wl, args, counts, v0):
     P = OracleParams(sh_degree=wl["sh_degree"])
     one = {k: v[v0:v0 + 1] for k, v in cams.items()}
     W, H = int(one["W"][0]), int(one["H"][0])
-    t0 = time.perf_counter()
-    proj = o.project(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], one["viewmats"],
-                     one["Ks"], one["W"], one["H"])
-    t1 = time.perf_counter()
-    isect = o.intersect(P, proj, one["W"], one["H"])
-    t2 = time.perf_counter()
     TX, TY = (W + 15) // 16, (H + 15) // 16
-    g = np.random.default_rng(0)
-    lens = isect["ranges"][:, 1] - isect["ranges"][:, 0]
-    busy = np.nonzero(lens > 0)[0]
-    pick = g.choice(busy, size=min(args.cpu_sample_tiles, busy.size), replace=False)
-    mask = np.zeros(TX * TY, np.uint8)
-    mask[pick] = 1
-    ras = o.rasterize_fwd(P, proj, sc["opacities"], isect["ranges"], isect["ids"], one["W"], one["H"], tile_mask=mask)
-    t3 = time.perf_counter()
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     v_image, _ = scenes.upstream_grads(args.workload, W * H, seed=0)
-    o.rasterize_bwd(P, proj, sc["opacities"], isect["ranges"], isect["ids"], one["W"], one["H"], ras["final_T"],
-                    ras["last_ids"], v_image, tile_mask=mask)
-    t4 = time.perf_counter()
-    # evaluation counts of the sample (same definitions as the GPU counts)
-    pixmask = np.zeros(W * H, bool)
     ys, xs = np.divmod(np.arange(W * H), W)
-    pixmask = mask[(ys // 16) * TX + xs // 16] == 1
-    start = isect["ranges"][(ys // 16) * TX + xs // 16, 0]
-    last = ras["last_ids"]
-    e_fwd_s = int(ras["n_eval"][pixmask].sum())
-    e_bwd_s = int(np.where(last >= 0, last - start + 1, 0)[pixmask].sum())
+    tile_of_pix = (ys // 16) * TX + xs // 16
     E_view = counts[v0]["E_fwd"] + counts[v0]["E_bwd"]
-    scale = E_view / max(e_fwd_s + e_bwd_s, 1)
-    t_view = (t1 - t0) + (t2 - t1) + (t4 - t2) * scale
-    return {"value": E_view / t_view, "unit": "Gaussian-pixel evals/s", "cores": 1, "kind": "oracle",
-            "ms_per_view_est": 1e3 * t_view,
-            "sample": f"view 0: projection of all {sc['means'].shape[0]} Gaussians ({1e3 * (t1 - t0):.0f} ms), "
-                      f"binning + qsort of M={isect['M']} ({1e3 * (t2 - t1):.0f} ms), forward+backward compositing "
-                      f"of {mask.sum()} of {TX * TY} tiles ({1e3 * (t4 - t2):.0f} ms, {e_fwd_s + e_bwd_s} evals), "
-                      f"scaled by evaluations x{scale:.1f}; single thread, float32, gcc -O2"}
+
+    def run(threads, sample_tiles):
+        oracle.set_threads(threads)
+        try:
+            t0 = time.perf_counter()
+            proj = o.project(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], one["viewmats"],
+                             one["Ks"], one["W"], one["H"])
+            t1 = time.perf_counter()
+            isect = o.intersect(P, proj, one["W"], one["H"])
+            t2 = time.perf_counter()
+            lens = isect["ranges"][:, 1] - isect["ranges"][:, 0]
+            busy = np.nonzero(lens > 0)[0]
+            mask = np.zeros(TX * TY, np.uint8)
+            if sample_tiles is None or sample_tiles >= busy.size:
+                mask[busy] = 1
+            else:
+                mask[np.random.default_rng(0).choice(busy, size=sample_tiles, replace=False)] = 1
+            ras = o.rasterize_fwd(P, proj, sc["opacities"], isect["ranges"], isect["ids"], one["W"], one["H"],
+                                  tile_mask=mask)
+            o.rasterize_bwd(P, proj, sc["opacities"], isect["ranges"], isect["ids"], one["W"], one["H"],
+                            ras["final_T"], ras["last_ids"], v_image, tile_mask=mask)
+            t3 = time.perf_counter()
+        finally:
+            oracle.set_threads(1)
+        # evaluation counts of the tiles run (the same definitions as the GPU's square-list counts)
+        pixmask = mask[tile_of_pix] == 1
+        start = isect["ranges"][tile_of_pix, 0]
+        last = ras["last_ids"]
+        e_s = int(ras["n_eval"][pixmask].sum()) + int(np.where(last >= 0, last - start + 1, 0)[pixmask].sum())
+        scale = E_view / max(e_s, 1)
+        t_view = (t1 - t0) + (t2 - t1) + (t3 - t2) * scale
+        desc = (f"projection of all {sc['means'].shape[0]} Gaussians ({1e3 * (t1 - t0):.0f} ms), binning + qsort "
+                f"of M={isect['M']} ({1e3 * (t2 - t1):.0f} ms), forward+backward compositing of {int(mask.sum())} of "
+                f"{TX * TY} tiles ({1e3 * (t3 - t2):.0f} ms, {e_s} evals)"
+                + (f", scaled by evaluations x{scale:.2f}" if scale > 1.0001 else ""))
+        return E_view / t_view, 1e3 * t_view, desc
+
+    v1, ms1, d1 = run(1, args.cpu_sample_tiles)
+    vn, msn, dn = run(cores, None)
+    log(f"cpu baseline: 1 thread {ms1:.0f} ms/view, {cores} threads {msn:.0f} ms/view")
+    return {"value": vn, "unit": "Gaussian-pixel evals/s", "cores": cores, "kind": "oracle",
+            "ms_per_view_est": msn,
+            "sample": f"view 0 on {cores} threads: {dn}; float32, gcc -O2 -fopenmp (compositing loops over tiles "
+                      f"threaded, projection and binning on one thread)",
+            "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
+            "single_thread": {"value": v1, "cores": 1, "ms_per_view_est": ms1, "sample": f"view 0: {d1}"}}
 
 
 if __name__ == "__main__":

@@ -397,6 +397,7 @@ class RasterizeGaussians(torch.autograd.Function):
         g2 = rasterize_backward(p, ctx.proj, opacities, ctx.isect, W, H, ctx.fwd, v_image, v_alpha, background,
                                 absgrad=ctx.absgrad, features=None if sh else colors)
         ctx.meta["means2d_grad"] = g2["v_means2d"]          # dL/d(2D means) per view, for densification
+        ctx.meta["grads2d"] = g2                            # every compositing gradient, per view
         if ctx.absgrad:
             ctx.meta["means2d_absgrad"] = g2["v_means2d_abs"]
         want_vm = ctx.needs_input_grad[5]

@@ -11,6 +11,26 @@ from paper_2409_06765_amd import scenes
 
 pytestmark = pytest.mark.gpu
 O32 = Oracle(np.float32)
+O64 = Oracle(np.float64)
+
+
+def _oracle_grads2d(P, sc, cams, proj, isect, v_image, v_alpha=None):
+    """The float64 oracle's compositing gradients of the float32 projected
+    values and lists."""
+    a = (P, proj, sc["opacities"], isect["ranges"], isect["ids"], cams["W"], cams["H"])
+    r64 = O64.rasterize_fwd(*a)
+    return O64.rasterize_bwd(*a, r64["final_T"], r64["last_ids"], v_image, v_alpha)
+
+
+def _views_summed(v, C=None):
+    """[V,N,D] -> [C,N,D] (C = V by default) holding the sum over the V views
+    in view 0 and zeros elsewhere: the projection backward of direct colours
+    only sums the views' colour gradients."""
+    v = np.asarray(v, np.float64)
+    C = v.shape[0] if C is None else C
+    out = np.zeros((C,) + v.shape[1:])
+    out[0] = v.sum(axis=0)
+    return out
 
 
 def _leaves(sc):
@@ -20,7 +40,7 @@ def _leaves(sc):
 
 @pytest.mark.parametrize("deg,aa", [(3, False), (-1, False), (2, True)])
 def test_autograd_matches_oracle_gradients(deg, aa):
-    from _gpu import assert_grad_close
+    from _gpu import assert_chain_close, oracle_project_bwd
     from paper_2409_06765_amd import rasterization
     print(f"[gpu-autograd] deg={deg} aa={aa}", flush=True)
     sc = scenes.scene_tiny(300, sh_degree=deg, seed=21 + deg, log_scale_mean=-2.4)
@@ -40,10 +60,18 @@ def test_autograd_matches_oracle_gradients(deg, aa):
     loss = (image.reshape(-1, 3) * torch.from_numpy(v_image).cuda()).sum() + \
            (alpha.reshape(-1) * torch.from_numpy(v_alpha).cuda()).sum()
     loss.backward()
-    g2, g3 = O32.backward(P, sc, cams, proj, isect, ras, v_image, v_alpha)
-    for k, ko in (("means", "v_means"), ("quats", "v_quats"), ("scales", "v_scales"), ("opacities", "v_opacities"),
-                  ("sh", "v_sh")):
-        assert_grad_close(t[k].grad.cpu().numpy(), g3[ko], f"autograd:{k}", rtol=2e-3)
+    # the chain through the autograd entry point (its compositing gradients from meta) against the float64
+    # oracle chain
+    o2x = _oracle_grads2d(P, sc, cams, proj, isect, v_image, v_alpha)
+    g2 = {k: v.detach().cpu().numpy() for k, v in meta["grads2d"].items() if v is not None}
+    if deg < 0:           # direct colours shared by the views: one gradient row per Gaussian, the views' sum
+        o2x["v_colors"] = _views_summed(o2x["v_colors"])
+        g2["v_colors"] = _views_summed(g2["v_colors"].reshape((-1,) + o2x["v_colors"].shape[1:]), C=len(cams["W"]))
+    g3 = {ko: t[k].grad.cpu().numpy() for k, ko in (("means", "v_means"), ("quats", "v_quats"),
+                                                     ("scales", "v_scales"), ("opacities", "v_opacities"),
+                                                     ("sh", "v_sh"))}
+    pb32, pb64 = oracle_project_bwd(O32, P, sc, cams), oracle_project_bwd(O64, P, sc, cams)
+    assert_chain_close(g3, g2, o2x, pb64(o2x), pb32, pb64, f"autograd deg={deg} aa={aa}")
 
 
 def test_gpu_central_differences_on_smooth_parameters():
@@ -94,7 +122,7 @@ def test_autograd_viewmat_gradient_matches_oracle():
     """viewmats with requires_grad: the pose gradient through the whole
     rasterizer (compositing backward, then projection backward) against the
     oracle's chain on the same upstream gradients (flagged pixels zeroed)."""
-    from _gpu import assert_grad_close
+    from _gpu import assert_chain_close, oracle_project_bwd
     from paper_2409_06765_amd import rasterization
     print("[gpu-autograd] viewmat gradient", flush=True)
     sc = scenes.scene_tiny(250, sh_degree=2, seed=61, log_scale_mean=-2.4)
@@ -107,11 +135,11 @@ def test_autograd_viewmat_gradient_matches_oracle():
     t = _leaves(sc)
     vm = torch.from_numpy(cams["viewmats"]).cuda().requires_grad_(True)
     Ks = torch.from_numpy(cams["Ks"]).cuda()
-    image, _, _ = rasterization(t["means"], t["quats"], t["scales"], t["opacities"], t["sh"], vm, Ks, 80, 60)
+    image, _, meta = rasterization(t["means"], t["quats"], t["scales"], t["opacities"], t["sh"], vm, Ks, 80, 60)
     (image.reshape(-1, 3) * torch.from_numpy(v_image).cuda()).sum().backward()
-    g2 = O32.rasterize_bwd(P, proj, sc["opacities"], isect["ranges"], isect["ids"], cams["W"], cams["H"],
-                           ras["final_T"], ras["last_ids"], v_image)
-    g3 = O32.project_bwd(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],
-                         cams["Ks"], cams["W"], cams["H"], g2["v_means2d"], g2["v_conics"], g2["v_colors"],
-                         g2["v_opacities"], viewmat_grad=True)
-    assert_grad_close(vm.grad.cpu().numpy(), g3["v_viewmats"], "autograd:viewmats", rtol=2e-3)
+    o2x = _oracle_grads2d(P, sc, cams, proj, isect, v_image)
+    g2 = {k: v.detach().cpu().numpy() for k, v in meta["grads2d"].items() if v is not None}
+    g3 = {"v_viewmats": vm.grad.cpu().numpy(), "v_means": t["means"].grad.cpu().numpy()}
+    pb32 = oracle_project_bwd(O32, P, sc, cams, viewmat_grad=True)
+    pb64 = oracle_project_bwd(O64, P, sc, cams, viewmat_grad=True)
+    assert_chain_close(g3, g2, o2x, pb64(o2x), pb32, pb64, "autograd:viewmats", keys=("v_viewmats", "v_means"))

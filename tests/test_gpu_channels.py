@@ -105,7 +105,7 @@ def test_expected_depth_through_rasterization_matches_oracle_chain():
     (including the depth channel's way through t_z) against the oracle's
     projection backward fed by its compositing backward."""
     import torch
-    from _gpu import assert_grad_close, np_, to_dev
+    from _gpu import assert_chain_close, np_, oracle_project_bwd, to_dev
     from paper_2409_06765_amd.rasterize import rasterization
     sc = scenes.scene_tiny(300, sh_degree=1, seed=77, log_scale_mean=-2.4)
     cams = scenes.cams_tiny(W=72, H=56, f=55.0, n_cams=2, seed=77)
@@ -128,13 +128,16 @@ def test_expected_depth_through_rasterization_matches_oracle_chain():
     loss = (img * to_dev(v_image).view(img.shape)).sum()
     loss.backward()
     torch.cuda.synchronize()
-    o2 = O32.channels_bwd(*args, ref, v_image, depth="expected")
-    o3 = O32.project_bwd(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],
-                         cams["Ks"], cams["W"], cams["H"], o2["v_means2d"], o2["v_conics"], o2["v_colors"],
-                         o2["v_opacities"], v_depths=o2["v_depths"])
-    for k, ko in (("means", "v_means"), ("quats", "v_quats"), ("scales", "v_scales"),
-                  ("opacities", "v_opacities"), ("sh", "v_sh")):
-        assert_grad_close(np_(t[k].grad), o3[ko], f"chain:{k}", rtol=2e-3)
+    # the chain (compositing gradients from meta, then the projection backward with the depth channel's way
+    # through t_z) against the float64 oracle chain
+    O64 = Oracle(np.float64)
+    ref64 = O64.channels_fwd(*args, depth="expected")
+    o2x = O64.channels_bwd(*args, ref64, v_image, depth="expected")
+    g2 = {k: np_(v) for k, v in meta["grads2d"].items() if v is not None}
+    g3 = {ko: np_(t[k].grad) for k, ko in (("means", "v_means"), ("quats", "v_quats"), ("scales", "v_scales"),
+                                            ("opacities", "v_opacities"), ("sh", "v_sh"))}
+    pb32, pb64 = oracle_project_bwd(O32, P, sc, cams), oracle_project_bwd(O64, P, sc, cams)
+    assert_chain_close(g3, g2, o2x, pb64(o2x), pb32, pb64, "RGB+ED")
 
 
 def test_channel_count_limits_are_rejected():

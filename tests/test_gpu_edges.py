@@ -232,3 +232,33 @@ def test_tile_order_is_longest_first_and_changes_nothing():
     g1 = R.rasterize_backward(p, st["proj"], d["opacities"], isect, st["W"], st["H"], f1, v)
     for k in ("v_means2d", "v_conics", "v_colors", "v_opacities"):
         assert_grad_close(np_(g1[k]), np_(g0[k]), k)
+
+
+@pytest.mark.parametrize("C,N", [(1, 2), (1, 63), (1, 64), (1, 1025), (1, 16384), (2, 8192), (1, 16385)])
+def test_binning_keeps_equal_depths_in_id_order(C, N):
+    """Many projected Gaussians share one depth bit pattern (means on three
+    planes z = const seen by cameras whose rotation is exact): the depth
+    order of gsr_bin_prepare (one block up to 16,384 keys, the multi-block
+    sort beyond) must keep ties in id order, so that every tile's list is in
+    (depth, id) order; ids and ranges bit for bit against the oracle's
+    stable order (Rasterization of Gaussians: per-tile depth sort)."""
+    from _gpu import gpu_forward, np_, params
+    _say(f"equal-depth binning C={C} N={N}")
+    g = np.random.default_rng(N + C)
+    sc = scenes.scene_tiny(N, seed=N, log_scale_mean=-3.5)
+    plane = g.integers(0, 3, N)
+    plane[:2] = 1                                      # at least one tie, also for N = 2
+    sc["means"][:, 2] = np.float32([-0.25, 0.0, 0.5])[plane]
+    sc["means"][:, :2] = g.uniform(-1.2, 1.2, (N, 2)).astype(np.float32)
+    # eyes on the z axis looking down -z: rotation diag(1, -1, -1) and t = (0, 0, d) are exact, so
+    # t_z = d - z has one bit pattern per plane
+    eyes = [[0.0, 0.0, 4.0], [0.0, 0.0, 5.0]][:C]
+    cams = scenes.cameras([scenes.look_at(e) for e in eyes], [scenes.intrinsics(60.0, 96, 80)] * C, 96, 80)
+    st = gpu_forward(params(), sc, cams)
+    proj, isect, _ = O32.forward(OracleParams(), sc, cams)
+    dep = proj["depths"][proj["radii"] > 0]
+    assert np.unique(dep).size <= 3 * C and dep.size > np.unique(dep).size, "the scene must hold ties"
+    np.testing.assert_array_equal(np_(st["proj"]["depths"]), proj["depths"])
+    assert st["isect"]["M"] == isect["M"]
+    np.testing.assert_array_equal(np_(st["isect"]["ids"]), isect["ids"])
+    np.testing.assert_array_equal(np_(st["isect"]["ranges"]), isect["ranges"])

@@ -15,10 +15,13 @@ Projection Gradients), on every host core.  Checked:
 * compositing gradients element-wise at 1e-3 relative (plus the float32
   summation scale of each element's terms), the upstream gradient being
   zero on flagged pixels on both sides;
-* the projection gradients end to end against the float64 oracle chain
-  (double-precision compositing of the same float32 projected values, then
-  the double projection backward), at 1e-3 relative or within four times
-  the float32 oracle chain's own distance from it, elementwise.
+* the projection backward of the GPU's own compositing gradients against
+  the float64 oracle's, at 1e-3 relative or within four times the float32
+  oracle's distance from it, elementwise; and the projection gradients end
+  to end against the float64 oracle chain (double-precision compositing of
+  the same float32 projected values, then the double projection backward)
+  at 1e-3 relative plus the measured compositing error carried through the
+  projection backward (tests/_gpu.py assert_chain_close).
 
 The 3M-Gaussian scene seen from inside is checked the same way on 512
 tiles (the 64 with the longest lists and 448 more at random), whose pixels
@@ -128,19 +131,15 @@ def _check_view(wl, choose_tiles=None, flag_bar=1e-3):
         _say(f"{wl}: forward ok (max image error {err[ok].max():.2e}); oracle backward")
 
         o2 = O32.rasterize_bwd(*args, ras["final_T"], ras["last_ids"], v_image, tile_mask=tiles_mask, abs_sums=True)
-        from _gpu import assert_as_accurate_as_f32, assert_grad_close
+        from _gpu import assert_chain_close, assert_grad_close, oracle_project_bwd
         for k in ("v_means2d", "v_conics", "v_colors", "v_opacities"):
             assert_grad_close(g["g2"][k], o2[k], f"{wl}:{k}", abs_ref=o2["abs_" + k])
         # the chain: the float64 oracle's compositing of the same float32 projected values, then its projection
-        # backward; the float32 oracle's own chain measures how far float32 evaluation lands from it
+        # backward; the GPU's projection backward of its own compositing gradients checked stage-wise
         r64 = O64.rasterize_fwd(*args, tile_mask=tiles_mask)
         o2x = O64.rasterize_bwd(*args, r64["final_T"], r64["last_ids"], v_image, tile_mask=tiles_mask)
-        pb = (P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"], cams["Ks"],
-              cams["W"], cams["H"])
-        o3 = O32.project_bwd(*pb, o2["v_means2d"], o2["v_conics"], o2["v_colors"], o2["v_opacities"])
-        o3x = O64.project_bwd(*pb, o2x["v_means2d"], o2x["v_conics"], o2x["v_colors"], o2x["v_opacities"])
-        for k in ("v_means", "v_quats", "v_scales", "v_opacities", "v_sh"):
-            assert_as_accurate_as_f32(g["g3"][k], [o3[k]], o3x[k], f"{wl}:chain:{k}")
+        pb32, pb64 = oracle_project_bwd(O32, P, sc, cams), oracle_project_bwd(O64, P, sc, cams)
+        assert_chain_close(g["g3"], g["g2"], o2x, pb64(o2x), pb32, pb64, wl)
         _say(f"{wl}: gradients ok")
     finally:
         oracle.set_threads(1)

@@ -15,6 +15,7 @@ from _util import wide_cone_scene
 pytestmark = pytest.mark.gpu
 
 O32 = Oracle(np.float32)
+O64 = Oracle(np.float64)
 
 
 def _say(msg):
@@ -155,9 +156,14 @@ def test_rasterize_backward_and_projection_backward(case):
     for k, ko in (("v_means", "v_means"), ("v_quats", "v_quats"), ("v_scales", "v_scales"),
                   ("v_opacities", "v_opacities"), ("v_sh", "v_sh")):
         assert_grad_close(np_(g3o[k]), o3[ko], f"{name}:{k}")
-    # end to end: the GPU chain against the oracle chain
-    for k in ("v_means", "v_quats", "v_scales", "v_opacities", "v_sh"):
-        assert_grad_close(np_(g3[k]), o3[k], f"{name}:chain:{k}", rtol=2e-3)
+    # end to end: the GPU chain against the float64 oracle chain
+    from _gpu import assert_chain_close, oracle_project_bwd
+    a = (P, proj, sc["opacities"], isect["ranges"], isect["ids"], cams["W"], cams["H"])
+    r64 = O64.rasterize_fwd(*a, background=bg)
+    o2x = O64.rasterize_bwd(*a, r64["final_T"], r64["last_ids"], v_image, v_alpha, background=bg)
+    pb32, pb64 = oracle_project_bwd(O32, P, sc, cams), oracle_project_bwd(O64, P, sc, cams)
+    assert_chain_close({k: np_(v) for k, v in g3.items() if v is not None},
+                       {k: np_(v) for k, v in g2.items() if v is not None}, o2x, pb64(o2x), pb32, pb64, name)
 
 
 def test_forward_is_deterministic_and_backward_reproducible(case):
@@ -170,6 +176,15 @@ def test_forward_is_deterministic_and_backward_reproducible(case):
     v_image, _ = scenes.upstream_grads("tiny", npix, seed=9)
     a2, a3 = gpu_backward(p, st, v_image)
     b2, b3 = gpu_backward(p, st2, v_image)
-    for k in ("v_means", "v_scales", "v_sh"):
-        x, y = np_(a3[k]), np_(b3[k])
+    # the compositing backward sums with float atomics, in whatever order they land: two runs agree to
+    # 1e-6 of the norm; the projection backward has no atomics: the same inputs give the same bits (so
+    # its outputs differ between the runs only as far as the compositing gradients carry through it)
+    for k in ("v_means2d", "v_conics", "v_colors", "v_opacities"):
+        x, y = np_(a2[k]), np_(b2[k])
         assert np.linalg.norm(x - y) <= 1e-6 * max(np.linalg.norm(x), 1e-30), k
+    from paper_2409_06765_amd import rasterize as R
+    d = st["d"]
+    c3 = R.project_backward(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], st["vm"], st["Ks"],
+                            st["W"], st["H"], st["proj"], a2)
+    for k in ("v_means", "v_quats", "v_scales", "v_opacities", "v_sh"):
+        np.testing.assert_array_equal(np_(c3[k]), np_(a3[k]), err_msg=k)
