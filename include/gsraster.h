@@ -170,6 +170,22 @@ int gsr_intersect_emit(const gsr_params *p, int C, int N, const int32_t *W, cons
 int gsr_sort_pairs(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uint64_t *keys_alt,
                    int32_t *ids_alt, void *ws, size_t ws_bytes, gsr_stream_t stream);
 
+/* gsr_sort_pairs without the workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same result,
+ * bit for bit, with the digit histograms in a static device array of the
+ * library (16 MiB + 1 KiB per GPU it runs on, held until the process ends).
+ * M must be at most GSR_SORT_NOALLOC_MAX_PAIRS (2^25); larger M is rejected
+ * with GSR_EINVAL before anything is enqueued.  keys_alt/ids_alt [M] are
+ * still the caller's.  Runs on the current device (the stream must belong to
+ * it); the first call on a device looks up that device's copy of the array.
+ * Every call on one GPU uses the same array: calls that overlap in time on
+ * one GPU (different streams, or host threads) race and must be serialised
+ * by the caller; calls on one stream are. */
+#define GSR_SORT_NOALLOC_MAX_PAIRS ((int64_t)1 << 25)
+int gsr_sort_pairs_noalloc(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uint64_t *keys_alt,
+                           int32_t *ids_alt, gsr_stream_t stream);
+
 /* ranges [total_tiles, 2] int32: [start, end) of each tile's run in the
  * sorted keys; (0, 0) for an empty tile.  Keys must be sorted. */
 int gsr_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_t *ranges,

@@ -70,6 +70,7 @@ _SIGS = {
     "gsr_intersect_count": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
     "gsr_intersect_emit": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp], _i),
     "gsr_sort_pairs": ([_i64, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
+    "gsr_sort_pairs_noalloc": ([_i64, _i, _vp, _vp, _vp, _vp, _vp], _i),
     "gsr_tile_ranges": ([_i64, _vp, ctypes.c_int32, _vp, _vp], _i),
     "gsr_bin_prepare": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
     "gsr_bin_finish": ([_P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp, _sz,
@@ -207,6 +208,15 @@ def gsr_sort_pairs(M, key_bits, keys, ids, keys_alt, ids_alt, ws, stream=None):
     _check(lib().gsr_sort_pairs(int(M), int(key_bits), _ptr(keys, U64, "keys"), _ptr(ids, I32, "ids"),
                                 _ptr(keys_alt, U64, "keys_alt"), _ptr(ids_alt, I32, "ids_alt"),
                                 _ptr(ws, None, "workspace"), ws_bytes, _stream(stream)))
+
+
+GSR_SORT_NOALLOC_MAX_PAIRS = 1 << 25
+
+
+def gsr_sort_pairs_noalloc(M, key_bits, keys, ids, keys_alt, ids_alt, stream=None):
+    _check(lib().gsr_sort_pairs_noalloc(int(M), int(key_bits), _ptr(keys, U64, "keys"), _ptr(ids, I32, "ids"),
+                                        _ptr(keys_alt, U64, "keys_alt"), _ptr(ids_alt, I32, "ids_alt"),
+                                        _stream(stream)))
 
 
 def gsr_tile_ranges(M, keys, total_tiles, ranges, stream=None):

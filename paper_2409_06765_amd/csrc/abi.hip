@@ -200,6 +200,18 @@ int gsr_sort_pairs(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uint64
     return launch_sort_pairs(M, key_bits, keys, ids, keys_alt, ids_alt, ws, (hipStream_t)stream);
 }
 
+int gsr_sort_pairs_noalloc(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uint64_t *keys_alt,
+                           int32_t *ids_alt, gsr_stream_t stream) {
+    static const char *fn = "gsr_sort_pairs_noalloc";
+    if (M < 0 || M > sort_static_max_pairs())
+        return fail(GSR_EINVAL, "%s: M must be in 0..%lld (got %lld)", fn, (long long)sort_static_max_pairs(),
+                    (long long)M);
+    if (key_bits < 1 || key_bits > 64) return fail(GSR_EINVAL, "%s: key_bits must be in 1..64", fn);
+    if (M <= 1) return GSR_OK;
+    GSR_NEED(keys); GSR_NEED(ids); GSR_NEED(keys_alt); GSR_NEED(ids_alt);
+    return launch_sort_pairs_static(M, key_bits, keys, ids, keys_alt, ids_alt, (hipStream_t)stream);
+}
+
 int gsr_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_t *ranges, gsr_stream_t stream) {
     static const char *fn = "gsr_tile_ranges";
     if (M < 0 || M >= (int64_t)INT32_MAX || total_tiles < 0) return fail(GSR_EINVAL, "%s: bad sizes", fn);

@@ -80,6 +80,9 @@ int launch_intersect_emit(const gsr_params &p, const CamTable &cams, int N, cons
                           uint64_t *keys, int32_t *ids, hipStream_t s);
 
 size_t sort_workspace_bytes(int64_t M);
+int64_t sort_static_max_pairs();
+int launch_sort_pairs_static(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uint64_t *keys_alt,
+                             int32_t *ids_alt, hipStream_t s);
 int launch_sort_pairs(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uint64_t *keys_alt,
                       int32_t *ids_alt, void *ws, hipStream_t s);
 int launch_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_t *ranges, hipStream_t s);

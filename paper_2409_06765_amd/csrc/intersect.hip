@@ -12,6 +12,8 @@
 //    the result (tile, depth bits, id) order, identical bit for bit.
 // Prefix sums and sorts use reduce-then-scan (no inter-block waiting), so
 // every kernel finishes whatever the order in which blocks are scheduled.
+#include <mutex>
+
 #include "common.hpp"
 
 #pragma clang fp contract(off)
@@ -836,11 +838,11 @@ __global__ void __launch_bounds__(kOrderThreads) order_scatter_kernel(int32_t T,
     }
 }
 
-size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-int hist_stride(int64_t nb) { return (int)((nb + 3) & ~(int64_t)3); }
+constexpr int hist_stride(int64_t nb) { return (int)((nb + 3) & ~(int64_t)3); }
 
-size_t radix_ws_bytes(int64_t M) {
+constexpr size_t radix_ws_bytes(int64_t M) {
     const int64_t nb = (M + kSortTile - 1) / kSortTile;
     return align256((size_t)kBins * (size_t)hist_stride(nb > 0 ? nb : 1) * sizeof(int32_t)) +
            align256(kBins * sizeof(int32_t));
@@ -1041,6 +1043,55 @@ size_t sort_workspace_bytes(int64_t M) { return radix_ws_bytes(M); }
 
 int launch_sort_pairs(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uint64_t *keys_alt,
                       int32_t *ids_alt, void *ws, hipStream_t s) {
+    return radix_sort<uint64_t>(M, key_bits, keys, ids, keys_alt, ids_alt, ws, s);
+}
+
+// ---- the sort without a workspace argument ------------------------------------
+// For callers that cannot allocate (graph capture, serving loops): the digit
+// histograms and totals live in a file-scope device array, one copy per GPU,
+// sized for kStaticSortMax pairs (16 MiB + 1 KiB).  Its device address is
+// looked up once per device, with that device current, and kept; host code
+// hands the kernels that address, never the array's own (host-side) name.
+// Every slot the sort reads is first written by the same call's kernels
+// (histograms by radix_hist_kernel, totals by radix_rowscan_kernel), so
+// nothing needs clearing; calls that overlap on one GPU share the array and
+// race.
+namespace {
+constexpr int64_t kStaticSortMax = (int64_t)1 << 25;
+constexpr size_t kStaticSortBytes = radix_ws_bytes(kStaticSortMax);
+constexpr int kStaticDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticSortBytes];
+void *g_scratch[kStaticDevices];
+std::mutex g_scratch_mu;
+
+int static_scratch(void **ptr) {
+    int dev = -1;
+    int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (rc != GSR_OK) return rc;
+    if (dev < 0 || dev >= kStaticDevices) return fail(GSR_EINVAL, "device %d beyond the %d supported", dev, kStaticDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        rc = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (rc != GSR_OK) return rc;
+        if (!p) return fail(GSR_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch[dev] = p;
+    }
+    *ptr = g_scratch[dev];
+    return GSR_OK;
+}
+}  // namespace
+
+int64_t sort_static_max_pairs() { return kStaticSortMax; }
+
+int launch_sort_pairs_static(int64_t M, int key_bits, uint64_t *keys, int32_t *ids, uint64_t *keys_alt,
+                             int32_t *ids_alt, hipStream_t s) {
+    if (M > kStaticSortMax) return fail(GSR_EINVAL, "%lld pairs exceed the %lld of the static sort", (long long)M,
+                                        (long long)kStaticSortMax);
+    void *ws = nullptr;
+    const int rc = static_scratch(&ws);
+    if (rc != GSR_OK) return rc;
+    static_assert(radix_ws_bytes(kStaticSortMax) <= kStaticSortBytes, "static sort space too small");
     return radix_sort<uint64_t>(M, key_bits, keys, ids, keys_alt, ids_alt, ws, s);
 }
 

@@ -98,6 +98,11 @@ def test_sort_and_workspace_validation(L):
     assert lib.gsr_sort_pairs(100, 65, fake, fake, fake, fake, fake, 1 << 20, None) == L.GSR_EINVAL
     assert lib.gsr_sort_pairs(100_000, 40, fake, fake, fake, fake, fake, 16, None) == L.GSR_EWORKSPACE
     assert lib.gsr_sort_pairs(1, 40, None, None, None, None, None, 0, None) == L.GSR_OK
+    # the scratch-free sort checks its size limit before it looks up its device array
+    assert lib.gsr_sort_pairs_noalloc((1 << 25) + 1, 40, fake, fake, fake, fake, None) == L.GSR_EINVAL
+    assert "0..33554432" in lib.gsr_last_error().decode()
+    assert lib.gsr_sort_pairs_noalloc(100, 0, fake, fake, fake, fake, None) == L.GSR_EINVAL
+    assert lib.gsr_sort_pairs_noalloc(1, 40, None, None, None, None, None) == L.GSR_OK
     p = L.default_params()
     W = (ctypes.c_int32 * 1)(64)
     assert lib.gsr_intersect_count(ctypes.byref(p), 1, 5000, W, W, fake, fake, fake, fake, fake, None, fake, 8,
