@@ -367,13 +367,15 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
     const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
     const int nslots = want_abs ? 11 : 9;
     float *dst_base = nullptr;
-    int dst_mul = 0;
+    uint32_t dst_stride = 0;      // bytes between consecutive Gaussians' values of this lane's output
     bool dst_by_n = false;
-    if (lane < 2) { dst_base = a.v_means2d + lane; dst_mul = 2; }
-    else if (lane < 5) { dst_base = a.v_conics + (lane - 2); dst_mul = 3; }
-    else if (lane < 8) { dst_base = a.v_colors + (lane - 5); dst_mul = 3; dst_by_n = a.p.colors_shared != 0; }
-    else if (lane == 8) { dst_base = a.v_opac; dst_mul = 1; }
-    else if (lane < 11 && want_abs) { dst_base = a.v_means2d_abs + (lane - 9); dst_mul = 2; }
+    if (lane < 2) { dst_base = a.v_means2d + lane; dst_stride = 8; }
+    else if (lane < 5) { dst_base = a.v_conics + (lane - 2); dst_stride = 12; }
+    else if (lane < 8) { dst_base = a.v_colors + (lane - 5); dst_stride = 12; dst_by_n = a.p.colors_shared != 0; }
+    else if (lane == 8) { dst_base = a.v_opac; dst_stride = 4; }
+    else if (lane < 11 && want_abs) { dst_base = a.v_means2d_abs + (lane - 9); dst_stride = 8; }
+    const bool dst_lane = lane < nslots && dst_base != nullptr;
+    const uint64_t dst_addr = (uint64_t)dst_base;
     const int cam_base = c * a.N;
     // lanes 2, 4: dL/da, dL/dc are half the dx^2, dy^2 moments; lanes 9, 10: |dL/dmu'| carries log2(e)
     const float lscale = (lane == 2 || lane == 4) ? 0.5f : (lane == 9 || lane == 10) ? 1.0f / kLog2e : 1.0f;
@@ -428,13 +430,15 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
                 any = true;
                 const float inv = __builtin_amdgcn_rcpf(1.0f - al);
                 const float Tk = T[q] * inv;
-                const float wgt = use ? al * Tk : 0.0f;
                 const float cv = (col.x * vC[q][0] + col.y * vC[q][1]) + col.z * vC[q][2];
-                float v_al = fmaf(Tk, cv, inv * (vATf[q] - SV[q]));
+                const float v_al = fmaf(Tk, cv, inv * (vATf[q] - SV[q]));
+                // lanes that do not composite the entry (and clamped alphas: no gradient to o or sigma) get
+                // zero weights through selects, so the wave never branches on them
+                const float wgt = use ? al * Tk : 0.0f;
+                const float m_sig = (use && araw <= amax) ? -araw : 0.0f;
                 SV[q] = fmaf(wgt, cv, SV[q]);
                 T[q] = use ? Tk : T[q];
-                v_al = (use && araw <= amax) ? v_al : 0.0f;       // clamped alpha: no gradient to o or sigma
-                const float v_sig = -araw * v_al;
+                const float v_sig = m_sig * v_al;
                 const float t = v_sig * dx, sy = v_sig * dy;
                 acc[0] += t;
                 acc[1] += sy;
@@ -478,12 +482,11 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
             const float sc = fmaf(con.y, sdy, sdx);
             const float mean = (lane == 0 ? con.x * sc : fmaf(con.x * con.y, sc, con.z * sdy)) * (2.0f / kLog2e);
             const float val = lane < 2 ? mean : y * (lane == 8 ? -__builtin_amdgcn_rcpf(xyo.z) : lscale);
-            if (lane < nslots && dst_base) {
-                const int g = __builtin_amdgcn_readfirstlane(s_id[e]);   // uniform: scalar index arithmetic
-                int n = g - cam_base;
-                if ((unsigned)n >= (unsigned)a.N) n = 0;   // only a bad id can leave the tile's camera
-                unsafeAtomicAdd(dst_base + (int64_t)(dst_by_n ? n : g) * dst_mul, val);
-            }
+            const int g = __builtin_amdgcn_readfirstlane(s_id[e]);   // uniform: scalar index arithmetic
+            int n = g - cam_base;
+            if ((unsigned)n >= (unsigned)a.N) n = 0;   // only a bad id can leave the tile's camera
+            const uint32_t gi = dst_by_n ? (uint32_t)n : (uint32_t)g;
+            if (dst_lane) unsafeAtomicAdd((float *)(dst_addr + (uint64_t)gi * dst_stride), val);
         }
         __syncthreads();
     }
