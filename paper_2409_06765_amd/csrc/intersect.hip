@@ -6,12 +6,17 @@
 //    (camera, Gaussian, row-major tile) order, stably radix-sorted on all
 //    key bits;
 //  * the binning path used by the pipeline: the projected Gaussians are
-//    first stably sorted by depth bits (C*N 32-bit keys), their tiles are then
-//    emitted in that order with 32-bit tile keys, and a stable sort on the
-//    tile bits alone (two passes at 1080p) finishes the job.  Stability makes
-//    the result (tile, depth bits, id) order, identical bit for bit.
+//    first stably sorted by depth bits (C*N 32-bit keys; the first pass
+//    also drops the Gaussians of no tiles, so the later passes and
+//    everything after them see only the visible ones), their tiles are then
+//    emitted in that order with 32-bit tile keys (each emit block also
+//    counts the first tile-bit digits of its slots, the histogram the sort's
+//    first pass needs), and a stable sort on the tile bits alone (two passes
+//    at 1080p) finishes the job.  Stability makes the result (tile, depth
+//    bits, id) order, identical bit for bit.
 // Prefix sums and sorts use reduce-then-scan (no inter-block waiting), so
 // every kernel finishes whatever the order in which blocks are scheduled.
+#include <algorithm>
 #include <mutex>
 
 #include "common.hpp"
@@ -20,6 +25,10 @@
 
 namespace gsr {
 namespace {
+
+// Keys equal to kDropKey (all ones, 32-bit keys) are left out of a sort pass
+// run with drop set: the pass then also compacts, writing only the other pairs.
+constexpr uint32_t kDropKey = 0xFFFFFFFFu;
 
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
@@ -166,18 +175,24 @@ __global__ void __launch_bounds__(kScanThreads) block_sums_kernel(int64_t n_tota
 
 // The counts gathered into depth order (counts_sorted[i] = counts[order[i]])
 // and their per-block sums, in one pass.
+// Positions at or past *n_kept (the Gaussians the depth order kept) become
+// entries of no tiles, their order set to Gaussian 0.
 __global__ void __launch_bounds__(kScanThreads) gather_block_sums_kernel(int64_t n_total,
-        const int32_t *__restrict__ order, const int32_t *__restrict__ counts, int32_t *__restrict__ counts_sorted,
-        int64_t *__restrict__ block_sums) {
+        const int64_t *__restrict__ n_kept, int32_t *__restrict__ order, const int32_t *__restrict__ counts,
+        int32_t *__restrict__ counts_sorted, int64_t *__restrict__ block_sums) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const int64_t kept = min(n_total, *n_kept);
     int64_t local = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; i++) {
-        if (base + i < n_total) {
+        if (base + i < kept) {
             const int32_t g = order[base + i];
             const int32_t c = (g >= 0 && g < n_total) ? counts[g] : 0;
             counts_sorted[base + i] = c;
             local += c;
+        } else if (base + i < n_total) {
+            order[base + i] = 0;
+            counts_sorted[base + i] = 0;
         }
     }
     int64_t total;
@@ -241,6 +256,7 @@ __global__ void __launch_bounds__(kScanThreads) offsets_kernel(int64_t n_total, 
 // staged in LDS and written out coalesced.  Keys are tile << 32 | depth bits
 // (uint64) or the tile id alone (uint32).
 constexpr int kEmitThreads = 256;
+constexpr int kBinsEmit = 256;      // the radix sort's digit bins (one per thread of an emit block)
 constexpr int kEmitChunk = 512;
 constexpr int kEmitRows = 256;
 
@@ -280,7 +296,8 @@ template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N, int64_t n_total,
         const float *__restrict__ means2d, const int32_t *__restrict__ radii, const float *__restrict__ depths,
         CullIn cull, const int32_t *__restrict__ order, const int64_t *__restrict__ offsets, int64_t cap,
-        const int64_t *__restrict__ count_dev, K *__restrict__ keys, int32_t *__restrict__ ids) {
+        const int64_t *__restrict__ count_dev, K *__restrict__ keys, int32_t *__restrict__ ids,
+        int32_t *__restrict__ hist, int hist_bits, int hist_stride) {
     constexpr int kWaves = kEmitThreads / kWave;
     const int64_t total = count_dev ? *count_dev : cap;   // end of the last entry
     cap = min(cap, total);                       // capacity mode: the true count lives on the device
@@ -293,8 +310,9 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
     __shared__ int32_t s_oid[kWaves][kEmitChunk];
     const int lane = __lane_id(), w = threadIdx.x / kWave;
     const int64_t c0 = ((int64_t)blockIdx.x * kWaves + w) * kEmitChunk;
-    if (c0 >= cap) return;                       // wave-uniform
+    const bool active = c0 < cap;                // wave-uniform
     const int64_t c1 = min(c0 + (int64_t)kEmitChunk, cap);
+    if (active) {
     int64_t s = owner_search(offsets, n_total, c0);
     int r0 = 0;                                  // rows of entry s emitted by earlier windows
     int64_t so = 0;                              // and their slots
@@ -437,6 +455,20 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
         keys[c0 + i] = s_okey[w][i];
         ids[c0 + i] = s_oid[w][i];
     }
+    }
+    if (hist) {
+        // the block's slots are one tile of the radix sort that follows: its histogram of the first
+        // pass's digits (the low hist_bits bits), as radix_hist_kernel would count them
+        __shared__ int32_t s_hist[kBinsEmit];
+        s_hist[threadIdx.x] = 0;
+        __syncthreads();
+        if (active) {
+            const uint32_t mask = (1u << hist_bits) - 1u;
+            for (int i = lane; i < (int)(c1 - c0); i += kWave) atomicAdd(&s_hist[(uint32_t)s_okey[w][i] & mask], 1);
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < (1 << hist_bits)) hist[(int64_t)threadIdx.x * hist_stride + blockIdx.x] = s_hist[threadIdx.x];
+    }
 }
 
 int64_t emit_blocks(int64_t cap) {
@@ -480,16 +512,16 @@ __global__ void ranges_kernel(int64_t M, const int64_t *__restrict__ count_dev, 
 }
 
 // ---- binning-path helpers -------------------------------------------------------
-// Depth-sort keys of the projected Gaussians (culled ones last) and their counts.
+// Depth-sort keys of the projected Gaussians and their counts; a Gaussian of
+// no tiles gets kDropKey, which the first sort pass leaves out.
 __global__ void __launch_bounds__(256) bin_keys_kernel(CamTable cams, int N, int64_t n_total,
         const float *__restrict__ means2d, const int32_t *__restrict__ radii, const float *__restrict__ depths,
-        CullIn cull, int32_t *__restrict__ counts, uint32_t *__restrict__ dkeys, int32_t *__restrict__ dvals) {
+        CullIn cull, int32_t *__restrict__ counts, uint32_t *__restrict__ dkeys) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_total) return;
     const int k = gauss_tile_count(gauss_tiles(cams, N, g, means2d, radii, cull));
     counts[g] = k;
-    dkeys[g] = k > 0 ? __float_as_uint(depths[g]) : 0xFFFFFFFFu;
-    dvals[g] = (int32_t)g;
+    dkeys[g] = k > 0 ? __float_as_uint(depths[g]) : kDropKey;
 }
 
 // 64-bit keys of the sorted lists (only when a caller asks for them).
@@ -529,10 +561,11 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, uint64_t a
     return m;
 }
 
+
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K *__restrict__ keys, int64_t M,
         const int64_t *__restrict__ count_dev, int shift, int bits, int nblocks, int stride,
-        int32_t *__restrict__ hist) {
+        int32_t *__restrict__ hist, int drop) {
     __shared__ int32_t cnt[kBins];
     if (count_dev) M = min(M, *count_dev);      // blocks past the count write zero histograms
     cnt[threadIdx.x] = 0;
@@ -542,8 +575,9 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K *__res
 #pragma unroll
     for (int i = 0; i < kSortItems; i++) {
         const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
-        const bool valid = idx < M;
-        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & mask : 0u;
+        const K kv = idx < M ? keys[idx] : (K)0;
+        const bool valid = idx < M && !(drop && (uint64_t)kv == kDropKey);
+        const uint32_t d = valid ? (uint32_t)(kv >> shift) & mask : 0u;
         const uint64_t active = __ballot(valid);
         const uint64_t peers = match_digit(d, bits, active);
         if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&cnt[d], (int32_t)__popcll(peers));
@@ -593,17 +627,21 @@ __global__ void __launch_bounds__(kScanThreads) radix_rowscan_kernel(int32_t *__
     if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
+// ids_in NULL: the ids are the input positions.  drop: pairs with kDropKey
+// are left out, and block 0 writes the number of pairs kept to kept_out.
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__restrict__ keys_in,
         const int32_t *__restrict__ ids_in, K *__restrict__ keys_out, int32_t *__restrict__ ids_out,
         int64_t M, const int64_t *__restrict__ count_dev, int shift, int bits, int nblocks, int stride,
-        const int32_t *__restrict__ hist, const int32_t *__restrict__ digit_tot) {
+        const int32_t *__restrict__ hist, const int32_t *__restrict__ digit_tot, int drop,
+        int64_t *__restrict__ kept_out) {
     if (count_dev) M = min(M, *count_dev);
     __shared__ K s_keys[kSortTile];
     __shared__ int32_t s_ids[kSortTile];
     __shared__ int32_t s_wcnt[kSortWaves][kBins];
     __shared__ int32_t s_dstart[kBins];
     __shared__ int32_t s_gout[kBins];
+    __shared__ int32_t s_nkept;
     const int t = threadIdx.x, lane = __lane_id(), w = t / kWave;
     const uint32_t mask = (1u << bits) - 1u;
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -614,6 +652,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__
         int32_t tot;
         const int32_t before = block_exclusive_scan<int32_t>(used ? digit_tot[t] : 0, tot);
         s_gout[t] = before + (used ? hist[(int64_t)t * stride + blockIdx.x] : 0);
+        if (kept_out && blockIdx.x == 0 && t == 0) *kept_out = tot;
     }
 #pragma unroll
     for (int k = 0; k < kSortWaves; k++) s_wcnt[k][t] = 0;
@@ -627,9 +666,9 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__
 #pragma unroll
     for (int i = 0; i < kSortItems; i++) {
         const int64_t idx = base + (int64_t)w * (kWave * kSortItems) + i * kWave + lane;
-        const bool valid = idx < M;
-        key[i] = valid ? keys_in[idx] : (K)0;
-        val[i] = valid ? ids_in[idx] : 0;
+        key[i] = idx < M ? keys_in[idx] : (K)0;
+        const bool valid = idx < M && !(drop && (uint64_t)key[i] == kDropKey);
+        val[i] = valid ? (ids_in ? ids_in[idx] : (int32_t)idx) : 0;
         const uint32_t d = (uint32_t)(key[i] >> shift) & mask;
         const uint64_t active = __ballot(valid);
         const uint64_t peers = match_digit(d, bits, active);
@@ -648,6 +687,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__
         for (int k = 0; k < kSortWaves; k++) { c[k] = s_wcnt[k][t]; s_wcnt[k][t] = run; run += c[k]; }
         int32_t tot;
         s_dstart[t] = block_exclusive_scan<int32_t>(run, tot);
+        if (t == 0) s_nkept = tot;
     }
     __syncthreads();
 #pragma unroll
@@ -662,7 +702,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__
         }
     }
     __syncthreads();
-    const int n_valid = (int)((M - base) < kSortTile ? (M - base) : kSortTile);   // <= 0 past the count
+    const int n_valid = s_nkept;                 // pairs of this block kept (0 past the count)
     for (int j = t; j < n_valid; j += kSortThreads) {
         const K k = s_keys[j];
         const uint32_t d = (uint32_t)(k >> shift) & mask;
@@ -684,7 +724,8 @@ constexpr int kSmallWaves = kSmallThreads / kWave;
 
 __global__ void __launch_bounds__(kSmallThreads) radix_sort_small_kernel(uint32_t *__restrict__ keys,
                                                                          int32_t *__restrict__ ids, int M,
-                                                                         int key_bits) {
+                                                                         int key_bits, int iota,
+                                                                         int64_t *__restrict__ kept_out) {
     __shared__ uint32_t s_keys[kSmallSort];
     __shared__ int32_t s_ids[kSmallSort];
     __shared__ int32_t s_wcnt[kSmallWaves][kBins];
@@ -699,8 +740,9 @@ __global__ void __launch_bounds__(kSmallThreads) radix_sort_small_kernel(uint32_
     for (int i = 0; i < kSmallItems; i++) {
         const int idx = w * (kWave * kSmallItems) + i * kWave + lane;
         key[i] = idx < M ? keys[idx] : 0u;
-        val[i] = idx < M ? ids[idx] : 0;
+        val[i] = idx < M ? (iota ? idx : ids[idx]) : 0;
     }
+    if (kept_out && t == 0) *kept_out = M;        // every pair kept (dropped keys sort last)
     for (int shift = 0; shift < key_bits; shift += 8) {
         const int bits = min(8, key_bits - shift);
         const uint32_t mask = (1u << bits) - 1u;
@@ -851,13 +893,21 @@ constexpr size_t radix_ws_bytes(int64_t M) {
 // Sorts M pairs by the low key_bits bits; an even number of passes leaves
 // the result in keys/ids.  count_dev (nullable): the true number of pairs,
 // at most M, read on the device (the grids are sized for M).
+// kept (with 32-bit keys, count_dev NULL): the first pass leaves out the
+// pairs whose key is kDropKey, takes the ids from the input positions (ids is
+// not read), and writes the number of pairs kept to *kept; later passes sort
+// those alone, and the result is in keys/ids [0, *kept).  A sort small enough
+// for one block keeps every pair (the dropped keys sort last) and writes M.
+// hist0_ready: the first pass's block histograms are already in the
+// workspace (written by the kernel that produced the keys).
 template <typename K>
 int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int32_t *ids_alt, void *ws,
-               hipStream_t s, const int64_t *count_dev = nullptr) {
-    if (M <= 1) return GSR_OK;
+               hipStream_t s, const int64_t *count_dev = nullptr, int64_t *kept = nullptr, bool hist0_ready = false) {
+    if (kept && M == 0) return launch_fill_zero(kept, sizeof(int64_t), s);
+    if (M <= 1 && !kept) return GSR_OK;
     if constexpr (sizeof(K) == 4) {
         if (!count_dev && M <= kSmallSort) {   // the whole sort in one block
-            radix_sort_small_kernel<<<1, kSmallThreads, 0, s>>>(keys, ids, (int)M, key_bits);
+            radix_sort_small_kernel<<<1, kSmallThreads, 0, s>>>(keys, ids, (int)M, key_bits, kept ? 1 : 0, kept);
             return launch_check("radix_sort");
         }
     }
@@ -875,10 +925,14 @@ int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int3
         int bits = key_bits - shift;
         if (bits > width) bits = width;
         if (bits < 0) bits = 0;   // a padding pass: every digit 0, a stable copy
-        radix_hist_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, M, count_dev, shift, bits, nb, stride, hist);
+        const int drop = kept && ps == 0;
+        const int64_t *cnt = kept && ps > 0 ? kept : count_dev;
+        if (!(hist0_ready && ps == 0))
+            radix_hist_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, M, cnt, shift, bits, nb, stride, hist, drop);
         radix_rowscan_kernel<<<1 << bits, kScanThreads, 0, s>>>(hist, nb, stride, dtot);
-        radix_scatter_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, iin, kout, iout, M, count_dev, shift, bits, nb,
-                                                           stride, hist, dtot);
+        radix_scatter_kernel<K><<<nb, kSortThreads, 0, s>>>(kin, drop ? nullptr : iin, kout, iout, M, cnt, shift,
+                                                           bits, nb, stride, hist, dtot, drop,
+                                                           drop ? kept : nullptr);
         K *tk = kin; kin = kout; kout = tk;
         int32_t *ti = iin; iin = iout; iout = ti;
     }
@@ -887,6 +941,7 @@ int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int3
 
 // Binning workspace layout: prepare part (C*N sized, kept until finish).
 struct BinPrep {
+    int64_t *kept;           // [1] projected Gaussians with at least one tile
     int32_t *counts;         // [n] tiles per projected Gaussian
     uint32_t *dkeys, *dkeys_alt;
     int32_t *order, *order_alt;   // depth order of the projected Gaussians
@@ -902,6 +957,7 @@ BinPrep carve_prep(void *ws, int64_t n) {
     char *p = (char *)ws;
     auto take = [&](size_t bytes) { void *q = p; p += align256(bytes); return q; };
     const size_t nn = (size_t)(n > 0 ? n : 1);
+    b.kept = (int64_t *)take(8);
     b.counts = (int32_t *)take(nn * 4);
     b.dkeys = (uint32_t *)take(nn * 4);
     b.dkeys_alt = (uint32_t *)take(nn * 4);
@@ -919,8 +975,8 @@ BinPrep carve_prep(void *ws, int64_t n) {
 size_t prep_bytes(int64_t n) {
     const size_t nn = (size_t)(n > 0 ? n : 1);
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    return 6 * align256(nn * 4) + align256(nn * 8) + align256((size_t)(nb > 0 ? nb : 1) * 8) + align256(8) +
-           radix_ws_bytes(n);
+    return align256(8) + 6 * align256(nn * 4) + align256(nn * 8) + align256((size_t)(nb > 0 ? nb : 1) * 8) +
+           align256(8) + radix_ws_bytes(n);
 }
 
 struct BinFin {
@@ -986,7 +1042,7 @@ int launch_intersect_emit(const gsr_params &p, const CamTable &cams, int N, cons
     const CullIn none{nullptr, nullptr, nullptr, 0.0f, 0};   // this route keeps whole rectangles
     emit_kernel<uint64_t><<<dim3((unsigned)nb), dim3(kEmitThreads), 0, s>>>(cams, N, n, means2d, radii, depths,
                                                                            none, nullptr, offsets, cap, nullptr, keys,
-                                                                           ids);
+                                                                           ids, nullptr, 0, 0);
     return launch_check("intersect_emit");
 }
 
@@ -1124,13 +1180,14 @@ int launch_bin_prepare(const gsr_params &p, const CamTable &cams, int N, const f
     }
     const unsigned nb = (unsigned)((n + 255) / 256);
     bin_keys_kernel<<<nb, 256, 0, s>>>(cams, N, n, means2d, radii, depths, cull_inputs(p, conics, opacities, comps),
-                                       b.counts, b.dkeys, b.order);
-    int rc = radix_sort<uint32_t>(n, 32, b.dkeys, b.order, b.dkeys_alt, b.order_alt, b.sort_ws, s);
+                                       b.counts, b.dkeys);
+    // the depth order of the Gaussians that have tiles (the first pass drops the others)
+    int rc = radix_sort<uint32_t>(n, 32, b.dkeys, b.order, b.dkeys_alt, b.order_alt, b.sort_ws, s, nullptr, b.kept);
     if (rc != GSR_OK) return rc;
     // gather + block sums, then the scan of the block sums, which writes the count into the workspace
     // and, when asked, into total_dev (no copy node), then the offsets
     const int64_t nbs = (n + kScanTile - 1) / kScanTile;
-    gather_block_sums_kernel<<<dim3((unsigned)nbs), dim3(kScanThreads), 0, s>>>(n, b.order, b.counts,
+    gather_block_sums_kernel<<<dim3((unsigned)nbs), dim3(kScanThreads), 0, s>>>(n, b.kept, b.order, b.counts,
                                                                              b.counts_sorted, b.block_sums);
     scan_sums_kernel<<<1, kScanThreads, 0, s>>>(b.block_sums, nbs, b.total, total_dev);
     offsets_kernel<<<dim3((unsigned)nbs), dim3(kScanThreads), 0, s>>>(n, b.counts_sorted, b.block_sums,
@@ -1148,12 +1205,20 @@ int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const fl
     int rc = launch_fill_zero(ranges, (size_t)cams.total_tiles * 2 * sizeof(int32_t), s);
     if (rc != GSR_OK || n == 0 || M == 0) return rc;
     const int64_t ne = emit_blocks(M);
+    const int tile_bits = cams.total_tiles > 1 ? 32 - __builtin_clz((unsigned)(cams.total_tiles - 1)) : 1;
+    // the sort's first-pass digit width (as radix_sort splits tile_bits) and histogram layout: each emit block
+    // fills one sort tile, so it counts that tile's first digits on the way
+    static_assert(kEmitChunk * (kEmitThreads / kWave) == kSortTile, "an emit block fills one sort tile");
+    int passes = (tile_bits + 7) / 8;
+    if (passes % 2) passes++;
+    const int width0 = std::min((tile_bits + passes - 1) / passes, tile_bits);
+    const bool fuse = M > 1;
     // M is the capacity; the true count (b.total, from the prepare step) is read on the device
     emit_kernel<uint32_t><<<dim3((unsigned)ne), dim3(kEmitThreads), 0, s>>>(
         cams, N, n, means2d, radii, depths, cull_inputs(p, conics, opacities, comps), b.order, b.offsets_sorted, M,
-        b.total, f.tkeys, ids);
-    const int tile_bits = cams.total_tiles > 1 ? 32 - __builtin_clz((unsigned)(cams.total_tiles - 1)) : 1;
-    rc = radix_sort<uint32_t>(M, tile_bits, f.tkeys, ids, f.tkeys_alt, f.ids_alt, f.sort_ws, s, b.total);
+        b.total, f.tkeys, ids, fuse ? (int32_t *)f.sort_ws : nullptr, width0, hist_stride(ne));
+    rc = radix_sort<uint32_t>(M, tile_bits, f.tkeys, ids, f.tkeys_alt, f.ids_alt, f.sort_ws, s, b.total, nullptr,
+                              fuse);
     if (rc != GSR_OK) return rc;
     ranges_kernel<uint32_t><<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, b.total, f.tkeys,
                                                                                   cams.total_tiles, ranges);
