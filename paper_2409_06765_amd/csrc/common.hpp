@@ -240,6 +240,13 @@ __device__ __forceinline__ uint32_t quad_mask(float mx, float my, float hx, floa
 // directly (scaled_sigma), the argument of the hardware base-2 exponential;
 // alpha >= alpha_min exactly where log2(e) sigma <= log2(opacity / alpha_min).
 constexpr float kLog2e = 1.4426950408889634f;
+
+// The default skip, clamp and stop thresholds (gsr_default_params); kernels
+// specialised for them take the values as constants.
+constexpr float kStdAlphaMin = 1.0f / 255.0f, kStdAlphaMax = 0.99f, kStdTMin = 1e-4f;
+inline bool standard_thresholds(const gsr_params &p) {
+    return p.alpha_min == kStdAlphaMin && p.alpha_max == kStdAlphaMax && p.T_min == kStdTMin;
+}
 constexpr double kLog2eD = 1.4426950408889634074;
 
 // min(alpha, alpha_max) for a non-NaN alpha in one instruction: the median of

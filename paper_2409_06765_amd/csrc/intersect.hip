@@ -115,6 +115,30 @@ __device__ __forceinline__ GaussTiles gauss_tiles(const CamTable &cams, int N, i
     return t;
 }
 
+// What the key emission needs of a projected Gaussian with tiles, packed by
+// bin_keys_kernel into one 32-byte record so that the emission, which visits
+// the Gaussians in depth order, gathers one record instead of five arrays:
+// {mean x, mean y, conic a, conic b}, {conic c, opacity (times the
+// compensation), radius (int bits), -}.
+struct BinRec {
+    float4 a;
+    float4 b;
+};
+
+__device__ __forceinline__ GaussTiles gauss_tiles_rec(const CamTable &cams, int N, int64_t g, const BinRec &r,
+                                                      const CullIn &ci) {
+    GaussTiles t;
+    t.x0 = t.x1 = t.y0 = t.y1 = 0;
+    t.cull.mode = 1;
+    const int rad = __float_as_int(r.b.z);
+    if (rad <= 0) return t;
+    const int c = (int)(g / N);
+    tile_rect(r.a.x, r.a.y, rad, cams.cam[c].TX, cams.cam[c].TY, t.x0, t.x1, t.y0, t.y1);
+    if (!(t.x1 > t.x0 && t.y1 > t.y0)) { t.x1 = t.x0; t.y1 = t.y0; return t; }
+    if (ci.on) t.cull = tile_cull_setup(r.a.x, r.a.y, r.a.z, r.a.w, r.b.x, r.b.y, ci.alpha_min, rad);
+    return t;
+}
+
 // Tiles of a Gaussian: the rectangle's area, or the sum of its rows' runs.
 __device__ __forceinline__ int gauss_tile_count(const GaussTiles &t) {
     if (t.cull.mode == 1) return (t.x1 - t.x0) * (t.y1 - t.y0);
@@ -297,7 +321,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
         const float *__restrict__ means2d, const int32_t *__restrict__ radii, const float *__restrict__ depths,
         CullIn cull, const int32_t *__restrict__ order, const int64_t *__restrict__ offsets, int64_t cap,
         const int64_t *__restrict__ count_dev, K *__restrict__ keys, int32_t *__restrict__ ids,
-        int32_t *__restrict__ hist, int hist_bits, int hist_stride) {
+        int32_t *__restrict__ hist, int hist_bits, int hist_stride, const BinRec *__restrict__ recs) {
     constexpr int kWaves = kEmitThreads / kWave;
     const int64_t total = count_dev ? *count_dev : cap;   // end of the last entry
     cap = min(cap, total);                       // capacity mode: the true count lives on the device
@@ -330,12 +354,12 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
             start = offsets[q] + (lane == 0 ? so : 0);
             const int64_t end = q + 1 < n_total ? offsets[q + 1] : total;
             if (end > start) {
-                t = gauss_tiles(cams, N, g, means2d, radii, cull);
+                t = recs ? gauss_tiles_rec(cams, N, g, recs[g], cull) : gauss_tiles(cams, N, g, means2d, radii, cull);
                 nr = t.y1 - t.y0 - (lane == 0 ? r0 : 0);
                 base = cams.cam[g / N].tile_base;
                 TX = cams.cam[g / N].TX;
             }
-            s_dbits[w][lane] = __float_as_uint(depths[g]);
+            if constexpr (sizeof(K) == 8) s_dbits[w][lane] = __float_as_uint(depths[g]);   // 32-bit keys: tile only
             s_g[w][lane] = (int32_t)g;
         }
         const int ry0 = t.y0 + (lane == 0 ? r0 : 0);   // first row of this lane's entry in the table
@@ -350,20 +374,16 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
         const int nfit = __popcll(__ballot(q < n_total && rb + nr <= kEmitRows));   // a prefix of the lanes
         const int take = lane < nfit ? nr : (lane == nfit ? max(0, min(nr, kEmitRows - rb)) : 0);
         const int nrows = __shfl(rb + take, min(nfit, kWave - 1), kWave);
-        // ---- the table's rows, four consecutive ones per lane: owner entry, tile run, length
+        // ---- the table's rows, four consecutive ones per lane: owner entry, tile run, length.  Each lane
+        // first marks its own rows with its lane index, so a row finds its owner with one LDS read
+        for (int r = 0; r < take; r++) s_rent[w][rb + r] = (uint8_t)lane;
+        wave_sync_lds();
         constexpr int kPer = kEmitRows / kWave;
         int len[kPer], tile[kPer], own[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; k++) {
             const int i = lane * kPer + k;
-            // owner: the last lane whose first row is <= i (rb is non-decreasing; a lane without rows
-            // shares its first row with the next lane, and every lane after the owner starts past i)
-            int lo = 0;
-#pragma unroll
-            for (int step = kWave / 2; step >= 1; step >>= 1) {
-                const int cand = lo + step;
-                if (__shfl(rb, cand, kWave) <= i) lo = cand;
-            }
+            const int lo = i < nrows ? (int)s_rent[w][i] : 0;
             own[k] = lo;
             GaussTiles ot;
             ot.x0 = __shfl(t.x0, lo, kWave);
@@ -404,7 +424,6 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
             if (i < nrows) {
                 s_rslot[w][i] = (int32_t)(wbeg - c0) + ex;     // may be negative: rows before the slice
                 s_rtile[w][i] = tile[k];
-                s_rent[w][i] = (uint8_t)own[k];
             }
             ex += len[k];
         }
@@ -499,29 +518,57 @@ __global__ void fill_zero_multi_kernel(FillList f) {
 template <typename K>
 __device__ __forceinline__ int32_t tile_of(K key) { return (int32_t)(sizeof(K) == 8 ? (uint64_t)key >> 32 : key); }
 
+// Each thread takes kRangeItems consecutive keys (and the one on each side).
+constexpr int kRangeItems = 8;
+
 template <typename K>
-__global__ void ranges_kernel(int64_t M, const int64_t *__restrict__ count_dev, const K *__restrict__ keys,
-                              int32_t total_tiles, int32_t *__restrict__ ranges) {
+__global__ void __launch_bounds__(256) ranges_kernel(int64_t M, const int64_t *__restrict__ count_dev,
+                                                     const K *__restrict__ keys, int32_t total_tiles,
+                                                     int32_t *__restrict__ ranges) {
     if (count_dev) M = min(M, *count_dev);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    const int32_t t = tile_of<K>(keys[i]);
-    if (t < 0 || t >= total_tiles) return;
-    if (i == 0 || tile_of<K>(keys[i - 1]) != t) ranges[2 * t] = (int32_t)i;
-    if (i == M - 1 || tile_of<K>(keys[i + 1]) != t) ranges[2 * t + 1] = (int32_t)(i + 1);
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeItems;
+    if (i0 >= M) return;
+    int32_t t[kRangeItems + 2];
+#pragma unroll
+    for (int k = 0; k < kRangeItems + 2; k++) {
+        const int64_t i = i0 - 1 + k;
+        t[k] = (i >= 0 && i < M) ? tile_of<K>(keys[i]) : -1;
+    }
+#pragma unroll
+    for (int k = 1; k <= kRangeItems; k++) {
+        const int64_t i = i0 - 1 + k;
+        const int32_t tk = t[k];
+        if (i >= M || tk < 0 || tk >= total_tiles) continue;
+        if (t[k - 1] != tk) ranges[2 * tk] = (int32_t)i;
+        if (t[k + 1] != tk) ranges[2 * tk + 1] = (int32_t)(i + 1);
+    }
 }
+
+int64_t range_blocks(int64_t M) { return (M + 256 * kRangeItems - 1) / (256 * kRangeItems); }
 
 // ---- binning-path helpers -------------------------------------------------------
 // Depth-sort keys of the projected Gaussians and their counts; a Gaussian of
 // no tiles gets kDropKey, which the first sort pass leaves out.
 __global__ void __launch_bounds__(256) bin_keys_kernel(CamTable cams, int N, int64_t n_total,
         const float *__restrict__ means2d, const int32_t *__restrict__ radii, const float *__restrict__ depths,
-        CullIn cull, int32_t *__restrict__ counts, uint32_t *__restrict__ dkeys) {
+        CullIn cull, int32_t *__restrict__ counts, uint32_t *__restrict__ dkeys, BinRec *__restrict__ recs) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_total) return;
     const int k = gauss_tile_count(gauss_tiles(cams, N, g, means2d, radii, cull));
     counts[g] = k;
     dkeys[g] = k > 0 ? __float_as_uint(depths[g]) : kDropKey;
+    if (k > 0) {
+        float o = 0.0f, ca = 0.0f, cb = 0.0f, cc = 0.0f;
+        if (cull.on) {
+            o = cull.opacities[g % N];
+            if (cull.comps) o *= cull.comps[g];
+            ca = cull.conics[3 * g]; cb = cull.conics[3 * g + 1]; cc = cull.conics[3 * g + 2];
+        }
+        BinRec r;
+        r.a = make_float4(means2d[2 * g], means2d[2 * g + 1], ca, cb);
+        r.b = make_float4(cc, o, __int_as_float(radii[g]), 0.0f);
+        recs[g] = r;
+    }
 }
 
 // 64-bit keys of the sorted lists (only when a caller asks for them).
@@ -941,6 +988,7 @@ int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int3
 
 // Binning workspace layout: prepare part (C*N sized, kept until finish).
 struct BinPrep {
+    BinRec *recs;            // [n] what the emission reads of each Gaussian with tiles
     int64_t *kept;           // [1] projected Gaussians with at least one tile
     int32_t *counts;         // [n] tiles per projected Gaussian
     uint32_t *dkeys, *dkeys_alt;
@@ -957,6 +1005,7 @@ BinPrep carve_prep(void *ws, int64_t n) {
     char *p = (char *)ws;
     auto take = [&](size_t bytes) { void *q = p; p += align256(bytes); return q; };
     const size_t nn = (size_t)(n > 0 ? n : 1);
+    b.recs = (BinRec *)take(nn * sizeof(BinRec));
     b.kept = (int64_t *)take(8);
     b.counts = (int32_t *)take(nn * 4);
     b.dkeys = (uint32_t *)take(nn * 4);
@@ -975,8 +1024,8 @@ BinPrep carve_prep(void *ws, int64_t n) {
 size_t prep_bytes(int64_t n) {
     const size_t nn = (size_t)(n > 0 ? n : 1);
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    return align256(8) + 6 * align256(nn * 4) + align256(nn * 8) + align256((size_t)(nb > 0 ? nb : 1) * 8) +
-           align256(8) + radix_ws_bytes(n);
+    return align256(nn * sizeof(BinRec)) + align256(8) + 6 * align256(nn * 4) + align256(nn * 8) +
+           align256((size_t)(nb > 0 ? nb : 1) * 8) + align256(8) + radix_ws_bytes(n);
 }
 
 struct BinFin {
@@ -1042,7 +1091,7 @@ int launch_intersect_emit(const gsr_params &p, const CamTable &cams, int N, cons
     const CullIn none{nullptr, nullptr, nullptr, 0.0f, 0};   // this route keeps whole rectangles
     emit_kernel<uint64_t><<<dim3((unsigned)nb), dim3(kEmitThreads), 0, s>>>(cams, N, n, means2d, radii, depths,
                                                                            none, nullptr, offsets, cap, nullptr, keys,
-                                                                           ids, nullptr, 0, 0);
+                                                                           ids, nullptr, 0, 0, nullptr);
     return launch_check("intersect_emit");
 }
 
@@ -1078,7 +1127,7 @@ int launch_fill_zero_multi(int n, void *const *ptrs, const size_t *bytes, hipStr
 int launch_tile_ranges(int64_t M, const uint64_t *keys, int32_t total_tiles, int32_t *ranges, hipStream_t s) {
     int rc = launch_fill_zero(ranges, (size_t)total_tiles * 2 * sizeof(int32_t), s);
     if (rc != GSR_OK || M == 0) return rc;
-    ranges_kernel<uint64_t><<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, nullptr, keys, total_tiles,
+    ranges_kernel<uint64_t><<<dim3((unsigned)range_blocks(M)), dim3(256), 0, s>>>(M, nullptr, keys, total_tiles,
                                                                                   ranges);
     return launch_check("tile_ranges");
 }
@@ -1180,7 +1229,7 @@ int launch_bin_prepare(const gsr_params &p, const CamTable &cams, int N, const f
     }
     const unsigned nb = (unsigned)((n + 255) / 256);
     bin_keys_kernel<<<nb, 256, 0, s>>>(cams, N, n, means2d, radii, depths, cull_inputs(p, conics, opacities, comps),
-                                       b.counts, b.dkeys);
+                                       b.counts, b.dkeys, b.recs);
     // the depth order of the Gaussians that have tiles (the first pass drops the others)
     int rc = radix_sort<uint32_t>(n, 32, b.dkeys, b.order, b.dkeys_alt, b.order_alt, b.sort_ws, s, nullptr, b.kept);
     if (rc != GSR_OK) return rc;
@@ -1216,11 +1265,11 @@ int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const fl
     // M is the capacity; the true count (b.total, from the prepare step) is read on the device
     emit_kernel<uint32_t><<<dim3((unsigned)ne), dim3(kEmitThreads), 0, s>>>(
         cams, N, n, means2d, radii, depths, cull_inputs(p, conics, opacities, comps), b.order, b.offsets_sorted, M,
-        b.total, f.tkeys, ids, fuse ? (int32_t *)f.sort_ws : nullptr, width0, hist_stride(ne));
+        b.total, f.tkeys, ids, fuse ? (int32_t *)f.sort_ws : nullptr, width0, hist_stride(ne), b.recs);
     rc = radix_sort<uint32_t>(M, tile_bits, f.tkeys, ids, f.tkeys_alt, f.ids_alt, f.sort_ws, s, b.total, nullptr,
                               fuse);
     if (rc != GSR_OK) return rc;
-    ranges_kernel<uint32_t><<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, b.total, f.tkeys,
+    ranges_kernel<uint32_t><<<dim3((unsigned)range_blocks(M)), dim3(256), 0, s>>>(M, b.total, f.tkeys,
                                                                                   cams.total_tiles, ranges);
     if (keys64)
         keys64_kernel<<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s>>>(M, b.total, f.tkeys, ids, depths, n,

@@ -314,6 +314,7 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
 // composited entry) are dropped from the batch's list at staging time.
 constexpr int kTileBatch = 64;
 
+template <bool kStd>
 __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, CamTable cams) {
     __shared__ float4 s_xyo[kTileBatch];
     __shared__ float4 s_con[kTileBatch];
@@ -333,7 +334,8 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
     // pixel centre of this lane in quad 0; quad q adds (8 (q & 1), 8 (q >> 1))
     const float px0 = tile_x0 + (float)(lane & 7) + 0.5f, py0 = tile_y0 + (float)(lane >> 3) + 0.5f;
     const int start = a.ranges[2 * tile];
-    const float amin = a.p.alpha_min, amax = a.p.alpha_max;
+    // kStd: the thresholds are the defaults, compiled in as constants
+    const float amin = kStd ? kStdAlphaMin : a.p.alpha_min, amax = kStd ? kStdAlphaMax : a.p.alpha_max;
 
     // per pixel (one per quad): T restored back to front, R = v_alpha final_T - S . v_C with S the colour
     // composited behind the current entry (background included), v_C, last index
@@ -531,8 +533,10 @@ int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D
             // SIMDs; then a block of four quad waves per tile finishes sooner
             if (cams.total_tiles < kFewTiles)
                 raster_bwd_kernel<4><<<grid, block, 0, s>>>(a, cams);
+            else if (standard_thresholds(p))
+                raster_bwd_rgb_kernel<true><<<grid, dim3(kWave), 0, s>>>(a, cams);
             else
-                raster_bwd_rgb_kernel<<<grid, dim3(kWave), 0, s>>>(a, cams);
+                raster_bwd_rgb_kernel<false><<<grid, dim3(kWave), 0, s>>>(a, cams);
             break;
         case 4: raster_bwd_kernel<4><<<grid, block, 0, s>>>(a, cams); break;
         case 8: raster_bwd_kernel<8><<<grid, block, 0, s>>>(a, cams); break;

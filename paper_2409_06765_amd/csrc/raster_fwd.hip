@@ -72,7 +72,7 @@ struct RasterArgs {
 // kCount: also count the entries each pixel evaluates and composites.
 // DM: channel capacity; DM = 3 takes RGB from the packed records, any other
 // DM stages a.Dt <= DM channels per entry into LDS.
-template <bool kCount, int DM>
+template <bool kCount, int DM, bool kStd>
 __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamTable cams) {
     constexpr bool kRGB = DM == 3;
     __shared__ float4 s_xyo[kBatch];   // mean x, mean y, opacity, -
@@ -96,7 +96,9 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     const float px = (float)xi + 0.5f, py = (float)yi + 0.5f;
     const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
     const int start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
-    const float amin = a.p.alpha_min, amax = a.p.alpha_max, tmin = a.p.T_min;
+    // kStd: the thresholds are the defaults, compiled in as constants (no per-entry canonicalisation)
+    const float amin = kStd ? kStdAlphaMin : a.p.alpha_min, amax = kStd ? kStdAlphaMax : a.p.alpha_max;
+    const float tmin = kStd ? kStdTMin : a.p.T_min;
 
     float T = 1.0f, Wacc = 0.0f, Cacc[DM];   // Wacc: sum of alpha T, the expected-depth normaliser
 #pragma unroll
@@ -217,8 +219,10 @@ int launch_rasterize_fwd(const gsr_params &p, const CamTable &cams, int N, int D
     RasterArgs a{p, N, CN, D, composited_channels(p, D), colors, depths, gauss, background, ranges, ids, tile_order,
                  image, alpha, final_T, last_ids, n_eval};
     const dim3 grid((unsigned)cams.total_tiles), block(kThreads);
-#define GSR_RF(DM) do { if (n_eval) raster_fwd_kernel<true, DM><<<grid, block, 0, s>>>(a, cams); \
-                        else raster_fwd_kernel<false, DM><<<grid, block, 0, s>>>(a, cams); } while (0)
+    const bool std_thr = standard_thresholds(p);
+#define GSR_RF(DM) do { if (n_eval) raster_fwd_kernel<true, DM, false><<<grid, block, 0, s>>>(a, cams); \
+                        else if (std_thr) raster_fwd_kernel<false, DM, true><<<grid, block, 0, s>>>(a, cams); \
+                        else raster_fwd_kernel<false, DM, false><<<grid, block, 0, s>>>(a, cams); } while (0)
     switch (channel_capacity(p, D)) {
         case 3: GSR_RF(3); break;
         case 4: GSR_RF(4); break;
