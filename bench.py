@@ -1,24 +1,28 @@
-"""Benchmark: forward + backward of the tile rasterizer, one view per step.
+"""Benchmark: forward + backward of the tile rasterizer over a batch of views per step.
 
 Workload (default): 1,000,000 Gaussians in 32 clusters with degree-3 SH,
 rendered at 1920x1080 (fx = fy = 1500) from 16 viewpoints on a radius-6
-sphere; a step is the whole hot path for one view: projection, tile binning
-(depth order, counts and scan, key emission, radix sort on the tile bits,
-tile ranges, dispatch order), forward compositing, backward compositing and
-the projection backward.  Every buffer of the step is allocated before the
-timed loop (pipeline.ViewPipeline); a step only enqueues library calls, and
-the intersection count stays on the device (the lists are built in a buffer
-sized from an untimed pass over the same views, and every step's count is
-checked after the loop), so the host never waits inside a step.  Inputs are
-resident in HBM before timing starts.
+sphere; a step is the whole hot path for a batch of consecutive views (4 by
+default, --views-per-step): projection, tile binning (depth order, counts
+and scan, key emission, radix sort on the tile bits, tile ranges, dispatch
+order), forward compositing, backward compositing and the projection
+backward, each one call over all the step's cameras, as the paper's
+rasterization call takes a batch of cameras (the projection backward sums
+the views' gradients per Gaussian).  Every buffer of the step is allocated
+before the timed loop (pipeline.ViewPipeline); a step only enqueues library
+calls, and the intersection count stays on the device (the lists are built
+in a buffer sized from an untimed pass over the same views, and every step's
+count is checked after the loop), so the host never waits inside a step.
+Inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  ms_per_step = wall-clock ms per forward+backward view
-(eager launches); value = forward + backward Gaussian-pixel evaluations the
-timed kernels execute, per second of wall time (counted exactly by an untimed
-pass of the same views); the paper-equivalent rate (every pixel walking its
+Prints one JSON line.  ms_per_step = wall-clock ms per step, ms_per_view =
+per view; value = forward + backward Gaussian-pixel evaluations the timed
+kernels execute, per second of wall time (counted exactly by an untimed pass
+of the same views); the paper-equivalent rate (every pixel walking its
 tile's whole 3-sigma list until it stops) is reported beside it, as are the
-per-view GPU times (median, p10, p90), the host time of each stage and the
-same step replayed as one captured HIP graph.
+same views one per step (one camera per call), the per-step GPU times
+(median, p10, p90), the host time of each stage and the step replayed as one
+captured HIP graph.
 """
 import argparse
 import json
@@ -62,7 +66,7 @@ WORKLOADS = {
 
 
 def measured_traffic(summary="raster_bwd_clusters1m_sh3_1080p_traffic.md", sources=("raster_bwd.hip", "common.hpp"),
-                     key="traffic_bytes_per_launch"):
+                     key="traffic_bytes_per_launch", views=None):
     """HBM bytes per launch of a kernel from its committed counter summary,
     or None when the kernel's sources have changed since the counters were
     taken (the summary records their sha256)."""
@@ -76,6 +80,10 @@ def measured_traffic(summary="raster_bwd_clusters1m_sh3_1080p_traffic.md", sourc
     h = re.search(r"^source_sha256: ([0-9a-f]{64})$", text, re.M)
     if not (t and h):
         return None
+    if views is not None:                     # the counters must be of a launch over as many views
+        vv = re.search(r"^views_per_launch: ([0-9]+)$", text, re.M)
+        if not vv or int(vv.group(1)) != views:
+            return None
     sha = hashlib.sha256()
     for f in sources:
         sha.update(open(os.path.join(ROOT, "paper_2409_06765_amd", "csrc", f), "rb").read())
@@ -89,7 +97,9 @@ def log(msg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=16, help="timed steps (each of --views-per-step views)")
+    ap.add_argument("--views-per-step", type=int, default=4,
+                    help="views rendered and differentiated by one call of every stage (consecutive cameras)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clusters1m_sh3_1080p", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -153,8 +163,13 @@ def main():
     # its tile's list until it stops ("paper-equivalent"), and the work the
     # timed kernels really do: the culled lists, each pixel evaluating only
     # the entries of its 8x8 quad's list while it is live (forward), or up to
-    # its last composited entry (backward).
-    views = [i % n_views for i in range(args.steps)]
+    # its last composited entry (backward).  A view's work does not depend on
+    # the other views of its step (their tiles and lists are disjoint).
+    V = max(1, min(int(args.views_per_step), n_views))
+    while n_views % V:                       # a step's views are consecutive cameras of the workload
+        V -= 1
+    batches = [[(i * V + j) % n_views for j in range(V)] for i in range(args.steps)]
+    views = [v for b in batches for v in b]
     counts = {}
     for v in sorted(set(views)):
         sq = counting_pass(v, p_square)
@@ -166,20 +181,24 @@ def main():
     torch.cuda.synchronize()
     log(f"counts view {views[0]}: {counts[views[0]]}")
 
-    # The timed step: every buffer allocated once, the step only enqueues library calls.
+    # The timed step: V views in one call of every stage, every buffer allocated once, the step only
+    # enqueues library calls.
     from paper_2409_06765_amd.pipeline import ViewPipeline
-    cap = int(1.25 * max(c["M_culled"] for c in counts.values())) + 1024
+    warm_batches = [batches[i % len(batches)] for i in range(args.warmup)]
+    M_batch = lambda b: sum(counts[v]["M_culled"] for v in b) if all(v in counts for v in b) else None
+    cap = int(1.25 * max(M_batch(b) for b in batches)) + 1024
     nslots = args.warmup + args.steps
-    pipe = ViewPipeline(p, d, [W], [H], cap, slots=nslots)
+    pipe = ViewPipeline(p, d, [W] * V, [H] * V, cap, slots=nslots)
+    v_image_b = v_image.repeat(V, 1) if V > 1 else v_image
     stream = torch.cuda.current_stream()
     stage_names = ["project_fwd", "intersect", "rasterize_fwd", "zero_grads", "rasterize_bwd", "project_bwd"]
     stages = [pipe.project, pipe.bin, pipe.rasterize_forward, pipe.zero_grads,
-              lambda: pipe.rasterize_backward(v_image), pipe.project_backward]
+              lambda: pipe.rasterize_backward(v_image_b), pipe.project_backward]
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] for _ in range(args.steps)]
     host = np.zeros((args.steps, len(stages)))
 
-    def run(i, v, timed):
-        pipe.set_cameras(vms[v:v + 1], Kss[v:v + 1], copy=False)
+    def run(i, b, timed):
+        pipe.set_cameras(vms[b[0]:b[0] + V], Kss[b[0]:b[0] + V], copy=False)
         ev = events[i] if timed else None
         if ev:
             ev[0].record(stream)
@@ -193,8 +212,10 @@ def main():
                 host[i, k] = time.perf_counter() - t0
                 ev[k + 1].record(stream)
 
+    assert all(b[0] + V <= n_views and b == list(range(b[0], b[0] + V)) for b in batches + warm_batches), \
+        "each step's views must be consecutive cameras"
     for i in range(args.warmup):
-        run(i, views[i % len(views)], False)
+        run(i, warm_batches[i], False)
     torch.cuda.synchronize()
     if args.calibrate_copy:
         src = torch.ones(64 << 20, device=dev, dtype=torch.float32)
@@ -205,28 +226,29 @@ def main():
 
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for i, v in enumerate(views):
-        run(i, v, True)
+    for i, b in enumerate(batches):
+        run(i, b, True)
     t_host = time.perf_counter() - t_start
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_start
 
-    # every timed view's lists fitted the capacity (no host wait inside the loop; checked after)
+    # every timed step's lists fitted the capacity (no host wait inside the loop; checked after)
     got = pipe.counts()
     assert max(got) <= cap, "intersection capacity exceeded in the timed loop"
-    assert [got[args.warmup + i] for i in range(args.steps)] == [counts[v]["M_culled"] for v in views], \
+    assert [got[args.warmup + i] for i in range(args.steps)] == [M_batch(b) for b in batches], \
         "timed steps built other lists than the counting pass"
     per_stage = np.array([[ev[k].elapsed_time(ev[k + 1]) for k in range(len(stages))] for ev in events])
-    per_view = np.array([ev[0].elapsed_time(ev[-1]) for ev in events])
+    per_step = np.array([ev[0].elapsed_time(ev[-1]) for ev in events])
     stage_ms = {k: round(float(per_stage[:, i].mean()), 4) for i, k in enumerate(stage_names)}
     host_ms = {k: round(1e3 * float(host[:, i].mean()), 4) for i, k in enumerate(stage_names)}
     ms_per_step = 1e3 * t_wall / args.steps
+    nv_timed = args.steps * V
     tot = lambda key: sum(counts[v][key] for v in views)
     E_fwd, E_bwd, C_tot = tot("E_fwd"), tot("E_bwd"), tot("C")
     E_fwd_x, E_bwd_x = tot("E_fwd_exec"), tot("E_bwd_exec")
     value = (E_fwd_x + E_bwd_x) / t_wall
 
-    # dominant kernel: the backward compositing (bound by vector-instruction issue)
+    # dominant kernel: the backward compositing (bound by vector-instruction issue); one launch per step
     bwd_ms = stage_ms["rasterize_bwd"]
     bwd_flops_x = (FLOPS_EVAL * E_bwd_x + FLOPS_BWD_COMP * C_tot) / args.steps
     bwd_flops_p = (FLOPS_EVAL * E_bwd + FLOPS_BWD_COMP * C_tot) / args.steps
@@ -240,34 +262,57 @@ def main():
                 "achieved_paper_equivalent": round(achieved_p, 3),
                 "frac_paper_equivalent": round(achieved_p / PEAK_FP32_TFLOPS, 4)}
     if args.workload == "clusters1m_sh3_1080p":
-        t = measured_traffic()
+        t = measured_traffic(views=V)
         roofline["traffic"] = None if t is None else int(t)
 
-    # device memory: the resident scene, and what the preallocated forward + backward state of one view takes
+    # device memory: the resident scene, and what the preallocated forward + backward state of one step takes
     memory = {"scene_bytes": int(sum(v.numel() * v.element_size() for v in d.values())),
-              "per_view_state_bytes": int(_device_bytes(pipe)),
+              "per_step_state_bytes": int(_device_bytes(pipe)), "views_per_step": V,
               "device_bytes": int(torch.cuda.get_device_properties(0).total_memory)}
-    log(f"memory: scene {memory['scene_bytes'] / 2**20:.0f} MiB, one fwd+bwd view's state "
-        f"{memory['per_view_state_bytes'] / 2**20:.0f} MiB")
+    log(f"memory: scene {memory['scene_bytes'] / 2**20:.0f} MiB, one {V}-view step's state "
+        f"{memory['per_step_state_bytes'] / 2**20:.0f} MiB")
+    del pipe
+    torch.cuda.empty_cache()
+
+    # the same views one per step (one camera per call of every stage), for comparison
+    single = None
+    if V > 1:
+        cap1 = int(1.25 * max(counts[v]["M_culled"] for v in views)) + 1024
+        p1 = ViewPipeline(p, d, [W], [H], cap1, slots=args.warmup + nv_timed)
+        for i in range(args.warmup):
+            p1.set_cameras(vms[i % n_views:i % n_views + 1], Kss[i % n_views:i % n_views + 1], copy=False)
+            p1.step(v_image, slot=i)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i, v in enumerate(views):
+            p1.set_cameras(vms[v:v + 1], Kss[v:v + 1], copy=False)
+            p1.step(v_image, slot=args.warmup + i)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter() - t1
+        assert max(p1.counts()) <= cap1
+        single = {"ms_per_view": round(1e3 * t1 / nv_timed, 4), "value": (E_fwd_x + E_bwd_x) / t1}
+        log(f"one view per step: {single['ms_per_view']:.4f} ms/view")
+        del p1
+        torch.cuda.empty_cache()
 
     graph = None
     if not args.no_graph:
         from paper_2409_06765_amd.graph import CapturedStep
-        cs = CapturedStep(p, d, [W], [H], v_image, (vms[0:1], Kss[0:1]), capacity=cap)
-        for i in range(args.warmup):
-            cs.replay(vms[views[i % len(views)]:views[i % len(views)] + 1], Kss[views[i % len(views)]:views[i % len(views)] + 1])
-        seen = torch.zeros(len(views), device=dev, dtype=torch.int64)
+        cs = CapturedStep(p, d, [W] * V, [H] * V, v_image_b, (vms[0:V], Kss[0:V]), capacity=cap)
+        for b in warm_batches:
+            cs.replay(vms[b[0]:b[0] + V], Kss[b[0]:b[0] + V])
+        seen = torch.zeros(len(batches), device=dev, dtype=torch.int64)
         torch.cuda.synchronize()
         tg = time.perf_counter()
-        for i, v in enumerate(views):
-            o = cs.replay(vms[v:v + 1], Kss[v:v + 1])
+        for i, b in enumerate(batches):
+            o = cs.replay(vms[b[0]:b[0] + V], Kss[b[0]:b[0] + V])
             seen[i:i + 1].copy_(o["isect"]["total_dev"][:1])
         torch.cuda.synchronize()
         tg = time.perf_counter() - tg
         assert int(seen.max()) <= cs.capacity, "a replay's lists exceeded the captured capacity"
-        graph = {"ms_per_view": round(1e3 * tg / args.steps, 4), "value": (E_fwd_x + E_bwd_x) / tg,
-                 "capacity": cs.capacity}
-        log(f"graph: {graph['ms_per_view']:.4f} ms/view (eager {ms_per_step:.4f})")
+        graph = {"ms_per_step": round(1e3 * tg / args.steps, 4), "ms_per_view": round(1e3 * tg / nv_timed, 4),
+                 "value": (E_fwd_x + E_bwd_x) / tg, "capacity": cs.capacity}
+        log(f"graph: {graph['ms_per_view']:.4f} ms/view (eager {1e3 * t_wall / nv_timed:.4f})")
         del cs
 
     out = {
@@ -278,26 +323,30 @@ def main():
         "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (seeded generators, activated parameters)",
-        "config": {"workload": f"{args.workload}: {wl['desc']}", "views_timed": args.steps, "width": W, "height": H,
-                   "n_gaussians": int(sc["means"].shape[0])},
+        "config": {"workload": f"{args.workload}: {wl['desc']}", "views_per_step": V, "views_timed": nv_timed,
+                   "width": W, "height": H, "n_gaussians": int(sc["means"].shape[0])},
         "value_definition": "forward + backward evaluations the timed kernels execute (culled lists, each pixel's "
                             "quad list while live / up to its last composited entry) per second of wall time",
-        "ms_per_view": ms_per_step,
-        "ms_per_view_gpu": {"median": round(float(np.median(per_view)), 4),
-                            "p10": round(float(np.percentile(per_view, 10)), 4),
-                            "p90": round(float(np.percentile(per_view, 90)), 4)},
-        "views_per_s": args.steps / t_wall,
+        "step_definition": f"{V} views through one call of every stage (projection, binning, forward and backward "
+                           f"compositing, projection backward); the projection backward sums the views' gradients",
+        "ms_per_view": round(1e3 * t_wall / nv_timed, 4),
+        "ms_per_step_gpu": {"median": round(float(np.median(per_step)), 4),
+                            "p10": round(float(np.percentile(per_step, 10)), 4),
+                            "p90": round(float(np.percentile(per_step, 90)), 4)},
+        "views_per_s": nv_timed / t_wall,
+        "one_view_per_step": single,
         "stage_ms": stage_ms,
+        "stage_ms_per_view": {k: round(v / V, 4) for k, v in stage_ms.items()},
         "stage_ms_median": {k: round(float(np.median(per_stage[:, i])), 4) for i, k in enumerate(stage_names)},
         "host_ms_per_stage": host_ms,
         "host_ms_per_step": round(1e3 * t_host / args.steps, 4),
-        "evals": {"E_fwd_per_view": E_fwd / args.steps, "E_bwd_per_view": E_bwd / args.steps,
-                  "composited_per_view": C_tot / args.steps,
-                  "E_fwd_exec_per_view": E_fwd_x / args.steps, "E_bwd_exec_per_view": E_bwd_x / args.steps,
-                  "E_fwd_culled_lists_per_view": tot("E_fwd_lists") / args.steps,
-                  "E_fwd_issued_per_view": tot("E_fwd_issued") / args.steps,
+        "evals": {"E_fwd_per_view": E_fwd / nv_timed, "E_bwd_per_view": E_bwd / nv_timed,
+                  "composited_per_view": C_tot / nv_timed,
+                  "E_fwd_exec_per_view": E_fwd_x / nv_timed, "E_bwd_exec_per_view": E_bwd_x / nv_timed,
+                  "E_fwd_culled_lists_per_view": tot("E_fwd_lists") / nv_timed,
+                  "E_fwd_issued_per_view": tot("E_fwd_issued") / nv_timed,
                   "E_fwd_issued_over_exec": round(tot("E_fwd_issued") / max(E_fwd_x, 1), 4),
-                  "M_per_view": tot("M") / args.steps, "M_culled_per_view": tot("M_culled") / args.steps},
+                  "M_per_view": tot("M") / nv_timed, "M_culled_per_view": tot("M_culled") / nv_timed},
         "evals_paper_equivalent_per_s": (E_fwd + E_bwd) / t_wall,
         "raster_fwd_tflops_executed": round(fwd_tflops, 3),
         "roofline": roofline,
@@ -305,8 +354,6 @@ def main():
     }
     if graph is not None:
         out["graph"] = graph
-    del pipe
-    torch.cuda.empty_cache()
     if not args.no_serve and args.workload == "clusters1m_sh3_1080p":
         out["serving"] = serving(d, p, args)
     if args.train_steps > 0 and args.workload == "clusters1m_sh3_1080p":

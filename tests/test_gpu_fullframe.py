@@ -1,12 +1,14 @@
 """Whole-frame parity at the configuration the benchmark times.
 
-The 1M-Gaussian, 1920 x 1080 view 0 goes through pipeline.ViewPipeline, the
-exact step bench.py times: culled tile lists, the forward compositing
-without counters, the dispatch order, the one-wave-per-tile RGB backward
-and the projection backward, every buffer allocated once.  The float32
-oracle computes the same view with the paper's whole 3-sigma tile lists over
-all 8,160 tiles (Rasterization of Gaussians; Depth Compositing Gradients;
-Projection Gradients), on every host core.  Checked:
+Views 0-3 of the 1M-Gaussian, 1920 x 1080 workload go through
+pipeline.ViewPipeline as one step, the exact step bench.py times: the four
+cameras in one call of every stage, culled tile lists, the forward
+compositing without counters, the dispatch order, the one-wave-per-tile RGB
+backward and the projection backward (which sums the views' gradients),
+every buffer allocated once.  The float32 oracle computes the same views
+with the paper's whole 3-sigma tile lists over all 32,640 tiles
+(Rasterization of Gaussians; Depth Compositing Gradients; Projection
+Gradients), on every host core.  Checked:
 
 * projection bit for bit;
 * images and final transmittance within 1e-4, and the last composited
@@ -44,31 +46,33 @@ def _say(msg):
     print(f"[gpu-fullframe] {msg}", flush=True)
 
 
-def _gpu_view(wl, v, v_image):
-    """The timed step for view v: ViewPipeline with the pipeline's default
+def _gpu_view(wl, views, v_image):
+    """The timed step for the consecutive views ``views`` (one call of every
+    stage over their cameras): ViewPipeline with the pipeline's default
     parameters, on the device; returns host copies of everything checked."""
     from _gpu import np_, to_dev
     from paper_2409_06765_amd import rasterize as R
     from paper_2409_06765_amd.pipeline import ViewPipeline
     sc = getattr(scenes, f"scene_{wl}")()
     cams = getattr(scenes, f"cams_{wl}")()
-    W, H = int(cams["W"][v]), int(cams["H"][v])
+    v0, C = views[0], len(views)
+    W, H = [int(w) for w in cams["W"][v0:v0 + C]], [int(h) for h in cams["H"][v0:v0 + C]]
     d = {k: to_dev(x) for k, x in sc.items() if isinstance(x, np.ndarray)}
-    vm, Ks = to_dev(cams["viewmats"][v:v + 1]), to_dev(cams["Ks"][v:v + 1])
+    vm, Ks = to_dev(cams["viewmats"][v0:v0 + C]), to_dev(cams["Ks"][v0:v0 + C])
     p = R.make_params(sh_degree=3)
     assert p.tile_cull == 1
-    # list capacity from an eager count of the same view
-    proj = R.project(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, [W], [H])
-    cap = int(R.intersect(p, proj, [W], [H])["M"] * 1.1) + 1024
+    # list capacity from an eager count of the same views
+    proj = R.project(p, d["means"], d["quats"], d["scales"], d["opacities"], d["sh"], vm, Ks, W, H)
+    cap = int(R.intersect(p, proj, W, H)["M"] * 1.1) + 1024
     del proj
-    pipe = ViewPipeline(p, d, [W], [H], cap)
+    pipe = ViewPipeline(p, d, W, H, cap)
     assert pipe.order is not None, "the dispatch order is part of the timed step"
     pipe.set_cameras(vm, Ks)
     pipe.step(to_dev(v_image))
     torch.cuda.synchronize()
     M = pipe.counts()[0]
     assert M <= cap
-    out = dict(sc=sc, cams={k: x[v:v + 1] for k, x in cams.items()}, W=W, H=H, M=M,
+    out = dict(sc=sc, cams={k: x[v0:v0 + C] for k, x in cams.items()}, W=W, H=H, M=M,
                proj={k: np_(x) for k, x in pipe.proj.items() if x is not None},
                ids=np_(pipe.ids[:M]), ranges=np_(pipe.ranges),
                image=np_(pipe.image), final_T=np_(pipe.final_T), last_ids=np_(pipe.last_ids),
@@ -83,37 +87,39 @@ def _last_gid(last_pos, ids):
     return np.where(last_pos >= 0, ids[np.maximum(last_pos, 0)], -1)
 
 
-def _check_view(wl, choose_tiles=None, flag_bar=1e-3):
+def _check_view(wl, choose_tiles=None, flag_bar=1e-3, n_views=1):
     cams_all = getattr(scenes, f"cams_{wl}")()
     W, H = int(cams_all["W"][0]), int(cams_all["H"][0])
     TX, TY = (W + 15) // 16, (H + 15) // 16
     P = OracleParams(sh_degree=3)
     # the oracle's forward first: the upstream gradient is zero on its flagged pixels (and off the checked tiles)
     sc = getattr(scenes, f"scene_{wl}")()
-    cams = {k: x[:1] for k, x in cams_all.items()}
+    cams = {k: x[:n_views] for k, x in cams_all.items()}
+    assert all(int(w) == W for w in cams["W"]) and all(int(h) == H for h in cams["H"])
     oracle.set_threads(16)
     try:
         _say(f"{wl}: oracle projection and binning (square lists)")
         proj = O32.project(P, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], cams["viewmats"],
                            cams["Ks"], cams["W"], cams["H"])
         isect = O32.intersect(P, proj, cams["W"], cams["H"])
-        tiles_mask = None if choose_tiles is None else choose_tiles(isect["ranges"], TX * TY)
+        tiles_mask = None if choose_tiles is None else choose_tiles(isect["ranges"], TX * TY * n_views)
         _say(f"{wl}: oracle forward over {'all' if tiles_mask is None else int(tiles_mask.sum())} tiles, "
              f"M={isect['M']}")
         args = (P, proj, sc["opacities"], isect["ranges"], isect["ids"], cams["W"], cams["H"])
         ras = O32.rasterize_fwd(*args, tile_mask=tiles_mask)
-        pix_in = np.ones(W * H, bool)
+        pix_in = np.ones(n_views * W * H, bool)
         if tiles_mask is not None:
-            ys, xs = np.divmod(np.arange(W * H), W)
-            pix_in = tiles_mask[(ys // 16) * TX + xs // 16] == 1
+            cc, rest = np.divmod(np.arange(n_views * W * H), W * H)
+            ys, xs = np.divmod(rest, W)
+            pix_in = tiles_mask[cc * TX * TY + (ys // 16) * TX + xs // 16] == 1
         ok = (ras["flags"] == 0) & pix_in
         frac = 1.0 - ok[pix_in].mean()
         _say(f"{wl}: flagged {int((~ok & pix_in).sum())} of {int(pix_in.sum())} pixels ({frac:.2e})")
         assert frac < flag_bar
-        v_image, _ = scenes.upstream_grads(wl, W * H, seed=0)
+        v_image, _ = scenes.upstream_grads(wl, n_views * W * H, seed=0)
         v_image[~ok] = 0.0
-        _say(f"{wl}: GPU step (timed configuration)")
-        g = _gpu_view(wl, 0, v_image)
+        _say(f"{wl}: GPU step (timed configuration, {n_views} views in one call)")
+        g = _gpu_view(wl, list(range(n_views)), v_image)
 
         gp = g["proj"]
         np.testing.assert_array_equal(gp["radii"], proj["radii"])
@@ -136,8 +142,11 @@ def _check_view(wl, choose_tiles=None, flag_bar=1e-3):
             assert_grad_close(g["g2"][k], o2[k], f"{wl}:{k}", abs_ref=o2["abs_" + k])
         # the chain: the float64 oracle's compositing of the same float32 projected values, then its projection
         # backward; the GPU's projection backward of its own compositing gradients checked stage-wise
+        _say(f"{wl}: compositing gradients ok; float64 oracle forward")
         r64 = O64.rasterize_fwd(*args, tile_mask=tiles_mask)
+        _say(f"{wl}: float64 oracle backward")
         o2x = O64.rasterize_bwd(*args, r64["final_T"], r64["last_ids"], v_image, tile_mask=tiles_mask)
+        _say(f"{wl}: projection gradients against the float64 chain")
         pb32, pb64 = oracle_project_bwd(O32, P, sc, cams), oracle_project_bwd(O64, P, sc, cams)
         assert_chain_close(g["g3"], g["g2"], o2x, pb64(o2x), pb32, pb64, wl)
         _say(f"{wl}: gradients ok")
@@ -146,7 +155,8 @@ def _check_view(wl, choose_tiles=None, flag_bar=1e-3):
 
 
 def test_full_frame_at_the_timed_configuration():
-    _check_view("clusters1m_sh3_1080p")
+    # the benchmark's step: four consecutive views through one call of every stage
+    _check_view("clusters1m_sh3_1080p", n_views=4)
 
 
 def _longest_and_random(ranges, T, n_long=64, n_rand=448, seed=5):
