@@ -569,6 +569,7 @@ def cpu_baseline(sc, cams, wl, args, counts, v0):
     ys, xs = np.divmod(np.arange(W * H), W)
     tile_of_pix = (ys // 16) * TX + xs // 16
     E_view = counts[v0]["E_fwd"] + counts[v0]["E_bwd"]
+    E_view_exec = counts[v0]["E_fwd_exec"] + counts[v0]["E_bwd_exec"]
 
     def run(threads, sample_tiles):
         oracle.set_threads(threads)
@@ -604,17 +605,22 @@ def cpu_baseline(sc, cams, wl, args, counts, v0):
                 f"of M={isect['M']} ({1e3 * (t2 - t1):.0f} ms), forward+backward compositing of {int(mask.sum())} of "
                 f"{TX * TY} tiles ({1e3 * (t3 - t2):.0f} ms, {e_s} evals)"
                 + (f", scaled by evaluations x{scale:.2f}" if scale > 1.0001 else ""))
-        return E_view / t_view, 1e3 * t_view, desc
+        return E_view_exec / t_view, 1e3 * t_view, desc, E_view / t_view
 
-    v1, ms1, d1 = run(1, args.cpu_sample_tiles)
-    vn, msn, dn = run(cores, None)
+    v1, ms1, d1, sq1 = run(1, args.cpu_sample_tiles)
+    vn, msn, dn, sqn = run(cores, None)
     log(f"cpu baseline: 1 thread {ms1:.0f} ms/view, {cores} threads {msn:.0f} ms/view")
     return {"value": vn, "unit": "Gaussian-pixel evals/s", "cores": cores, "kind": "oracle",
+            "value_definition": "the evaluations the GPU path executes for view 0 (the definition of value) per "
+                                "second of the oracle's time for that view; the oracle itself composites the "
+                                "square lists: value_square_lists counts those",
+            "value_square_lists": sqn,
             "ms_per_view_est": msn,
             "sample": f"view 0 on {cores} threads: {dn}; float32, gcc -O2 -fopenmp (compositing loops over tiles "
                       f"threaded, projection and binning on one thread)",
             "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
-            "single_thread": {"value": v1, "cores": 1, "ms_per_view_est": ms1, "sample": f"view 0: {d1}"}}
+            "single_thread": {"value": v1, "value_square_lists": sq1, "cores": 1, "ms_per_view_est": ms1,
+                              "sample": f"view 0: {d1}"}}
 
 
 if __name__ == "__main__":

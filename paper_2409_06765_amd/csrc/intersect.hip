@@ -586,7 +586,9 @@ __global__ void __launch_bounds__(256) keys64_kernel(int64_t M, const int64_t *_
 
 // ---------------------------------------------------------------------------
 // Stable LSD radix sort of (uint64 or uint32 key, int32 id), up to 8 bits per
-// pass.  Per pass: (1) per-block digit histograms, stored digit-major;
+// pass (an even number of passes; where the bits do not split evenly the low
+// passes take the narrower digits).  Per pass: (1) per-block digit histograms
+// (LDS atomics), stored digit-major;
 // (2) one block per digit scans its row over the blocks; (3) each block
 // ranks its elements stably (wave-level match on the digit bits, then wave
 // and block prefixes), reorders them in LDS and writes digit runs out.
@@ -624,10 +626,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K *__res
         const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
         const K kv = idx < M ? keys[idx] : (K)0;
         const bool valid = idx < M && !(drop && (uint64_t)kv == kDropKey);
-        const uint32_t d = valid ? (uint32_t)(kv >> shift) & mask : 0u;
-        const uint64_t active = __ballot(valid);
-        const uint64_t peers = match_digit(d, bits, active);
-        if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&cnt[d], (int32_t)__popcll(peers));
+        if (valid) atomicAdd(&cnt[(uint32_t)(kv >> shift) & mask], 1);   // counts need no order: LDS atomics
     }
     __syncthreads();
     if (threadIdx.x < (1 << bits)) hist[(int64_t)threadIdx.x * stride + blockIdx.x] = cnt[threadIdx.x];
@@ -960,7 +959,6 @@ int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int3
     }
     int passes = (key_bits + 7) / 8;
     if (passes % 2) passes++;
-    const int width = (key_bits + passes - 1) / passes;
     const int nb = (int)((M + kSortTile - 1) / kSortTile);
     const int stride = hist_stride(nb);
     int32_t *hist = (int32_t *)ws;
@@ -968,10 +966,9 @@ int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int3
     K *kin = keys, *kout = keys_alt;
     int32_t *iin = ids, *iout = ids_alt;
     for (int ps = 0; ps < passes; ps++) {
-        const int shift = ps * width;
-        int bits = key_bits - shift;
-        if (bits > width) bits = width;
-        if (bits < 0) bits = 0;   // a padding pass: every digit 0, a stable copy
+        // the lower passes take the narrower digits (fewer buckets: longer runs in the scattered writes)
+        const int shift = (key_bits * ps) / passes;
+        const int bits = (key_bits * (ps + 1)) / passes - shift;   // 0: a padding pass, a stable copy
         const int drop = kept && ps == 0;
         const int64_t *cnt = kept && ps > 0 ? kept : count_dev;
         if (!(hist0_ready && ps == 0))
@@ -1260,7 +1257,7 @@ int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const fl
     static_assert(kEmitChunk * (kEmitThreads / kWave) == kSortTile, "an emit block fills one sort tile");
     int passes = (tile_bits + 7) / 8;
     if (passes % 2) passes++;
-    const int width0 = std::min((tile_bits + passes - 1) / passes, tile_bits);
+    const int width0 = tile_bits / passes;
     const bool fuse = M > 1;
     // M is the capacity; the true count (b.total, from the prepare step) is read on the device
     emit_kernel<uint32_t><<<dim3((unsigned)ne), dim3(kEmitThreads), 0, s>>>(

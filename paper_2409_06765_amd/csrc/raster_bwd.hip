@@ -310,18 +310,23 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
 // across the wave) and then reduced and added to memory once per (tile,
 // entry) instead of once per (quad, entry): fewer butterfly reductions and
 // fewer atomics for the same per-pixel work.  Batches of 64 entries are
-// staged in LDS; entries that reach no quad (or only quads past their last
-// composited entry) are dropped from the batch's list at staging time.
+// staged in LDS, compacted: entries that reach no quad (or only quads past
+// their last composited entry) are dropped at staging time, and the rest are
+// stored in list order, so the walk reads its records at consecutive slots
+// with no index lookup in between.
 constexpr int kTileBatch = 64;
+
+// The gradient outputs are global memory.  An address formed from an integer
+// would make the atomic a flat instruction, which also counts on the LDS
+// counter, so the next entry's LDS reads would wait for it to complete; the
+// explicit address space keeps it a global atomic.
+using global_float = __attribute__((address_space(1))) float;
 
 template <bool kStd>
 __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, CamTable cams) {
     __shared__ float4 s_xyo[kTileBatch];
     __shared__ float4 s_con[kTileBatch];
     __shared__ float4 s_col[kTileBatch];
-    __shared__ int32_t s_id[kTileBatch];
-    __shared__ uint8_t s_qm[kTileBatch];
-    __shared__ uint8_t s_list[kTileBatch];
 
     const int tile = block_tile(a.order, cams.total_tiles);
     if (tile < 0) return;
@@ -380,38 +385,42 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
     const uint64_t dst_addr = (uint64_t)dst_base;
     const int cam_base = c * a.N;
     // lanes 2, 4: dL/da, dL/dc are half the dx^2, dy^2 moments; lanes 9, 10: |dL/dmu'| carries log2(e)
-    const float lscale = (lane == 2 || lane == 4) ? 0.5f : (lane == 9 || lane == 10) ? 1.0f / kLog2e : 1.0f;
+    const float lscale = lane < 2 ? 2.0f / kLog2e : (lane == 2 || lane == 4) ? 0.5f
+                       : (lane == 9 || lane == 10) ? 1.0f / kLog2e : 1.0f;
 
     for (int hi = stop + 1; hi > start; hi -= kTileBatch) {
         const int base = max(start, hi - kTileBatch);
         const int k = base + lane;
         uint32_t qm = 0u;
+        PackedGauss r;
+        int g = 0;
         if (k < hi) {
-            int g = a.ids[k];
+            g = a.ids[k];
             if ((unsigned)g >= (unsigned)a.CN) g = 0;   // ids come from the sort; this only bounds a bad input
-            const PackedGauss r = a.gauss[g];
+            r = a.gauss[g];
             qm = refine_quad_mask(quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0), r.xyoh,
                                   r.conh, r.col.w, tile_x0, tile_y0);
 #pragma unroll
             for (int q = 0; q < 4; q++)
                 if (k > qlast[q]) qm &= ~(1u << q);      // past every pixel of the quad's last entry
-            s_xyo[lane] = r.xyoh;
-            s_con[lane] = r.conh;
-            s_col[lane] = r.col;
-            s_id[lane] = g;
         }
-        s_qm[lane] = (uint8_t)qm;
+        // the entries that reach a quad, compacted in list order; the records' spare words carry the list
+        // index, the quad mask and the id
         const uint64_t bal = __ballot(qm != 0u);
-        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-        if (qm != 0u) s_list[__popcll(bal & below)] = (uint8_t)lane;
+        if (qm != 0u) {
+            const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+            const int slot = __popcll(bal & below);
+            s_xyo[slot] = make_float4(r.xyoh.x, r.xyoh.y, r.xyoh.z, __int_as_float(k));
+            s_con[slot] = make_float4(r.conh.x, r.conh.y, r.conh.z, __uint_as_float(qm));
+            s_col[slot] = make_float4(r.col.x, r.col.y, r.col.z, __int_as_float(g));
+        }
         __syncthreads();
         for (int j = __popcll(bal) - 1; j >= 0; j--) {
-            const int e = __builtin_amdgcn_readfirstlane(s_list[j]);
-            const int kk = base + e;
-            const uint32_t qme = __builtin_amdgcn_readfirstlane(s_qm[e]);
-            const float4 xyo = s_xyo[e];
-            const float4 con = s_con[e];
-            const float4 col = s_col[e];
+            const float4 xyo = s_xyo[j];
+            const float4 con = s_con[j];
+            const float4 col = s_col[j];
+            const int kk = __builtin_amdgcn_readfirstlane(__float_as_int(xyo.w));
+            const uint32_t qme = __builtin_amdgcn_readfirstlane(__float_as_uint(con.w));
             // Per-lane sums over this lane's pixels of v_sigma times (dx, dy, dx^2, dx dy, dy^2), of the
             // colour gradients, of v_sigma, and of |dL/dmu'|: the conic and the opacity are the same for
             // every pixel, so the mean gradient (d sigma / d mu' is linear in dx, dy) and the opacity
@@ -458,6 +467,12 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
                 }
             }
             if (!any) continue;
+            {   // the mean gradient is linear in the first moments with this entry's coefficients: form it per
+                // lane before the reduction, so lanes 0 and 1 take their totals as they are
+                const float sc = fmaf(con.y, acc[1], acc[0]);
+                acc[1] = fmaf(con.x * con.y, sc, con.z * acc[1]);
+                acc[0] = con.x * sc;
+            }
             // Transposing butterfly: lanes 0-7 of each 16-lane row end with the row's total of value
             // (lane & 7); lanes 8-15 then take the row totals of the v_sigma sum (lane 8) and of the two
             // |dL/dmu'| sums (lanes 9, 10), and one pair of cross-row exchanges finishes all of them.
@@ -479,16 +494,12 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
             // lanes 0, 1: dL/dmu' = (2 A' S_dx + B' S_dy, B' S_dx + 2 C' S_dy) / log2(e) with the scaled
             // conic (A', B', C') = (A, 2 A r, Q + A r^2), i.e. 2 (A s_c, A r s_c + Q S_dy) / log2(e) with
             // s_c = S_dx + r S_dy; lane 8: dL/do = -(sum of v_sigma) / o
-            const float yo = dpp<kDppXor1>(y);            // lane 0 <-> lane 1
-            const float sdx = lane == 0 ? y : yo, sdy = lane == 0 ? yo : y;
-            const float sc = fmaf(con.y, sdy, sdx);
-            const float mean = (lane == 0 ? con.x * sc : fmaf(con.x * con.y, sc, con.z * sdy)) * (2.0f / kLog2e);
-            const float val = lane < 2 ? mean : y * (lane == 8 ? -__builtin_amdgcn_rcpf(xyo.z) : lscale);
-            const int g = __builtin_amdgcn_readfirstlane(s_id[e]);   // uniform: scalar index arithmetic
-            int n = g - cam_base;
+            const float val = y * (lane == 8 ? -__builtin_amdgcn_rcpf(xyo.z) : lscale);
+            const int ge = __builtin_amdgcn_readfirstlane(__float_as_int(col.w));   // uniform: scalar index arithmetic
+            int n = ge - cam_base;
             if ((unsigned)n >= (unsigned)a.N) n = 0;   // only a bad id can leave the tile's camera
-            const uint32_t gi = dst_by_n ? (uint32_t)n : (uint32_t)g;
-            if (dst_lane) unsafeAtomicAdd((float *)(dst_addr + (uint64_t)gi * dst_stride), val);
+            const uint32_t gi = dst_by_n ? (uint32_t)n : (uint32_t)ge;
+            if (dst_lane) __builtin_amdgcn_global_atomic_fadd_f32((global_float *)(dst_addr + (uint64_t)gi * dst_stride), val);
         }
         __syncthreads();
     }
