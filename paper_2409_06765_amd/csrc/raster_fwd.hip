@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     __shared__ float4 s_con[kBatch];   // conic a, b, c, -
     __shared__ float4 s_col[kBatch];   // colour r, g, b, log2(opacity / alpha_min)
     __shared__ float s_feat[kRGB ? 1 : DM * kBatch];
-    __shared__ uint8_t s_qlist[4][kBatch];
+    __shared__ __align__(4) uint8_t s_qlist[4][kBatch];
     __shared__ int32_t s_wcnt[4][4];
     __shared__ int32_t s_qcnt[4];
 
@@ -106,6 +106,7 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
     int last = -1, ncomp = 0, stop_at = -1;
     int nq = 0, nq_last = 0, nit = 0;        // counts: quad-list entries evaluated live, up to the last, stepped
     bool done = !inside;
+    float live = inside ? 1.0f : 0.0f;       // the plain RGB walk's form of !done
     for (int b0 = start; b0 < end; b0 += kBatch) {
         if (__syncthreads_count(done) == kThreads) break;
         const int k = b0 + (int)threadIdx.x;
@@ -122,8 +123,45 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
             if (!kRGB) stage_features<DM, kBatch>(a, c, g, threadIdx.x, s_feat);
         }
         compact_quads(qm, s_qlist, s_wcnt, s_qcnt);
-        const int cnt = s_qcnt[w];                  // entries that can reach this wave's quad
+        const int cnt = __builtin_amdgcn_readfirstlane(s_qcnt[w]);   // entries that can reach this wave's quad
         if (__all(done)) continue;
+        if constexpr (kRGB && kStd && !kCount) {
+            // The timed instance: the same decisions with the per-lane state in vector registers and
+            // every condition applied by a select, so no lane mask is combined by scalar instructions
+            // (the scalar unit, shared by the waves of a compute unit, limits this loop more than the
+            // vector units), four list indices per LDS read and the all-stopped test once per eight
+            // entries.  With the default thresholds an entry that reaches a live pixel has alpha >= 1/255
+            // and T >= 1e-4 before it, so it composites exactly where its weight alpha T is positive.
+            for (int j0 = 0; j0 < cnt; j0 += 8) {
+                const int jn = min(cnt - j0, 8);
+                const uint32_t e4a = __builtin_amdgcn_readfirstlane(*(const uint32_t *)&s_qlist[w][j0]);
+                const uint32_t e4b = __builtin_amdgcn_readfirstlane(*(const uint32_t *)&s_qlist[w][j0 + 4]);
+                for (int u = 0; u < jn; u++) {
+                    const int e = ((u < 4 ? e4a : e4b) >> (8 * (u & 3))) & 0xFFu;
+                    const float4 xyo = s_xyo[e];
+                    const float4 con = s_con[e];
+                    const float dx = xyo.x - px, dy = xyo.y - py;
+                    const float sig = scaled_sigma(con, dx, dy);
+                    const float al = min_alpha(xyo.z * __builtin_amdgcn_exp2f(-sig), amax);
+                    float ae = sig >= 0.0f ? al : 0.0f;           // alpha where the entry is used, else 0
+                    ae = ae >= amin ? ae : 0.0f;
+                    ae *= live;
+                    const float Tn = T * (1.0f - ae);
+                    const bool keep = Tn >= tmin;                 // false only where this entry stops the pixel
+                    const float wgt = keep ? ae * T : 0.0f;
+                    const float4 col = s_col[e];
+                    Cacc[0] = fmaf(col.x, wgt, Cacc[0]);
+                    Cacc[1] = fmaf(col.y, wgt, Cacc[1]);
+                    Cacc[2] = fmaf(col.z, wgt, Cacc[2]);
+                    T = keep ? Tn : T;
+                    live = keep ? live : 0.0f;
+                    last = wgt > 0.0f ? b0 + e : last;
+                }
+                if (__all(live == 0.0f)) break;
+            }
+            done = live == 0.0f;
+            continue;
+        }
         for (int j = 0; j < cnt; j++) {
             const int e = __builtin_amdgcn_readfirstlane(s_qlist[w][j]);
             const float4 xyo = s_xyo[e];
