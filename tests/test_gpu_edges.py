@@ -262,3 +262,31 @@ def test_binning_keeps_equal_depths_in_id_order(C, N):
     assert st["isect"]["M"] == isect["M"]
     np.testing.assert_array_equal(np_(st["isect"]["ids"]), isect["ids"])
     np.testing.assert_array_equal(np_(st["isect"]["ranges"]), isect["ranges"])
+
+
+@pytest.mark.parametrize("opaque,tile_cull", [(False, 0), (True, 0), (True, 1)])
+def test_timed_forward_matches_the_counting_forward(opaque, tile_cull):
+    """With the default thresholds and no per-pixel counts, plain RGB takes a walk of its own (the
+    per-pixel state in vector registers, each condition applied by a select); its image, final T and
+    last composited index equal the counting instance's bit for bit.  Opaque Gaussians make most
+    pixels stop at T < 1e-4, the logit-normal opacities of the other scene put many alphas near 1/255."""
+    from _gpu import gpu_forward, np_, params
+    _say(f"timed forward vs counting forward, opaque={opaque} tile_cull={tile_cull}")
+    sc = scenes.scene_tiny(4000, seed=21, log_scale_mean=-2.8)
+    if opaque:
+        sc["opacities"][:] = 0.995
+    cams = scenes.cams_tiny(W=200, H=136, f=150.0, n_cams=2, seed=7)
+    p = params(tile_cull=tile_cull)
+    a = gpu_forward(p, sc, cams, n_eval=True)
+    b = gpu_forward(p, sc, cams, n_eval=False)
+    assert a["isect"]["M"] > 0
+    for k in ("image", "final_T", "last_ids"):
+        np.testing.assert_array_equal(np_(b["fwd"][k]), np_(a["fwd"][k]), err_msg=k)
+    if opaque:   # the stopping rule is exercised: many pixels stop before the end of their tile's list
+        W, H, TX, TY = 200, 136, 13, 9
+        c, y, x = np.divmod(np.arange(2 * H * W), H * W)[0], *np.divmod(np.arange(2 * H * W) % (H * W), W)
+        tile = c * TX * TY + (y // 16) * TX + x // 16
+        ranges = np_(a["isect"]["ranges"])
+        list_len = ranges[tile, 1] - ranges[tile, 0]
+        stopped = np_(a["fwd"]["n_eval"])[:, 0] < list_len
+        assert stopped.sum() > 2000, stopped.sum()
