@@ -529,10 +529,25 @@ __global__ void __launch_bounds__(256) ranges_kernel(int64_t M, const int64_t *_
     const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeItems;
     if (i0 >= M) return;
     int32_t t[kRangeItems + 2];
+    bool loaded = false;
+    if constexpr (sizeof(K) == 4) {
+        static_assert(kRangeItems == 8, "two 16-byte loads of 32-bit keys");
+        if (i0 + kRangeItems <= M) {   // i0 is a multiple of 8 and the key buffer 256-byte aligned
+            const uint4 *q = reinterpret_cast<const uint4 *>(keys + i0);
+            const uint4 lo = q[0], hi = q[1];
+            t[1] = (int32_t)lo.x; t[2] = (int32_t)lo.y; t[3] = (int32_t)lo.z; t[4] = (int32_t)lo.w;
+            t[5] = (int32_t)hi.x; t[6] = (int32_t)hi.y; t[7] = (int32_t)hi.z; t[8] = (int32_t)hi.w;
+            t[0] = i0 > 0 ? tile_of<K>(keys[i0 - 1]) : -1;
+            t[kRangeItems + 1] = i0 + kRangeItems < M ? tile_of<K>(keys[i0 + kRangeItems]) : -1;
+            loaded = true;
+        }
+    }
+    if (!loaded) {
 #pragma unroll
-    for (int k = 0; k < kRangeItems + 2; k++) {
-        const int64_t i = i0 - 1 + k;
-        t[k] = (i >= 0 && i < M) ? tile_of<K>(keys[i]) : -1;
+        for (int k = 0; k < kRangeItems + 2; k++) {
+            const int64_t i = i0 - 1 + k;
+            t[k] = (i >= 0 && i < M) ? tile_of<K>(keys[i]) : -1;
+        }
     }
 #pragma unroll
     for (int k = 1; k <= kRangeItems; k++) {
