@@ -224,17 +224,29 @@ __global__ void __launch_bounds__(kScanThreads) gather_block_sums_kernel(int64_t
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
-// One block turns the block sums into exclusive block offsets.
+// One block turns the block sums into exclusive block offsets, kSumItems
+// consecutive sums per thread per round (one round up to 4,096 sums).
+constexpr int kSumItems = 16;
+
 __global__ void __launch_bounds__(kScanThreads) scan_sums_kernel(int64_t *__restrict__ sums, int64_t nb,
                                                                  int64_t *__restrict__ total_out,
                                                                  int64_t *__restrict__ total_copy) {
     int64_t carry = 0;
-    for (int64_t start = 0; start < nb; start += kScanThreads) {
-        const int64_t i = start + threadIdx.x;
-        const int64_t v = i < nb ? sums[i] : 0;
+    for (int64_t start = 0; start < nb; start += (int64_t)kScanThreads * kSumItems) {
+        const int64_t i0 = start + (int64_t)threadIdx.x * kSumItems;
+        int64_t v[kSumItems], local = 0;
+#pragma unroll
+        for (int k = 0; k < kSumItems; k++) {
+            v[k] = i0 + k < nb ? sums[i0 + k] : 0;
+            local += v[k];
+        }
         int64_t tot;
-        const int64_t ex = block_exclusive_scan<int64_t>(v, tot);
-        if (i < nb) sums[i] = carry + ex;
+        int64_t run = carry + block_exclusive_scan<int64_t>(local, tot);
+#pragma unroll
+        for (int k = 0; k < kSumItems; k++) {
+            if (i0 + k < nb) sums[i0 + k] = run;
+            run += v[k];
+        }
         carry += tot;
     }
     if (threadIdx.x == 0) {
@@ -615,9 +627,10 @@ constexpr int kSortWaves = kSortThreads / kWave;
 constexpr int kBins = 256;
 
 // Lanes (among `active`) holding the same digit as this lane.
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, uint64_t active) {
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
     uint64_t m = active;
-    for (int b = 0; b < bits; b++) {
+#pragma unroll
+    for (int b = 0; b < 8; b++) {   // all eight bits: a narrower digit's upper bits are 0 in every lane
         const bool bit = (d >> b) & 1u;
         const uint64_t bal = __ballot(bit);
         m &= bit ? bal : ~bal;
@@ -732,7 +745,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__
         val[i] = valid ? (ids_in ? ids_in[idx] : (int32_t)idx) : 0;
         const uint32_t d = (uint32_t)(key[i] >> shift) & mask;
         const uint64_t active = __ballot(valid);
-        const uint64_t peers = match_digit(d, bits, active);
+        const uint64_t peers = match_digit(d, active);
         rank[i] = -1;
         if (valid) {
             const int32_t before = s_wcnt[w][d];
@@ -815,7 +828,7 @@ __global__ void __launch_bounds__(kSmallThreads) radix_sort_small_kernel(uint32_
             const int idx = w * (kWave * kSmallItems) + i * kWave + lane;
             const bool valid = idx < M;
             const uint32_t d = (key[i] >> shift) & mask;
-            const uint64_t peers = match_digit(d, bits, __ballot(valid));
+            const uint64_t peers = match_digit(d, __ballot(valid));
             rank[i] = -1;
             if (valid) {
                 const int32_t before = s_wcnt[w][d];
