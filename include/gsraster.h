@@ -43,8 +43,9 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 8
+#define GSR_ABI_VERSION 9
 #define GSR_MAX_CAMERAS 64
+#define GSR_GRAD_RECORD 9   /* floats per (camera, Gaussian) in the grad_records layout */
 
 enum gsr_status {
     GSR_OK = 0,
@@ -56,7 +57,8 @@ enum gsr_status {
 
 /* Rasterizer constants.  Defaults (gsr_default_params): near 0.01, far +inf,
  * eps2d 0.3, jac_clamp 1.3, alpha_min 1/255, alpha_max 0.99, T_min 1e-4,
- * tile 16, sh_degree -1, antialiased 0. */
+ * tile 16, sh_degree -1, antialiased 0, render_depth none, colors_shared 0,
+ * tile_cull 1, grad_records 0. */
 typedef struct gsr_params {
     float near_plane;   /* cull when the camera-space depth t_z < near_plane          */
     float far_plane;    /* cull when t_z > far_plane                                   */
@@ -73,6 +75,9 @@ typedef struct gsr_params {
     int32_t tile_cull;     /* gsr_bin_*: 1 drops the tiles of a Gaussian's 3-sigma square
                               that no pixel centre can see at alpha >= alpha_min; 0 keeps
                               the whole square, as the paper bins                       */
+    int32_t grad_records;  /* gsr_rasterize_bwd, gsr_project_bwd: 1 keeps the 2D gradients
+                              of each (camera, Gaussian) together in one record of
+                              GSR_GRAD_RECORD floats at v_means2d; 0: four arrays  */
 } gsr_params;
 
 /* Depth rendering (Depth rendering appendix): the camera-space depth t_z of
@@ -320,6 +325,16 @@ int gsr_rasterize_bwd(const gsr_params *p, int C, int N, int D, const int32_t *W
                       const float *v_image, const float *v_alpha,
                       float *v_means2d, float *v_conics, float *v_colors, float *v_depths, float *v_opacities,
                       float *v_means2d_abs, void *ws, size_t ws_bytes, int flags, gsr_stream_t stream);
+
+/* The grad_records layout (params.grad_records = 1), a layout of the same
+ * sums: v_means2d points to [C,N,GSR_GRAD_RECORD] floats, each record
+ * {dL/dmu' x, y, dL/d(a, b, c) of the conic, dL/dcolour r, g, b, dL/dopacity};
+ * v_conics, v_colors and v_opacities (gsr_project_bwd: v_opacities_cn) are
+ * NULL.  Only for plain RGB: D = 3, no depth channel, colours not shared
+ * (GSR_EINVAL otherwise).  The compositing backward adds the nine sums of a
+ * (tile, Gaussian) with one atomic instruction whose lanes then fall in one
+ * or two cache lines instead of four arrays; gsr_project_bwd reads the same
+ * records.  v_means2d_abs and v_depths stay separate arrays. */
 
 /* Projection Gradients, Scale and rotation gradients, SH backward.  Per
  * Gaussian, summed over the C cameras (no atomics: one thread per Gaussian):

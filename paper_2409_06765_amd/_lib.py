@@ -28,7 +28,7 @@ GSR_COLUMN_COPY, GSR_COLUMN_MEANS, GSR_COLUMN_LOG_SCALES, GSR_COLUMN_STATE = 0, 
 GSR_MAX_CAMERAS = 64
 GSR_BWD_ACCUMULATE, GSR_BWD_PACKED = 1, 2
 GSR_DEPTH_NONE, GSR_DEPTH_ACCUMULATED, GSR_DEPTH_EXPECTED = 0, 1, 2
-ABI_VERSION = 8                 # the signatures below
+ABI_VERSION = 9                 # the signatures below
 _NAMES = {0: "GSR_OK", 1: "GSR_EINVAL", 2: "GSR_EOVERFLOW", 3: "GSR_EWORKSPACE", 4: "GSR_EHIP"}
 
 
@@ -43,7 +43,8 @@ class gsr_params(ctypes.Structure):
                 ("jac_clamp", ctypes.c_float), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("T_min", ctypes.c_float), ("tile", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
                 ("antialiased", ctypes.c_int32), ("render_depth", ctypes.c_int32),
-                ("colors_shared", ctypes.c_int32), ("tile_cull", ctypes.c_int32)]
+                ("colors_shared", ctypes.c_int32), ("tile_cull", ctypes.c_int32), ("grad_records", ctypes.c_int32)]
+GSR_GRAD_RECORD = 9             # floats per (camera, Gaussian) in the grad_records layout
 
 
 class gsr_adam_group(ctypes.Structure):

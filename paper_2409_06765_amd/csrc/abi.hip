@@ -48,6 +48,15 @@ int check_params(const gsr_params *p) {
         return fail(GSR_EINVAL, "render_depth must be 0, 1 or 2 (got %d)", p->render_depth);
     if (p->colors_shared != 0 && p->colors_shared != 1) return fail(GSR_EINVAL, "colors_shared must be 0 or 1");
     if (p->tile_cull != 0 && p->tile_cull != 1) return fail(GSR_EINVAL, "tile_cull must be 0 or 1");
+    if (p->grad_records != 0 && p->grad_records != 1) return fail(GSR_EINVAL, "grad_records must be 0 or 1");
+    return GSR_OK;
+}
+
+// The grad_records layout holds plain RGB only: three colour channels per (camera, Gaussian).
+int check_grad_records(const char *fn, const gsr_params *p, int D) {
+    if (!p->grad_records) return GSR_OK;
+    if (D != 3 || p->render_depth != GSR_DEPTH_NONE || p->colors_shared)
+        return fail(GSR_EINVAL, "%s: grad_records needs D = 3, no depth channel and colours per camera", fn);
     return GSR_OK;
 }
 
@@ -107,6 +116,7 @@ void gsr_default_params(gsr_params *p) {
     p->render_depth = GSR_DEPTH_NONE;
     p->colors_shared = 0;
     p->tile_cull = 1;
+    p->grad_records = 0;
 }
 
 size_t gsr_workspace_bytes(int op, int C, int N, int64_t M) {
@@ -349,8 +359,17 @@ int gsr_rasterize_bwd(const gsr_params *p, int C, int N, int D, const int32_t *W
     if ((int64_t)C * N == 0) return GSR_OK;
     GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(ranges); GSR_NEED(ids);
     GSR_NEED(final_T); GSR_NEED(last_ids); GSR_NEED(v_image);
-    GSR_NEED(v_means2d); GSR_NEED(v_conics); GSR_NEED(v_opacities);
-    if (D > 0) { GSR_NEED(colors); GSR_NEED(v_colors); }
+    GSR_NEED(v_means2d);
+    if (p->grad_records) {
+        rc = check_grad_records(fn, p, D);
+        if (rc != GSR_OK) return rc;
+        if (v_conics || v_colors || v_opacities)
+            return fail(GSR_EINVAL, "%s: with grad_records v_conics, v_colors and v_opacities must be NULL", fn);
+        GSR_NEED(colors);
+    } else {
+        GSR_NEED(v_conics); GSR_NEED(v_opacities);
+        if (D > 0) { GSR_NEED(colors); GSR_NEED(v_colors); }
+    }
     if (p->render_depth != GSR_DEPTH_NONE) { GSR_NEED(depths); GSR_NEED(v_depths); }
     if (p->render_depth == GSR_DEPTH_EXPECTED) GSR_NEED(image);
     if (p->antialiased) GSR_NEED(compensations);
@@ -381,12 +400,22 @@ int gsr_project_bwd(const gsr_params *p, int C, int N, const int32_t *W, const i
                                                         (hipStream_t)stream) : GSR_OK;
     GSR_NEED(means); GSR_NEED(quats); GSR_NEED(scales); GSR_NEED(opacities);
     GSR_NEED(v_means); GSR_NEED(v_quats); GSR_NEED(v_scales); GSR_NEED(v_opacities);
-    const bool colour_grad = p->sh_degree >= 0 || v_colors;   // direct colours may be left out
+    if (p->grad_records) {
+        rc = check_grad_records(fn, p, 3);
+        if (rc != GSR_OK) return rc;
+        if (v_conics || v_colors || v_opacities_cn)
+            return fail(GSR_EINVAL, "%s: with grad_records v_conics, v_colors and v_opacities_cn must be NULL", fn);
+    }
+    // direct colours may be left out (records always carry a colour gradient: read when sh_or_colors is given)
+    const bool colour_grad = p->sh_degree >= 0 || (p->grad_records ? v_sh_or_colors != nullptr : v_colors != nullptr);
     if (colour_grad) { GSR_NEED(sh_or_colors); GSR_NEED(v_sh_or_colors); }
     if (C > 0) {
         GSR_NEED(viewmats); GSR_NEED(Ks); GSR_NEED(radii);
-        GSR_NEED(v_means2d); GSR_NEED(v_conics); GSR_NEED(v_opacities_cn);
-        if (colour_grad) GSR_NEED(v_colors);
+        GSR_NEED(v_means2d);
+        if (!p->grad_records) {
+            GSR_NEED(v_conics); GSR_NEED(v_opacities_cn);
+            if (colour_grad) GSR_NEED(v_colors);
+        }
         if (p->antialiased) GSR_NEED(compensations);
     }
     if (v_viewmats && C > 0 && N > 0) {

@@ -333,13 +333,19 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
         const float tx = o.t[0], ty = o.t[1], tz = o.t[2];
         float vt[3] = {0.0f, 0.0f, 0.0f};
 
+        // the 2D gradients of (c, n): four arrays, or one record per (camera, Gaussian)
+        const bool rec = p.grad_records != 0;
+        const float *gm = rec ? v_means2d + g * GSR_GRAD_RECORD : v_means2d + 2 * g;
+        const float *gc = rec ? gm + 2 : v_conics + 3 * g;
+        const float *gcol = rec ? gm + 5 : (v_colors ? v_colors + 3 * g : nullptr);
+
         // opacity (the rasterizer's opacity is o times the compensation)
-        const float vo = v_opac_cn[g];
+        const float vo = rec ? gm[8] : v_opac_cn[g];
         const float comp = (p.antialiased && comps) ? comps[g] : 1.0f;
         acc_o += vo * comp;
 
         // 2D mean
-        const float vmx = v_means2d[2 * g], vmy = v_means2d[2 * g + 1];
+        const float vmx = gm[0], vmy = gm[1];
         vt[0] += vmx * fx / tz;
         vt[1] += vmy * fy / tz;
         vt[2] += -(vmx * fx * tx + vmy * fy * ty) / (tz * tz);
@@ -350,9 +356,9 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
         // Gaussians Y is nearly singular and the later products with T and Sigma cancel, which
         // amplifies errors that differ between rows; rows built consistently keep them small.
         const float ya = o.c / o.det, yb = -o.b / o.det, yc = o.a / o.det;
-        const float ga = v_conics[3 * g], gb = 0.5f * v_conics[3 * g + 1], gc = v_conics[3 * g + 2];
-        const float YG00 = ya * ga + yb * gb, YG01 = ya * gb + yb * gc;
-        const float YG10 = yb * ga + yc * gb, YG11 = yb * gb + yc * gc;
+        const float ga = gc[0], gb = 0.5f * gc[1], gcc = gc[2];
+        const float YG00 = ya * ga + yb * gb, YG01 = ya * gb + yb * gcc;
+        const float YG10 = yb * ga + yc * gb, YG11 = yb * gb + yc * gcc;
         float S00 = -(YG00 * ya + YG01 * yb);
         float S01 = -(YG00 * yb + YG01 * yc);
         float S10 = -(YG10 * ya + YG11 * yb);
@@ -429,7 +435,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
         // colour
         float gdir[3] = {0.0f, 0.0f, 0.0f};   // mean gradient through the SH view direction
         float vc[3] = {0.0f, 0.0f, 0.0f};   // no v_colors: direct colours are not differentiated here
-        if (v_colors) { vc[0] = v_colors[3 * g]; vc[1] = v_colors[3 * g + 1]; vc[2] = v_colors[3 * g + 2]; }
+        if (gcol) { vc[0] = gcol[0]; vc[1] = gcol[1]; vc[2] = gcol[2]; }
         if constexpr (NK > 0) {
             float cp[3], d[3];
             for (int j = 0; j < 3; j++) cp[j] = -((V[j] * V[3] + V[4 + j] * V[7]) + V[8 + j] * V[11]);

@@ -207,7 +207,11 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
     float *dst_base = nullptr;
     int dst_mul = 0;
     bool dst_by_n = false;
-    if (lane < 2) { dst_base = a.v_means2d + lane; dst_mul = 2; }
+    if (a.p.grad_records) {   // plain RGB: lanes 0..8 are the fields of the Gaussian's record, in order
+        if (lane < 9) { dst_base = a.v_means2d + lane; dst_mul = GSR_GRAD_RECORD; }
+        else if (lane < 11 && want_abs) { dst_base = a.v_means2d_abs + (lane - 9); dst_mul = 2; }
+    }
+    else if (lane < 2) { dst_base = a.v_means2d + lane; dst_mul = 2; }
     else if (lane < 5) { dst_base = a.v_conics + (lane - 2); dst_mul = 3; }
     else if (lane < 8) { if (lane - 5 < Dt) dst_base = channel_dst(a, lane - 5, dst_mul, dst_by_n); }
     else if (lane == 8) { dst_base = a.v_opac; dst_mul = 1; }
@@ -376,7 +380,11 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
     float *dst_base = nullptr;
     uint32_t dst_stride = 0;      // bytes between consecutive Gaussians' values of this lane's output
     bool dst_by_n = false;
-    if (lane < 2) { dst_base = a.v_means2d + lane; dst_stride = 8; }
+    if (a.p.grad_records) {   // lanes 0..8 are the fields of the Gaussian's record, in order
+        if (lane < 9) { dst_base = a.v_means2d + lane; dst_stride = 4 * GSR_GRAD_RECORD; }
+        else if (lane < 11 && want_abs) { dst_base = a.v_means2d_abs + (lane - 9); dst_stride = 8; }
+    }
+    else if (lane < 2) { dst_base = a.v_means2d + lane; dst_stride = 8; }
     else if (lane < 5) { dst_base = a.v_conics + (lane - 2); dst_stride = 12; }
     else if (lane < 8) { dst_base = a.v_colors + (lane - 5); dst_stride = 12; dst_by_n = a.p.colors_shared != 0; }
     else if (lane == 8) { dst_base = a.v_opac; dst_stride = 4; }
@@ -519,10 +527,13 @@ int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D
     const size_t FN = p.colors_shared ? (size_t)N : CN;
     int rc = GSR_OK;
     if (!(flags & GSR_BWD_ACCUMULATE)) {   // one launch zeroes every output
-        void *const ptrs[6] = {v_means2d, v_conics, D > 0 ? v_colors : nullptr,
-                               p.render_depth != GSR_DEPTH_NONE ? v_depths : nullptr, v_opac, v_means2d_abs};
-        const size_t bytes[6] = {CN * 2 * sizeof(float), CN * 3 * sizeof(float), FN * (size_t)D * sizeof(float),
-                                 CN * sizeof(float), CN * sizeof(float), CN * 2 * sizeof(float)};
+        const bool rec = p.grad_records != 0;
+        void *const ptrs[6] = {v_means2d, rec ? nullptr : v_conics, (D > 0 && !rec) ? v_colors : nullptr,
+                               p.render_depth != GSR_DEPTH_NONE ? v_depths : nullptr, rec ? nullptr : v_opac,
+                               v_means2d_abs};
+        const size_t bytes[6] = {CN * (rec ? GSR_GRAD_RECORD : 2) * sizeof(float), CN * 3 * sizeof(float),
+                                 FN * (size_t)D * sizeof(float), CN * sizeof(float), CN * sizeof(float),
+                                 CN * 2 * sizeof(float)};
         rc = launch_fill_zero_multi(6, ptrs, bytes, s);
     }
     if (rc != GSR_OK || cams.total_tiles == 0 || N == 0) return rc;

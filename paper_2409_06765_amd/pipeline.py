@@ -17,7 +17,7 @@ records into a HIP graph.
 import torch
 
 from . import _lib as L
-from .rasterize import ORDER_MIN_TILES, layout
+from .rasterize import ORDER_MIN_TILES, _with, layout
 
 
 class ViewPipeline:
@@ -26,9 +26,17 @@ class ViewPipeline:
     -1); read at every step, so update them in place.  W, H: per-camera
     image sizes of the C views of one step.  capacity: entries of the
     intersection-list buffer.  slots: device count slots (one per step the
-    caller wants to check later)."""
+    caller wants to check later).  With plain RGB the 2D gradients are kept
+    as records (``grad_rec`` [C,N,9]) and ``g2`` holds strided views of
+    their fields; ``records=False`` keeps four arrays instead."""
 
-    def __init__(self, p, scene, W, H, capacity, slots=1, absgrad=False, stream=None):
+    def __init__(self, p, scene, W, H, capacity, slots=1, absgrad=False, stream=None, records=None):
+        # plain RGB keeps each (camera, Gaussian)'s 2D gradients in one record (params.grad_records): the
+        # compositing backward's atomics for a Gaussian then touch one or two cache lines, not four arrays
+        # (records=False asks for the four arrays)
+        plain = p.render_depth == 0 and not p.colors_shared
+        self.records = plain if records is None else bool(records) and plain
+        p = _with(p, grad_records=1) if self.records else p
         self.p = p
         self.scene = scene
         self.W, self.H = [int(w) for w in W], [int(h) for h in H]
@@ -62,7 +70,10 @@ class ViewPipeline:
         self.alpha = torch.empty(self.P, **f32)
         self.final_T = torch.empty(self.P, **f32)
         self.last_ids = torch.empty(self.P, **i32)
-        sizes = dict(v_means2d=(C, N, 2), v_conics=(C, N, 3), v_colors=(C, N, 3), v_opacities=(C, N))
+        if self.records:
+            sizes = dict(records=(C, N, L.GSR_GRAD_RECORD))
+        else:
+            sizes = dict(v_means2d=(C, N, 2), v_conics=(C, N, 3), v_colors=(C, N, 3), v_opacities=(C, N))
         if absgrad:
             sizes["v_means2d_abs"] = (C, N, 2)
         total = sum(int(torch.Size(s).numel()) for s in sizes.values())
@@ -72,6 +83,10 @@ class ViewPipeline:
             m = int(torch.Size(s).numel())
             self.g2[k] = self.grad_flat[o:o + m].view(s)
             o += m
+        self.grad_rec = self.g2.pop("records", None)
+        if self.records:   # the fields of the records, as strided views
+            r = self.grad_rec
+            self.g2.update(v_means2d=r[..., 0:2], v_conics=r[..., 2:5], v_colors=r[..., 5:8], v_opacities=r[..., 8])
         self.g2.setdefault("v_means2d_abs", None)
         sc = scene
         self.g3 = dict(v_means=torch.empty_like(sc["means"]), v_quats=torch.empty_like(sc["quats"]),
@@ -123,18 +138,28 @@ class ViewPipeline:
         """The compositing backward alone: the records the forward packed are
         reused and the gradients (zeroed by ``zero_grads``) are added to."""
         pr, sc, g = self.proj, self.scene, self.g2
+        g4 = self._grad_args()
         L.gsr_rasterize_bwd(self.p, self.C, self.N, 3, self.W, self.H, pr["means2d"], pr["conics"], pr["colors"],
                             pr["depths"], sc["opacities"], pr["comps"], None, self.ranges, self.ids, self.order,
-                            self.image, self.final_T, self.last_ids, v_image, v_alpha, g["v_means2d"],
-                            g["v_conics"], g["v_colors"], None, g["v_opacities"], g["v_means2d_abs"],
-                            ws=self.ws_raster, flags=L.GSR_BWD_ACCUMULATE | L.GSR_BWD_PACKED, stream=self.stream)
+                            self.image, self.final_T, self.last_ids, v_image, v_alpha, g4[0], g4[1], g4[2], None,
+                            g4[3], g["v_means2d_abs"], ws=self.ws_raster,
+                            flags=L.GSR_BWD_ACCUMULATE | L.GSR_BWD_PACKED, stream=self.stream)
+
+    def _grad_args(self):
+        """v_means2d, v_conics, v_colors, v_opacities as the library takes them: the records and three
+        NULLs, or the four arrays."""
+        g = self.g2
+        if self.records:
+            return self.grad_rec, None, None, None
+        return g["v_means2d"], g["v_conics"], g["v_colors"], g["v_opacities"]
 
     def project_backward(self):
-        sc, pr, g2, g3 = self.scene, self.proj, self.g2, self.g3
+        sc, pr, g3 = self.scene, self.proj, self.g3
+        g4 = self._grad_args()
         L.gsr_project_bwd(self.p, self.C, self.N, self.W, self.H, sc["means"], sc["quats"], sc["scales"],
-                          sc["opacities"], sc["sh"], *self.cam, pr["radii"], pr["comps"], g2["v_means2d"],
-                          g2["v_conics"], g2["v_colors"], g2["v_opacities"], None, g3["v_means"], g3["v_quats"],
-                          g3["v_scales"], g3["v_opacities"], g3["v_sh"], stream=self.stream)
+                          sc["opacities"], sc["sh"], *self.cam, pr["radii"], pr["comps"], *g4, None,
+                          g3["v_means"], g3["v_quats"], g3["v_scales"], g3["v_opacities"], g3["v_sh"],
+                          stream=self.stream)
 
     def step(self, v_image, slot=0, v_alpha=None):
         """The whole forward + backward for the cameras set last."""

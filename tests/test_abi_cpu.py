@@ -172,3 +172,40 @@ def test_training_entry_points_reject_bad_arguments(L):
     assert lib.gsr_opacity_reset(0, None, None, None, None, 0.01, None) == L.GSR_OK
     assert lib.gsr_mcmc_noise(0, None, None, None, None, None, 1.0, 100.0, 0.005, None) == L.GSR_OK
     assert lib.gsr_densify_apply(0, None, None, None, None, None, 1.6, 0, None, None) == L.GSR_OK
+
+
+def test_grad_records_layout_is_validated(L):
+    """params.grad_records: 0 or 1; only plain RGB (D = 3, no depth channel, colours per camera); the
+    three other gradient pointers NULL.  All rejected before anything is enqueued (fake pointers)."""
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)
+    W = (ctypes.c_int32 * 1)(64)
+
+    def bwd(p, D=3, v_conics=None, v_colors=None, v_opac=None):
+        # p, C, N, D, W, H; means2d conics colors depths opacities comps background; ranges ids order;
+        # image final_T last_ids; v_image v_alpha; v_means2d v_conics v_colors v_depths v_opac v_abs; ws flags
+        return lib.gsr_rasterize_bwd(ctypes.byref(p), 1, 8, D, W, W, fake, fake, fake, fake, fake, None, None,
+                                     fake, fake, None, None, fake, fake, fake, None, fake, v_conics, v_colors,
+                                     fake if p.render_depth else None, v_opac, None, fake, 1 << 30, 0, None)
+
+    def pbwd(p, v_conics=None, v_colors=None, v_opac=None):
+        return lib.gsr_project_bwd(ctypes.byref(p), 1, 8, W, W, fake, fake, fake, fake, fake, fake, fake, fake,
+                                   None, fake, v_conics, v_colors, v_opac, None, fake, fake, fake, fake, fake,
+                                   None, None, 0, None)
+
+    assert bwd(L.default_params(grad_records=2)) == L.GSR_EINVAL
+    assert "grad_records" in lib.gsr_last_error().decode()
+    rec = L.default_params(grad_records=1, sh_degree=3)
+    assert bwd(rec, D=4) == L.GSR_EINVAL
+    assert bwd(L.default_params(grad_records=1, render_depth=1), D=3) == L.GSR_EINVAL
+    assert bwd(L.default_params(grad_records=1, colors_shared=1)) == L.GSR_EINVAL
+    assert bwd(rec, v_conics=fake) == L.GSR_EINVAL
+    assert "NULL" in lib.gsr_last_error().decode()
+    assert bwd(rec, v_colors=fake) == L.GSR_EINVAL
+    assert bwd(rec, v_opac=fake) == L.GSR_EINVAL
+    assert pbwd(rec, v_conics=fake) == L.GSR_EINVAL
+    assert pbwd(rec, v_opac=fake) == L.GSR_EINVAL
+    assert pbwd(L.default_params(grad_records=1, colors_shared=1)) == L.GSR_EINVAL
+    # the four-array layout still needs its arrays
+    assert bwd(L.default_params(sh_degree=3)) == L.GSR_EINVAL
+    assert pbwd(L.default_params(sh_degree=3)) == L.GSR_EINVAL
