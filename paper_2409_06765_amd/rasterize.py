@@ -288,12 +288,25 @@ def rasterize_forward(p, proj, opacities, isect, W, H, background=None, n_eval=F
     return out
 
 
-def grad_buffers(C, N, device, absgrad=False, D=3, shared=False, depth=False, zero=True):
+def grad_buffers(C, N, device, absgrad=False, D=3, shared=False, depth=False, zero=True, records=False):
     """Per-camera gradient buffers of the compositing backward, carved from
     one allocation (zeroed with one fill unless ``zero`` is False): v_colors
     is [N,D] for shared features, else [C,N,D]; v_depths [C,N] when depth is
-    rendered."""
+    rendered.  ``records`` (plain RGB only): the four 2D gradients of each
+    (camera, Gaussian) kept together in "grad_rec" [C,N,9] (the library's
+    grad_records layout), with strided views of its fields under the usual
+    names."""
     n = C * N
+    if records:
+        if D != 3 or shared or depth:
+            raise ValueError("gradient records hold plain RGB only")
+        G = L.GSR_GRAD_RECORD
+        flat = (torch.zeros if zero else torch.empty)(n * G + (2 * n if absgrad else 0), device=device,
+                                                      dtype=torch.float32)
+        r = flat[:n * G].view(C, N, G)
+        return dict(grad_rec=r, v_means2d=r[..., 0:2], v_conics=r[..., 2:5], v_colors=r[..., 5:8],
+                    v_opacities=r[..., 8], v_depths=None,
+                    v_means2d_abs=flat[n * G:].view(C, N, 2) if absgrad else None)
     nf = (N if shared else n) * D
     sizes = dict(v_means2d=2 * n, v_conics=3 * n, v_colors=nf, v_opacities=n, v_depths=n if depth else 0,
                  v_means2d_abs=2 * n if absgrad else 0)
@@ -308,19 +321,21 @@ def grad_buffers(C, N, device, absgrad=False, D=3, shared=False, depth=False, ze
 
 
 def rasterize_backward(p, proj, opacities, isect, W, H, fwd, v_image, v_alpha=None, background=None,
-                       absgrad=False, grads=None, features=None, stream=None, overwrite=False):
+                       absgrad=False, grads=None, features=None, stream=None, overwrite=False, records=False):
     """Gradients of the compositing.  ``grads`` (from ``grad_buffers``) are
     added to; by default fresh zeroed buffers are used.  ``overwrite``: fresh
     uninitialised buffers that the library zeroes itself (no torch fill).
-    The records the forward packed into its workspace are reused."""
+    The records the forward packed into its workspace are reused.
+    ``records``: fresh buffers in the gradient-record layout (see
+    ``grad_buffers``), which ``project_backward`` reads as they are."""
     C, N = proj["radii"].shape
     d = proj["radii"].device
     pf, D, feat = _features(p, proj, features)
     depth = p.render_depth != L.GSR_DEPTH_NONE
     if overwrite and grads is not None:
         raise ValueError("overwrite makes its own buffers")
-    g = grad_buffers(C, N, d, absgrad, D, bool(pf.colors_shared), depth, zero=not overwrite) if grads is None \
-        else grads
+    g = grad_buffers(C, N, d, absgrad, D, bool(pf.colors_shared), depth, zero=not overwrite, records=records) \
+        if grads is None else grads
     if absgrad and g["v_means2d_abs"] is None:
         raise ValueError("absgrad needs grad buffers made with absgrad=True")
     ws = fwd.get("ws")
@@ -329,12 +344,17 @@ def rasterize_backward(p, proj, opacities, isect, W, H, fwd, v_image, v_alpha=No
         ws = raster_workspace(C, N, d)
     else:
         flags |= L.GSR_BWD_PACKED
+    rec = g.get("grad_rec")
+    if rec is not None:
+        pf = _with(pf, grad_records=1)
+        g4 = (rec, None, None, None)
+    else:
+        g4 = (g["v_means2d"], g["v_conics"], g["v_colors"] if D > 0 else None, g["v_opacities"])
     L.gsr_rasterize_bwd(pf, C, N, D, W, H, proj["means2d"], proj["conics"], feat, proj["depths"], opacities,
                         proj["comps"], background, isect["ranges"], isect["ids_buf"], isect.get("order"), fwd["image"],
-                        fwd["final_T"],
-                        fwd["last_ids"], v_image, v_alpha, g["v_means2d"], g["v_conics"],
-                        g["v_colors"] if D > 0 else None, g["v_depths"] if depth else None, g["v_opacities"],
-                        g["v_means2d_abs"] if absgrad else None, ws=ws, flags=flags, stream=stream)
+                        fwd["final_T"], fwd["last_ids"], v_image, v_alpha, g4[0], g4[1], g4[2],
+                        g["v_depths"] if depth else None, g4[3], g["v_means2d_abs"] if absgrad else None, ws=ws,
+                        flags=flags, stream=stream)
     return g
 
 
@@ -355,9 +375,14 @@ def project_backward(p, means, quats, scales, opacities, sh_or_colors, viewmats,
     ws = None
     if viewmat_grad:
         ws = torch.empty(max(L.workspace_bytes(L.GSR_OP_PROJECT_BWD, C, N, 0), 1), device=d, dtype=torch.uint8)
+    rec = g2.get("grad_rec")
+    if rec is not None:   # the gradient-record layout: one pointer, the three others NULL
+        p = _with(p, grad_records=1)
+        g4 = (rec, None, None, None)
+    else:
+        g4 = (g2["v_means2d"], g2["v_conics"], g2["v_colors"] if colour else None, g2["v_opacities"])
     L.gsr_project_bwd(p, C, N, W, H, means, quats, scales, opacities, sh_or_colors, viewmats, Ks, proj["radii"],
-                      proj["comps"], g2["v_means2d"], g2["v_conics"], g2["v_colors"] if colour else None,
-                      g2["v_opacities"], v_depths, out["v_means"], out["v_quats"], out["v_scales"],
+                      proj["comps"], *g4, v_depths, out["v_means"], out["v_quats"], out["v_scales"],
                       out["v_opacities"], out["v_sh"], v_viewmats=out["v_viewmats"], ws=ws, stream=stream)
     return out
 
@@ -394,9 +419,12 @@ class RasterizeGaussians(torch.autograd.Function):
         p, W, H, sh = ctx.p, ctx.W, ctx.H, ctx.sh
         v_image = torch.zeros_like(ctx.fwd["image"]) if v_image is None else v_image.contiguous()
         v_alpha = None if v_alpha is None else v_alpha.contiguous()
+        # colours from the projection's SH, plain RGB: the 2D gradients as records (fields as strided views)
+        records = sh and p.render_depth == L.GSR_DEPTH_NONE and not p.colors_shared
         g2 = rasterize_backward(p, ctx.proj, opacities, ctx.isect, W, H, ctx.fwd, v_image, v_alpha, background,
-                                absgrad=ctx.absgrad, features=None if sh else colors)
-        ctx.meta["means2d_grad"] = g2["v_means2d"]          # dL/d(2D means) per view, for densification
+                                absgrad=ctx.absgrad, features=None if sh else colors, records=records)
+        # dL/d(2D means) per view, for densification (a contiguous copy when it is a field of the records)
+        ctx.meta["means2d_grad"] = g2["v_means2d"].contiguous()
         ctx.meta["grads2d"] = g2                            # every compositing gradient, per view
         if ctx.absgrad:
             ctx.meta["means2d_absgrad"] = g2["v_means2d_abs"]

@@ -205,8 +205,10 @@ class GaussianTrainer:
         v_image = torch.empty_like(image)
         loss = torch.empty(1, device=self.device, dtype=torch.float32)
         L.gsr_l1_loss(image, target, 1.0 / image.numel(), v_image, loss, self.l1_ws)
+        # the 2D gradients as records (one or two cache lines per Gaussian for the backward's atomics)
         g2 = R.rasterize_backward(self.p, proj, sc["opacities"], isect, W, H, fwd, v_image,
-                                  absgrad=self.cfg.absgrad and self.cfg.strategy == "adc")
+                                  absgrad=self.cfg.absgrad and self.cfg.strategy == "adc",
+                                  records=self.p.render_depth == 0 and not self.p.colors_shared)
         g3 = R.project_backward(self.p, sc["means"], sc["quats"], sc["scales"], sc["opacities"], sc["sh"], vm, Ks, W,
                                 H, proj, g2)
         return loss, g2, g3
@@ -231,7 +233,7 @@ class GaussianTrainer:
         self.M_cap = max(self.M_cap, int(self.last_M * 1.25) + 1024)
         self.last_grads = g3
         if c.strategy == "adc" and t < c.refine_stop:
-            v2 = g2["v_means2d_abs"] if c.absgrad else g2["v_means2d"]
+            v2 = g2["v_means2d_abs"] if c.absgrad else g2["v_means2d"].contiguous()   # records: a strided view
             L.gsr_densify_stats(C, self.N, W, H, proj["radii"], v2, float(C), self.accum, self.count)
         self._adam(t, g3)
         if c.strategy == "mcmc":
