@@ -18,13 +18,14 @@ def _say(msg):
 
 
 # 64 x 48: 12 tiles, the four-waves-per-tile backward; 1280 x 720: 3,600 tiles, the one-wave RGB backward
-@pytest.mark.parametrize("W,H,absgrad", [(64, 48, False), (64, 48, True), (1280, 720, False), (1280, 720, True)])
-def test_records_hold_the_sums_of_the_four_arrays(W, H, absgrad):
+@pytest.mark.parametrize("W,H,absgrad,aa", [(64, 48, False, False), (64, 48, True, True), (1280, 720, False, False),
+                                             (1280, 720, True, False), (1280, 720, False, True)])
+def test_records_hold_the_sums_of_the_four_arrays(W, H, absgrad, aa):
     from _gpu import gpu_backward, gpu_forward, np_, params, to_dev
     from paper_2409_06765_amd import _lib as L
     from paper_2409_06765_amd import rasterize as R
-    _say(f"{W}x{H} absgrad={absgrad}")
-    p = params(sh_degree=3, tile_cull=1)
+    _say(f"{W}x{H} absgrad={absgrad} antialiased={aa}")
+    p = params(sh_degree=3, tile_cull=1, antialiased=aa)
     sc = scenes.scene_tiny(3000, sh_degree=3, seed=31, log_scale_mean=-3.0)
     cams = scenes.cams_tiny(W=W, H=H, f=0.8 * W, n_cams=2, seed=3)
     st = gpu_forward(p, sc, cams, n_eval=False)
