@@ -326,7 +326,7 @@ constexpr int kTileBatch = 64;
 // explicit address space keeps it a global atomic.
 using global_float = __attribute__((address_space(1))) float;
 
-template <bool kStd>
+template <bool kStd, bool kAbs>
 __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, CamTable cams) {
     __shared__ float4 s_xyo[kTileBatch];
     __shared__ float4 s_con[kTileBatch];
@@ -348,13 +348,13 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
 
     // per pixel (one per quad): T restored back to front, R = v_alpha final_T - S . v_C with S the colour
     // composited behind the current entry (background included), v_C, last index
-    float T[4], SV[4], vATf[4], vC[4][3];
+    float T[4], R[4], vC[4][3];
     int last[4], qlast[4];
     int stop = -1;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const int xi = tx * kTile + (q & 1) * 8 + (lane & 7), yi = ty * kTile + (q >> 1) * 8 + (lane >> 3);
-        T[q] = 1.0f; SV[q] = 0.0f; vATf[q] = 0.0f; vC[q][0] = vC[q][1] = vC[q][2] = 0.0f;
+        T[q] = 1.0f; R[q] = 0.0f; vC[q][0] = vC[q][1] = vC[q][2] = 0.0f;
         last[q] = -1;
         if (xi < ci.W && yi < ci.H) {
             const int64_t pix = ci.pix_off + (int64_t)yi * ci.W + xi;
@@ -362,10 +362,10 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
             const float Tf = a.final_T[pix];
             T[q] = Tf;
             vC[q][0] = a.v_image[3 * pix]; vC[q][1] = a.v_image[3 * pix + 1]; vC[q][2] = a.v_image[3 * pix + 2];
-            if (a.v_alpha) vATf[q] = a.v_alpha[pix] * Tf;
+            if (a.v_alpha) R[q] = a.v_alpha[pix] * Tf;
             if (a.background) {
                 const float *bg = a.background + 3 * c;
-                SV[q] = Tf * ((bg[0] * vC[q][0] + bg[1] * vC[q][1]) + bg[2] * vC[q][2]);
+                R[q] -= Tf * ((bg[0] * vC[q][0] + bg[1] * vC[q][1]) + bg[2] * vC[q][2]);
             }
         }
         int m = last[q];
@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
         qlast[q] = __builtin_amdgcn_readfirstlane(m);       // largest last index of quad q
         stop = max(stop, qlast[q]);
     }
-    const bool want_abs = a.v_means2d_abs != nullptr;
+    constexpr bool want_abs = kAbs;   // v_means2d_abs given: compiled in only where it is asked for
     const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
     const int nslots = want_abs ? 11 : 9;
     float *dst_base = nullptr;
@@ -450,12 +450,12 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
                 const float inv = __builtin_amdgcn_rcpf(1.0f - al);
                 const float Tk = T[q] * inv;
                 const float cv = (col.x * vC[q][0] + col.y * vC[q][1]) + col.z * vC[q][2];
-                const float v_al = fmaf(Tk, cv, inv * (vATf[q] - SV[q]));
+                const float v_al = fmaf(Tk, cv, inv * R[q]);
                 // lanes that do not composite the entry (and clamped alphas: no gradient to o or sigma) get
                 // zero weights through selects, so the wave never branches on them
                 const float wgt = use ? al * Tk : 0.0f;
                 const float m_sig = (use && araw <= amax) ? -araw : 0.0f;
-                SV[q] = fmaf(wgt, cv, SV[q]);
+                R[q] = fmaf(-wgt, cv, R[q]);
                 T[q] = use ? Tk : T[q];
                 const float v_sig = m_sig * v_al;
                 const float t = v_sig * dx, sy = v_sig * dy;
@@ -555,10 +555,14 @@ int launch_rasterize_bwd(const gsr_params &p, const CamTable &cams, int N, int D
             // SIMDs; then a block of four quad waves per tile finishes sooner
             if (cams.total_tiles < kFewTiles)
                 raster_bwd_kernel<4><<<grid, block, 0, s>>>(a, cams);
+            else if (standard_thresholds(p) && !v_means2d_abs)
+                raster_bwd_rgb_kernel<true, false><<<grid, dim3(kWave), 0, s>>>(a, cams);
             else if (standard_thresholds(p))
-                raster_bwd_rgb_kernel<true><<<grid, dim3(kWave), 0, s>>>(a, cams);
+                raster_bwd_rgb_kernel<true, true><<<grid, dim3(kWave), 0, s>>>(a, cams);
+            else if (!v_means2d_abs)
+                raster_bwd_rgb_kernel<false, false><<<grid, dim3(kWave), 0, s>>>(a, cams);
             else
-                raster_bwd_rgb_kernel<false><<<grid, dim3(kWave), 0, s>>>(a, cams);
+                raster_bwd_rgb_kernel<false, true><<<grid, dim3(kWave), 0, s>>>(a, cams);
             break;
         case 4: raster_bwd_kernel<4><<<grid, block, 0, s>>>(a, cams); break;
         case 8: raster_bwd_kernel<8><<<grid, block, 0, s>>>(a, cams); break;
