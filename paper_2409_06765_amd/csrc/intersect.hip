@@ -116,10 +116,10 @@ __device__ __forceinline__ GaussTiles gauss_tiles(const CamTable &cams, int N, i
 }
 
 // What the key emission needs of a projected Gaussian with tiles, packed by
-// bin_keys_kernel into one 32-byte record so that the emission, which visits
-// the Gaussians in depth order, gathers one record instead of five arrays:
-// {mean x, mean y, conic a, conic b}, {conic c, opacity (times the
-// compensation), radius (int bits), -}.
+// bin_keys_kernel into one 32-byte record, which gather_recs_kernel moves
+// into depth order (the order the emission visits the Gaussians in) together
+// with the tile count it holds: {mean x, mean y, conic a, conic b},
+// {conic c, opacity (times the compensation), radius (int bits), tiles (int bits)}.
 struct BinRec {
     float4 a;
     float4 b;
@@ -197,26 +197,36 @@ __global__ void __launch_bounds__(kScanThreads) block_sums_kernel(int64_t n_tota
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
-// The counts gathered into depth order (counts_sorted[i] = counts[order[i]])
-// and their per-block sums, in one pass.
+// The emission records gathered into depth order (recs_sorted[i] =
+// recs[order[i]]), their tile counts (kept in the record) as counts_sorted,
+// and the per-block sums of those counts, in one pass: the one random read of
+// the binning path, after which the emission reads its records in order.
 // Positions at or past *n_kept (the Gaussians the depth order kept) become
-// entries of no tiles, their order set to Gaussian 0.
-__global__ void __launch_bounds__(kScanThreads) gather_block_sums_kernel(int64_t n_total,
-        const int64_t *__restrict__ n_kept, int32_t *__restrict__ order, const int32_t *__restrict__ counts,
-        int32_t *__restrict__ counts_sorted, int64_t *__restrict__ block_sums) {
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+// entries of no tiles, their order set to Gaussian 0 (their records are not
+// read); Gaussians of no tiles inside it (the one-block sort keeps them) carry
+// records of count 0.
+__global__ void __launch_bounds__(kScanThreads) gather_recs_kernel(int64_t n_total,
+        const int64_t *__restrict__ n_kept, int32_t *__restrict__ order, const BinRec *__restrict__ recs,
+        BinRec *__restrict__ recs_sorted, int32_t *__restrict__ counts_sorted, int64_t *__restrict__ block_sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
     const int64_t kept = min(n_total, *n_kept);
     int64_t local = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; i++) {
-        if (base + i < kept) {
-            const int32_t g = order[base + i];
-            const int32_t c = (g >= 0 && g < n_total) ? counts[g] : 0;
-            counts_sorted[base + i] = c;
+        const int64_t j = base + (int64_t)i * kScanThreads;   // block sums only: any split of the block's slots
+        if (j < kept) {
+            const int32_t g = order[j];
+            BinRec r;
+            r.a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            r.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // radius 0, count 0: a bad order entry emits nothing
+            if (g >= 0 && g < n_total) r = recs[g];
+            recs_sorted[j] = r;
+            const int32_t c = __float_as_int(r.b.w);
+            counts_sorted[j] = c;
             local += c;
-        } else if (base + i < n_total) {
-            order[base + i] = 0;
-            counts_sorted[base + i] = 0;
+        } else if (j < n_total) {
+            order[j] = 0;
+            counts_sorted[j] = 0;
         }
     }
     int64_t total;
@@ -287,6 +297,7 @@ __global__ void __launch_bounds__(kScanThreads) offsets_kernel(int64_t n_total, 
 // tile rows (whole rectangle rows, or the culled runs) into an LDS table of
 // up to kEmitRows rows: slot of the run's first tile, that tile, run length,
 // entry.  An entry with more rows than fit is continued in the next window.
+// The culling records, when given, are in emission order (recs[q] for entry q).
 // Then each lane writes a run of at most 8 consecutive slots of the wave's
 // slice, finding its row by binary search over the table.  The slice is
 // staged in LDS and written out coalesced.  Keys are tile << 32 | depth bits
@@ -366,7 +377,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
             start = offsets[q] + (lane == 0 ? so : 0);
             const int64_t end = q + 1 < n_total ? offsets[q + 1] : total;
             if (end > start) {
-                t = recs ? gauss_tiles_rec(cams, N, g, recs[g], cull) : gauss_tiles(cams, N, g, means2d, radii, cull);
+                t = recs ? gauss_tiles_rec(cams, N, g, recs[q], cull) : gauss_tiles(cams, N, g, means2d, radii, cull);
                 nr = t.y1 - t.y0 - (lane == 0 ? r0 : 0);
                 base = cams.cam[g / N].tile_base;
                 TX = cams.cam[g / N].TX;
@@ -574,15 +585,16 @@ __global__ void __launch_bounds__(256) ranges_kernel(int64_t M, const int64_t *_
 int64_t range_blocks(int64_t M) { return (M + 256 * kRangeItems - 1) / (256 * kRangeItems); }
 
 // ---- binning-path helpers -------------------------------------------------------
-// Depth-sort keys of the projected Gaussians and their counts; a Gaussian of
-// no tiles gets kDropKey, which the first sort pass leaves out.
+// Depth-sort keys of the projected Gaussians and their emission records (tile
+// count included); a Gaussian of no tiles gets kDropKey, which the first sort
+// pass leaves out (the one-block sort keeps it, last), and a record of count 0
+// whose other fields are not read.
 __global__ void __launch_bounds__(256) bin_keys_kernel(CamTable cams, int N, int64_t n_total,
         const float *__restrict__ means2d, const int32_t *__restrict__ radii, const float *__restrict__ depths,
-        CullIn cull, int32_t *__restrict__ counts, uint32_t *__restrict__ dkeys, BinRec *__restrict__ recs) {
+        CullIn cull, uint32_t *__restrict__ dkeys, BinRec *__restrict__ recs) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_total) return;
     const int k = gauss_tile_count(gauss_tiles(cams, N, g, means2d, radii, cull));
-    counts[g] = k;
     dkeys[g] = k > 0 ? __float_as_uint(depths[g]) : kDropKey;
     if (k > 0) {
         float o = 0.0f, ca = 0.0f, cb = 0.0f, cc = 0.0f;
@@ -593,8 +605,10 @@ __global__ void __launch_bounds__(256) bin_keys_kernel(CamTable cams, int N, int
         }
         BinRec r;
         r.a = make_float4(means2d[2 * g], means2d[2 * g + 1], ca, cb);
-        r.b = make_float4(cc, o, __int_as_float(radii[g]), 0.0f);
+        r.b = make_float4(cc, o, __int_as_float(radii[g]), __int_as_float(k));
         recs[g] = r;
+    } else {
+        recs[g].b.w = __int_as_float(0);
     }
 }
 
@@ -1013,9 +1027,9 @@ int radix_sort(int64_t M, int key_bits, K *keys, int32_t *ids, K *keys_alt, int3
 
 // Binning workspace layout: prepare part (C*N sized, kept until finish).
 struct BinPrep {
-    BinRec *recs;            // [n] what the emission reads of each Gaussian with tiles
+    BinRec *recs;            // [n] what the emission reads of each Gaussian with tiles, by Gaussian
+    BinRec *recs_sorted;     // [n] the same in depth order
     int64_t *kept;           // [1] projected Gaussians with at least one tile
-    int32_t *counts;         // [n] tiles per projected Gaussian
     uint32_t *dkeys, *dkeys_alt;
     int32_t *order, *order_alt;   // depth order of the projected Gaussians
     int32_t *counts_sorted;  // [n]
@@ -1031,8 +1045,8 @@ BinPrep carve_prep(void *ws, int64_t n) {
     auto take = [&](size_t bytes) { void *q = p; p += align256(bytes); return q; };
     const size_t nn = (size_t)(n > 0 ? n : 1);
     b.recs = (BinRec *)take(nn * sizeof(BinRec));
+    b.recs_sorted = (BinRec *)take(nn * sizeof(BinRec));
     b.kept = (int64_t *)take(8);
-    b.counts = (int32_t *)take(nn * 4);
     b.dkeys = (uint32_t *)take(nn * 4);
     b.dkeys_alt = (uint32_t *)take(nn * 4);
     b.order = (int32_t *)take(nn * 4);
@@ -1049,7 +1063,7 @@ BinPrep carve_prep(void *ws, int64_t n) {
 size_t prep_bytes(int64_t n) {
     const size_t nn = (size_t)(n > 0 ? n : 1);
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    return align256(nn * sizeof(BinRec)) + align256(8) + 6 * align256(nn * 4) + align256(nn * 8) +
+    return 2 * align256(nn * sizeof(BinRec)) + align256(8) + 5 * align256(nn * 4) + align256(nn * 8) +
            align256((size_t)(nb > 0 ? nb : 1) * 8) + align256(8) + radix_ws_bytes(n);
 }
 
@@ -1254,15 +1268,15 @@ int launch_bin_prepare(const gsr_params &p, const CamTable &cams, int N, const f
     }
     const unsigned nb = (unsigned)((n + 255) / 256);
     bin_keys_kernel<<<nb, 256, 0, s>>>(cams, N, n, means2d, radii, depths, cull_inputs(p, conics, opacities, comps),
-                                       b.counts, b.dkeys, b.recs);
+                                       b.dkeys, b.recs);
     // the depth order of the Gaussians that have tiles (the first pass drops the others)
     int rc = radix_sort<uint32_t>(n, 32, b.dkeys, b.order, b.dkeys_alt, b.order_alt, b.sort_ws, s, nullptr, b.kept);
     if (rc != GSR_OK) return rc;
     // gather + block sums, then the scan of the block sums, which writes the count into the workspace
     // and, when asked, into total_dev (no copy node), then the offsets
     const int64_t nbs = (n + kScanTile - 1) / kScanTile;
-    gather_block_sums_kernel<<<dim3((unsigned)nbs), dim3(kScanThreads), 0, s>>>(n, b.kept, b.order, b.counts,
-                                                                             b.counts_sorted, b.block_sums);
+    gather_recs_kernel<<<dim3((unsigned)nbs), dim3(kScanThreads), 0, s>>>(n, b.kept, b.order, b.recs, b.recs_sorted,
+                                                                       b.counts_sorted, b.block_sums);
     scan_sums_kernel<<<1, kScanThreads, 0, s>>>(b.block_sums, nbs, b.total, total_dev);
     offsets_kernel<<<dim3((unsigned)nbs), dim3(kScanThreads), 0, s>>>(n, b.counts_sorted, b.block_sums,
                                                                     b.offsets_sorted);
@@ -1290,7 +1304,7 @@ int launch_bin_finish(const gsr_params &p, const CamTable &cams, int N, const fl
     // M is the capacity; the true count (b.total, from the prepare step) is read on the device
     emit_kernel<uint32_t><<<dim3((unsigned)ne), dim3(kEmitThreads), 0, s>>>(
         cams, N, n, means2d, radii, depths, cull_inputs(p, conics, opacities, comps), b.order, b.offsets_sorted, M,
-        b.total, f.tkeys, ids, fuse ? (int32_t *)f.sort_ws : nullptr, width0, hist_stride(ne), b.recs);
+        b.total, f.tkeys, ids, fuse ? (int32_t *)f.sort_ws : nullptr, width0, hist_stride(ne), b.recs_sorted);
     rc = radix_sort<uint32_t>(M, tile_bits, f.tkeys, ids, f.tkeys_alt, f.ids_alt, f.sort_ws, s, b.total, nullptr,
                               fuse);
     if (rc != GSR_OK) return rc;
