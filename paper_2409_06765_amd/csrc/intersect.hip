@@ -8,7 +8,9 @@
 //  * the binning path used by the pipeline: the projected Gaussians are
 //    first stably sorted by depth bits (C*N 32-bit keys; the first pass
 //    also drops the Gaussians of no tiles, so the later passes and
-//    everything after them see only the visible ones), their tiles are then
+//    everything after them see only the visible ones), their binning records
+//    (what the emission reads of a Gaussian, its tile count included) are
+//    gathered into that order in one pass, their tiles are then
 //    emitted in that order with 32-bit tile keys (each emit block also
 //    counts the first tile-bit digits of its slots, the histogram the sort's
 //    first pass needs), and a stable sort on the tile bits alone (two passes
