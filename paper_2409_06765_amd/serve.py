@@ -167,7 +167,7 @@ class GpuBackend:
     launch.  Projection and binning run on ``stage_stream``, compositing on
     ``raster_stream``."""
 
-    BYTES_PER_GAUSSIAN = 40 + 48 + 36    # projected arrays + packed record + binning workspace
+    BYTES_PER_GAUSSIAN = 40 + 48 + 92    # projected arrays + packed record + binning workspace
 
     def __init__(self, scene, params, device="cuda:0"):
         import torch
