@@ -264,6 +264,32 @@ def test_binning_keeps_equal_depths_in_id_order(C, N):
     np.testing.assert_array_equal(np_(st["isect"]["ranges"]), isect["ranges"])
 
 
+@pytest.mark.parametrize("C,N", [(1, 800), (1, 16384), (2, 5000), (1, 20000)])
+def test_binning_skips_gaussians_of_no_tiles(C, N):
+    """A third of the projected Gaussians lie behind the cameras and a third
+    beside the image (radius 0 or an empty tile rectangle, so no tiles): the
+    one-block depth sort (up to 16,384 keys) keeps them, last, with records of
+    no tiles, and the multi-block sort drops them in its first pass; either
+    way ids and ranges equal the oracle's bit for bit (Rasterization of
+    Gaussians: tile binning)."""
+    from _gpu import gpu_forward, np_, params
+    _say(f"binning with Gaussians of no tiles C={C} N={N}")
+    g = np.random.default_rng(7 * N + C)
+    sc = scenes.scene_tiny(N, seed=N + 1, log_scale_mean=-3.0)
+    part = g.integers(0, 3, N)
+    sc["means"][part == 1, 2] = g.uniform(6.0, 9.0, int((part == 1).sum())).astype(np.float32)   # behind
+    sc["means"][part == 2, 0] = g.uniform(4.0, 6.0, int((part == 2).sum())).astype(np.float32)   # beside
+    eyes = [[0.0, 0.0, 4.0], [0.0, 0.3, 4.5]][:C]
+    cams = scenes.cameras([scenes.look_at(e) for e in eyes], [scenes.intrinsics(80.0, 90, 70)] * C, 90, 70)
+    st = gpu_forward(params(), sc, cams)
+    proj, isect, _ = O32.forward(OracleParams(), sc, cams)
+    vis = proj["radii"] > 0
+    assert 0 < vis.sum() < vis.size, "the scene must hold Gaussians with and without tiles"
+    assert st["isect"]["M"] == isect["M"]
+    np.testing.assert_array_equal(np_(st["isect"]["ids"]), isect["ids"])
+    np.testing.assert_array_equal(np_(st["isect"]["ranges"]), isect["ranges"])
+
+
 @pytest.mark.parametrize("opaque,tile_cull", [(False, 0), (True, 0), (True, 1)])
 def test_timed_forward_matches_the_counting_forward(opaque, tile_cull):
     """With the default thresholds and no per-pixel counts, plain RGB takes a walk of its own (the
