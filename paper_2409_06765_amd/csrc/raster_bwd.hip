@@ -390,6 +390,7 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
     else if (lane == 8) { dst_base = a.v_opac; dst_stride = 4; }
     else if (lane < 11 && want_abs) { dst_base = a.v_means2d_abs + (lane - 9); dst_stride = 8; }
     const bool dst_lane = lane < nslots && dst_base != nullptr;
+    const bool recs = a.p.grad_records != 0;
     const uint64_t dst_addr = (uint64_t)dst_base;
     const int cam_base = c * a.N;
     // lanes 2, 4: dL/da, dL/dc are half the dx^2, dy^2 moments; lanes 9, 10: |dL/dmu'| carries log2(e)
@@ -433,8 +434,10 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
             // colour gradients, of v_sigma, and of |dL/dmu'|: the conic and the opacity are the same for
             // every pixel, so the mean gradient (d sigma / d mu' is linear in dx, dy) and the opacity
             // gradient (v_sigma = -o e^-sigma dL/dalpha) follow from these sums after the reduction.
-            float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            float acc_o = 0.0f, acc_ax = 0.0f, acc_ay = 0.0f;
+            // started at -0, the identity of float addition (0 + x is not x for x = -0), so the first
+            // quad's terms are taken as they are instead of being added to zero
+            float acc[8] = {-0.0f, -0.0f, -0.0f, -0.0f, -0.0f, -0.0f, -0.0f, -0.0f};
+            float acc_o = -0.0f, acc_ax = -0.0f, acc_ay = -0.0f;
             bool any = false;
 #pragma unroll
             for (int q = 0; q < 4; q++) {
@@ -504,10 +507,18 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
             // s_c = S_dx + r S_dy; lane 8: dL/do = -(sum of v_sigma) / o
             const float val = y * (lane == 8 ? -__builtin_amdgcn_rcpf(xyo.z) : lscale);
             const int ge = __builtin_amdgcn_readfirstlane(__float_as_int(col.w));   // uniform: scalar index arithmetic
-            int n = ge - cam_base;
-            if ((unsigned)n >= (unsigned)a.N) n = 0;   // only a bad id can leave the tile's camera
-            const uint32_t gi = dst_by_n ? (uint32_t)n : (uint32_t)ge;
-            if (dst_lane) __builtin_amdgcn_global_atomic_fadd_f32((global_float *)(dst_addr + (uint64_t)gi * dst_stride), val);
+            if (!want_abs && recs) {
+                // the nine lanes add to one record: a base shared by the wave plus the lane's field
+                // (one address multiply-add per entry instead of a per-lane 64-bit product)
+                global_float *rec = (global_float *)a.v_means2d + (uint64_t)(uint32_t)ge * GSR_GRAD_RECORD;
+                if (lane < GSR_GRAD_RECORD) __builtin_amdgcn_global_atomic_fadd_f32(rec + lane, val);
+            } else {
+                int n = ge - cam_base;
+                if ((unsigned)n >= (unsigned)a.N) n = 0;   // only a bad id can leave the tile's camera
+                const uint32_t gi = dst_by_n ? (uint32_t)n : (uint32_t)ge;
+                if (dst_lane)
+                    __builtin_amdgcn_global_atomic_fadd_f32((global_float *)(dst_addr + (uint64_t)gi * dst_stride), val);
+            }
         }
         __syncthreads();
     }
