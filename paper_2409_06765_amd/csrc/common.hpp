@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "gsraster.h"
 
 namespace gsr {
@@ -412,7 +414,9 @@ __device__ __forceinline__ void stage_features(const Args &a, int c, int g, int 
 // count[q]) holds, in increasing order, the entries whose mask has bit q.
 // Must be called by all kThreadsPerTile threads; ends with a barrier.
 constexpr int kThreadsPerTile = 256;
-__device__ __forceinline__ void compact_quads(uint32_t m, uint8_t (*list)[kThreadsPerTile], int32_t (*wcnt)[4],
+// L = uint8_t stores the slot t, L = uint16_t its byte offset in a float4 array (16 t).
+template <typename L>
+__device__ __forceinline__ void compact_quads(uint32_t m, L (*list)[kThreadsPerTile], int32_t (*wcnt)[4],
                                               int32_t *count) {
     const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -428,7 +432,7 @@ __device__ __forceinline__ void compact_quads(uint32_t m, uint8_t (*list)[kThrea
     for (int q = 0; q < 4; q++) {
         int32_t base = 0;
         for (int v = 0; v < w; v++) base += wcnt[q][v];
-        if ((m >> q) & 1u) list[q][base + pre[q]] = (uint8_t)t;
+        if ((m >> q) & 1u) list[q][base + pre[q]] = sizeof(L) == 1 ? (L)t : (L)(16 * t);
     }
     if (t < 4) count[t] = wcnt[t][0] + wcnt[t][1] + wcnt[t][2] + wcnt[t][3];
     __syncthreads();

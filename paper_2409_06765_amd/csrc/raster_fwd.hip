@@ -75,11 +75,14 @@ struct RasterArgs {
 template <bool kCount, int DM, bool kStd>
 __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamTable cams) {
     constexpr bool kRGB = DM == 3;
-    __shared__ float4 s_xyo[kBatch];   // mean x, mean y, opacity, -
+    __shared__ float4 s_xyo[kBatch];   // mean x, mean y, opacity, list position (int bits)
     __shared__ float4 s_con[kBatch];   // conic a, b, c, -
     __shared__ float4 s_col[kBatch];   // colour r, g, b, log2(opacity / alpha_min)
     __shared__ float s_feat[kRGB ? 1 : DM * kBatch];
-    __shared__ __align__(4) uint8_t s_qlist[4][kBatch];
+    // the plain RGB walk's lists hold byte offsets (16-bit), the others slots (8-bit)
+    constexpr bool kFast = kRGB && kStd && !kCount;
+    using QL = std::conditional_t<kFast, uint16_t, uint8_t>;
+    __shared__ __align__(16) QL s_qlist[4][kBatch];
     __shared__ int32_t s_wcnt[4][4];
     __shared__ int32_t s_qcnt[4];
 
@@ -117,7 +120,9 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
             const PackedGauss r = a.gauss[g];
             qm = refine_quad_mask(quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0), r.xyoh,
                                   r.conh, r.col.w, tile_x0, tile_y0);
-            s_xyo[threadIdx.x] = r.xyoh;
+            // the fourth word (the support extent, used above) takes the entry's list position, which the
+            // plain RGB walk records for the last composited entry without scalar arithmetic
+            s_xyo[threadIdx.x] = make_float4(r.xyoh.x, r.xyoh.y, r.xyoh.z, __int_as_float(k));
             s_con[threadIdx.x] = r.conh;
             s_col[threadIdx.x] = r.col;
             if (!kRGB) stage_features<DM, kBatch>(a, c, g, threadIdx.x, s_feat);
@@ -129,17 +134,23 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
             // The timed instance: the same decisions with the per-lane state in vector registers and
             // every condition applied by a select, so no lane mask is combined by scalar instructions
             // (the scalar unit, shared by the waves of a compute unit, limits this loop more than the
-            // vector units), four list indices per LDS read and the all-stopped test once per eight
-            // entries.  With the default thresholds an entry that reaches a live pixel has alpha >= 1/255
+            // vector units), the list entries as byte offsets of the records, eight per LDS read (one
+            // scalar shift or mask each), the list position of the last composited entry taken from the
+            // record, and the all-stopped test once per eight entries.  With the default thresholds an entry that reaches a live pixel has alpha >= 1/255
             // and T >= 1e-4 before it, so it composites exactly where its weight alpha T is positive.
             for (int j0 = 0; j0 < cnt; j0 += 8) {
                 const int jn = min(cnt - j0, 8);
-                const uint32_t e4a = __builtin_amdgcn_readfirstlane(*(const uint32_t *)&s_qlist[w][j0]);
-                const uint32_t e4b = __builtin_amdgcn_readfirstlane(*(const uint32_t *)&s_qlist[w][j0 + 4]);
-                for (int u = 0; u < jn; u++) {
-                    const int e = ((u < 4 ? e4a : e4b) >> (8 * (u & 3))) & 0xFFu;
-                    const float4 xyo = s_xyo[e];
-                    const float4 con = s_con[e];
+                const uint4 o8 = *reinterpret_cast<const uint4 *>(&s_qlist[w][j0]);
+                const uint32_t o2[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(o8.x),
+                                        (uint32_t)__builtin_amdgcn_readfirstlane(o8.y),
+                                        (uint32_t)__builtin_amdgcn_readfirstlane(o8.z),
+                                        (uint32_t)__builtin_amdgcn_readfirstlane(o8.w)};
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    if (u >= jn) break;
+                    const uint32_t off = (o2[u >> 1] >> (16 * (u & 1))) & 0xFFFFu;   // 16 x slot
+                    const float4 xyo = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_xyo) + off);
+                    const float4 con = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_con) + off);
                     const float dx = xyo.x - px, dy = xyo.y - py;
                     const float sig = scaled_sigma(con, dx, dy);
                     const float al = min_alpha(xyo.z * __builtin_amdgcn_exp2f(-sig), amax);
@@ -149,13 +160,13 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
                     const float Tn = T * (1.0f - ae);
                     const bool keep = Tn >= tmin;                 // false only where this entry stops the pixel
                     const float wgt = keep ? ae * T : 0.0f;
-                    const float4 col = s_col[e];
+                    const float4 col = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_col) + off);
                     Cacc[0] = fmaf(col.x, wgt, Cacc[0]);
                     Cacc[1] = fmaf(col.y, wgt, Cacc[1]);
                     Cacc[2] = fmaf(col.z, wgt, Cacc[2]);
                     T = keep ? Tn : T;
                     live = keep ? live : 0.0f;
-                    last = wgt > 0.0f ? b0 + e : last;
+                    last = wgt > 0.0f ? __float_as_int(xyo.w) : last;
                 }
                 if (__all(live == 0.0f)) break;
             }
