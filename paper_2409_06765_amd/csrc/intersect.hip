@@ -191,9 +191,14 @@ __global__ void __launch_bounds__(kScanThreads) block_sums_kernel(int64_t n_tota
                                                                   int64_t *__restrict__ block_sums) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int64_t local = 0;
+    if (base + kScanItems <= n_total) {          // one 16-byte load (base is a multiple of 4)
+        const int4 q = *reinterpret_cast<const int4 *>(vals + base);
+        local = ((int64_t)q.x + q.y) + ((int64_t)q.z + q.w);
+    } else {
 #pragma unroll
-    for (int i = 0; i < kScanItems; i++)
-        if (base + i < n_total) local += vals[base + i];
+        for (int i = 0; i < kScanItems; i++)
+            if (base + i < n_total) local += vals[base + i];
+    }
     int64_t total;
     block_exclusive_scan<int64_t>(local, total);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
@@ -213,15 +218,26 @@ __global__ void __launch_bounds__(kScanThreads) gather_recs_kernel(int64_t n_tot
     const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
     const int64_t kept = min(n_total, *n_kept);
     int64_t local = 0;
+    // the loads first (clamped to slot 0 past the end, which always exists), then the rest
+    int32_t gs[kScanItems];
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        const int64_t j = base + (int64_t)i * kScanThreads;
+        const int32_t g = order[j < kept ? j : 0];
+        gs[i] = (g >= 0 && g < n_total) ? g : -1;
+    }
+    BinRec rs[kScanItems];
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) rs[i] = recs[gs[i] >= 0 ? gs[i] : 0];
 #pragma unroll
     for (int i = 0; i < kScanItems; i++) {
         const int64_t j = base + (int64_t)i * kScanThreads;   // block sums only: any split of the block's slots
         if (j < kept) {
-            const int32_t g = order[j];
-            BinRec r;
-            r.a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            r.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // radius 0, count 0: a bad order entry emits nothing
-            if (g >= 0 && g < n_total) r = recs[g];
+            BinRec r = rs[i];
+            if (gs[i] < 0) {                     // radius 0, count 0: a bad order entry emits nothing
+                r.a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                r.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
             recs_sorted[j] = r;
             const int32_t c = __float_as_int(r.b.w);
             counts_sorted[j] = c;
@@ -272,12 +288,16 @@ __global__ void __launch_bounds__(kScanThreads) offsets_kernel(int64_t n_total, 
         const int64_t *__restrict__ block_off, int64_t *__restrict__ offsets) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int32_t v[kScanItems];
+    if (base + kScanItems <= n_total) {          // one 16-byte load (base is a multiple of 4)
+        const int4 q = *reinterpret_cast<const int4 *>(counts + base);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; i++) v[i] = (base + i < n_total) ? counts[base + i] : 0;
+    }
     int64_t local = 0;
 #pragma unroll
-    for (int i = 0; i < kScanItems; i++) {
-        v[i] = (base + i < n_total) ? counts[base + i] : 0;
-        local += v[i];
-    }
+    for (int i = 0; i < kScanItems; i++) local += v[i];
     int64_t total;
     int64_t run = block_exclusive_scan<int64_t>(local, total) + block_off[blockIdx.x];
 #pragma unroll
@@ -596,18 +616,22 @@ __global__ void __launch_bounds__(256) bin_keys_kernel(CamTable cams, int N, int
         CullIn cull, uint32_t *__restrict__ dkeys, BinRec *__restrict__ recs) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_total) return;
-    const int k = gauss_tile_count(gauss_tiles(cams, N, g, means2d, radii, cull));
-    dkeys[g] = k > 0 ? __float_as_uint(depths[g]) : kDropKey;
+    // every input of the Gaussian loaded up front (all in bounds), then the tiles from the record
+    const int rad = radii[g];
+    const float mx = means2d[2 * g], my = means2d[2 * g + 1], dep = depths[g];
+    float o = 0.0f, ca = 0.0f, cb = 0.0f, cc = 0.0f;
+    if (cull.on) {
+        o = cull.opacities[g % N];
+        if (cull.comps) o *= cull.comps[g];
+        ca = cull.conics[3 * g]; cb = cull.conics[3 * g + 1]; cc = cull.conics[3 * g + 2];
+    }
+    BinRec r;
+    r.a = make_float4(mx, my, ca, cb);
+    r.b = make_float4(cc, o, __int_as_float(rad), 0.0f);
+    const int k = gauss_tile_count(gauss_tiles_rec(cams, N, g, r, cull));
+    dkeys[g] = k > 0 ? __float_as_uint(dep) : kDropKey;
     if (k > 0) {
-        float o = 0.0f, ca = 0.0f, cb = 0.0f, cc = 0.0f;
-        if (cull.on) {
-            o = cull.opacities[g % N];
-            if (cull.comps) o *= cull.comps[g];
-            ca = cull.conics[3 * g]; cb = cull.conics[3 * g + 1]; cc = cull.conics[3 * g + 2];
-        }
-        BinRec r;
-        r.a = make_float4(means2d[2 * g], means2d[2 * g + 1], ca, cb);
-        r.b = make_float4(cc, o, __int_as_float(radii[g]), __int_as_float(k));
+        r.b.w = __int_as_float(k);
         recs[g] = r;
     } else {
         recs[g].b.w = __int_as_float(0);
@@ -665,12 +689,17 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K *__res
     __syncthreads();
     const uint32_t mask = (1u << bits) - 1u;
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    // every load first, from in-bounds positions (slot 0 past the count; the buffers hold at least one
+    // pair), so that a wave has all its loads in flight at once; then the counts
+    const int64_t last = M > 0 ? M - 1 : 0;
+    K kv[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; i++) kv[i] = keys[min(base + (int64_t)i * kSortThreads + threadIdx.x, last)];
 #pragma unroll
     for (int i = 0; i < kSortItems; i++) {
         const int64_t idx = base + (int64_t)i * kSortThreads + threadIdx.x;
-        const K kv = idx < M ? keys[idx] : (K)0;
-        const bool valid = idx < M && !(drop && (uint64_t)kv == kDropKey);
-        if (valid) atomicAdd(&cnt[(uint32_t)(kv >> shift) & mask], 1);   // counts need no order: LDS atomics
+        const bool valid = idx < M && !(drop && (uint64_t)kv[i] == kDropKey);
+        if (valid) atomicAdd(&cnt[(uint32_t)(kv[i] >> shift) & mask], 1);   // counts need no order: LDS atomics
     }
     __syncthreads();
     if (threadIdx.x < (1 << bits)) hist[(int64_t)threadIdx.x * stride + blockIdx.x] = cnt[threadIdx.x];
@@ -753,12 +782,19 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const K *__
     int32_t val[kSortItems];
     int32_t rank[kSortItems];
     const uint64_t lt = lanemask_lt();
+    // every load first, from in-bounds positions (as in radix_hist_kernel), then the ranking
+    const int64_t last = M > 0 ? M - 1 : 0;
+#pragma unroll
+    for (int i = 0; i < kSortItems; i++) {
+        const int64_t idx = min(base + (int64_t)w * (kWave * kSortItems) + i * kWave + lane, last);
+        key[i] = keys_in[idx];
+        val[i] = ids_in ? ids_in[idx] : (int32_t)idx;
+    }
 #pragma unroll
     for (int i = 0; i < kSortItems; i++) {
         const int64_t idx = base + (int64_t)w * (kWave * kSortItems) + i * kWave + lane;
-        key[i] = idx < M ? keys_in[idx] : (K)0;
         const bool valid = idx < M && !(drop && (uint64_t)key[i] == kDropKey);
-        val[i] = valid ? (ids_in ? ids_in[idx] : (int32_t)idx) : 0;
+        if (!valid) val[i] = 0;
         const uint32_t d = (uint32_t)(key[i] >> shift) & mask;
         const uint64_t active = __ballot(valid);
         const uint64_t peers = match_digit(d, active);
@@ -827,10 +863,15 @@ __global__ void __launch_bounds__(kSmallThreads) radix_sort_small_kernel(uint32_
     int32_t val[kSmallItems];
     // position of item i of this lane: w * 1024 + i * 64 + lane (wave-striped)
 #pragma unroll
+    for (int i = 0; i < kSmallItems; i++) {      // every load first, clamped in bounds (M >= 1 here)
+        const int idx = min(w * (kWave * kSmallItems) + i * kWave + lane, M - 1);
+        key[i] = keys[idx];
+        val[i] = iota ? idx : ids[idx];
+    }
+#pragma unroll
     for (int i = 0; i < kSmallItems; i++) {
         const int idx = w * (kWave * kSmallItems) + i * kWave + lane;
-        key[i] = idx < M ? keys[idx] : 0u;
-        val[i] = idx < M ? (iota ? idx : ids[idx]) : 0;
+        if (idx >= M) { key[i] = 0u; val[i] = 0; }
     }
     if (kept_out && t == 0) *kept_out = M;        // every pair kept (dropped keys sort last)
     for (int shift = 0; shift < key_bits; shift += 8) {
