@@ -351,22 +351,33 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
     float T[4], R[4], vC[4][3];
     int last[4], qlast[4];
     int stop = -1;
+    // every pixel's inputs loaded first (a pixel outside the image reads the camera's first pixel and
+    // is then reset), so that the four quads' loads are in flight together
+    bool ins[4];
+    float va[4];
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const int xi = tx * kTile + (q & 1) * 8 + (lane & 7), yi = ty * kTile + (q >> 1) * 8 + (lane >> 3);
-        T[q] = 1.0f; R[q] = 0.0f; vC[q][0] = vC[q][1] = vC[q][2] = 0.0f;
-        last[q] = -1;
-        if (xi < ci.W && yi < ci.H) {
-            const int64_t pix = ci.pix_off + (int64_t)yi * ci.W + xi;
-            last[q] = a.last_ids[pix];
-            const float Tf = a.final_T[pix];
-            T[q] = Tf;
-            vC[q][0] = a.v_image[3 * pix]; vC[q][1] = a.v_image[3 * pix + 1]; vC[q][2] = a.v_image[3 * pix + 2];
-            if (a.v_alpha) R[q] = a.v_alpha[pix] * Tf;
+        ins[q] = xi < ci.W && yi < ci.H;
+        const int64_t pix = ci.pix_off + (ins[q] ? (int64_t)yi * ci.W + xi : 0);
+        last[q] = a.last_ids[pix];
+        T[q] = a.final_T[pix];
+        vC[q][0] = a.v_image[3 * pix]; vC[q][1] = a.v_image[3 * pix + 1]; vC[q][2] = a.v_image[3 * pix + 2];
+        va[q] = a.v_alpha ? a.v_alpha[pix] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        R[q] = 0.0f;
+        if (ins[q]) {
+            const float Tf = T[q];
+            if (a.v_alpha) R[q] = va[q] * Tf;
             if (a.background) {
                 const float *bg = a.background + 3 * c;
                 R[q] -= Tf * ((bg[0] * vC[q][0] + bg[1] * vC[q][1]) + bg[2] * vC[q][2]);
             }
+        } else {
+            T[q] = 1.0f; vC[q][0] = vC[q][1] = vC[q][2] = 0.0f;
+            last[q] = -1;
         }
         int m = last[q];
 #pragma unroll
