@@ -318,7 +318,21 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
         do {
         if (!in) break;
         const size_t g = (size_t)c * N + n;
-        if (radii[g] <= 0) break;
+        // the 2D gradients of (c, n): four arrays, or one record per (camera, Gaussian); loaded with the
+        // radius, before the projection is recomputed, so that their latency overlaps it
+        const bool rec = p.grad_records != 0;
+        const float *gm = rec ? v_means2d + g * GSR_GRAD_RECORD : v_means2d + 2 * g;
+        const float *gc = rec ? gm + 2 : v_conics + 3 * g;
+        const float *gcol = rec ? gm + 5 : (v_colors ? v_colors + 3 * g : nullptr);
+        const int rad = radii[g];
+        const float vmx = gm[0], vmy = gm[1];
+        const float ga = gc[0], gb = 0.5f * gc[1], gcc = gc[2];
+        float vc[3] = {0.0f, 0.0f, 0.0f};   // no v_colors: direct colours are not differentiated here
+        if (gcol) { vc[0] = gcol[0]; vc[1] = gcol[1]; vc[2] = gcol[2]; }
+        const float vo = rec ? gm[8] : v_opac_cn[g];
+        const float vdep = v_depths ? v_depths[g] : 0.0f;
+        const float comp = (p.antialiased && comps) ? comps[g] : 1.0f;
+        if (rad <= 0) break;
         const CamInfo ci = cams.cam[c];
         const float *V = viewmats + 16 * c;
         const float *Kc = Ks + 9 * c;
@@ -333,30 +347,20 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
         const float tx = o.t[0], ty = o.t[1], tz = o.t[2];
         float vt[3] = {0.0f, 0.0f, 0.0f};
 
-        // the 2D gradients of (c, n): four arrays, or one record per (camera, Gaussian)
-        const bool rec = p.grad_records != 0;
-        const float *gm = rec ? v_means2d + g * GSR_GRAD_RECORD : v_means2d + 2 * g;
-        const float *gc = rec ? gm + 2 : v_conics + 3 * g;
-        const float *gcol = rec ? gm + 5 : (v_colors ? v_colors + 3 * g : nullptr);
-
         // opacity (the rasterizer's opacity is o times the compensation)
-        const float vo = rec ? gm[8] : v_opac_cn[g];
-        const float comp = (p.antialiased && comps) ? comps[g] : 1.0f;
         acc_o += vo * comp;
 
         // 2D mean
-        const float vmx = gm[0], vmy = gm[1];
         vt[0] += vmx * fx / tz;
         vt[1] += vmy * fy / tz;
         vt[2] += -(vmx * fx * tx + vmy * fy * ty) / (tz * tz);
-        if (v_depths) vt[2] += v_depths[g];
+        if (v_depths) vt[2] += vdep;
 
         // conic -> Sigma':  dL/dSigma' = -Y G Y,  G = [[ga, gb/2], [gb/2, gc]].  The product is
         // formed in full (S10 apart from S01, each row from the same row of Y G): for needle-like
         // Gaussians Y is nearly singular and the later products with T and Sigma cancel, which
         // amplifies errors that differ between rows; rows built consistently keep them small.
         const float ya = o.c / o.det, yb = -o.b / o.det, yc = o.a / o.det;
-        const float ga = gc[0], gb = 0.5f * gc[1], gcc = gc[2];
         const float YG00 = ya * ga + yb * gb, YG01 = ya * gb + yb * gcc;
         const float YG10 = yb * ga + yc * gb, YG11 = yb * gb + yc * gcc;
         float S00 = -(YG00 * ya + YG01 * yb);
@@ -434,8 +438,6 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(gsr_params p, CamTable
 
         // colour
         float gdir[3] = {0.0f, 0.0f, 0.0f};   // mean gradient through the SH view direction
-        float vc[3] = {0.0f, 0.0f, 0.0f};   // no v_colors: direct colours are not differentiated here
-        if (gcol) { vc[0] = gcol[0]; vc[1] = gcol[1]; vc[2] = gcol[2]; }
         if constexpr (NK > 0) {
             float cp[3], d[3];
             for (int j = 0; j < 3; j++) cp[j] = -((V[j] * V[3] + V[4 + j] * V[7]) + V[8 + j] * V[11]);
