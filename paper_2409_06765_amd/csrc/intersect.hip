@@ -393,13 +393,21 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(CamTable cams, int N
         t.x0 = t.x1 = t.y0 = t.y1 = 0;
         t.cull.mode = 1;
         int nr = 0, base = 0, TX = 0;
+        // the window's loads first, from in-bounds positions (the last entry past the end), so that they
+        // are in flight together
+        const int64_t qc = min(q, n_total - 1);
+        const int64_t g_ld = order ? (int64_t)order[qc] : qc;
+        const int64_t off_q = offsets[qc];
+        const int64_t off_n = offsets[min(qc + 1, n_total - 1)];
+        BinRec rq;
+        if (recs) rq = recs[qc];
         if (q < n_total) {
-            g = order ? order[q] : q;
+            g = g_ld;
             if (g < 0 || g >= n_total) g = 0;    // order comes from the depth sort; this only bounds a bad input
-            start = offsets[q] + (lane == 0 ? so : 0);
-            const int64_t end = q + 1 < n_total ? offsets[q + 1] : total;
+            start = off_q + (lane == 0 ? so : 0);
+            const int64_t end = q + 1 < n_total ? off_n : total;
             if (end > start) {
-                t = recs ? gauss_tiles_rec(cams, N, g, recs[q], cull) : gauss_tiles(cams, N, g, means2d, radii, cull);
+                t = recs ? gauss_tiles_rec(cams, N, g, rq, cull) : gauss_tiles(cams, N, g, means2d, radii, cull);
                 nr = t.y1 - t.y0 - (lane == 0 ? r0 : 0);
                 base = cams.cam[g / N].tile_base;
                 TX = cams.cam[g / N].TX;
