@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(kThreads) raster_bwd_kernel(RasterBwdArgs a, C
 // their last composited entry) are dropped at staging time, and the rest are
 // stored in list order, so the walk reads its records at consecutive slots
 // with no index lookup in between.
-constexpr int kTileBatch = 64;
+constexpr int kTileBatch = 128;   // two entries per lane
 
 // The gradient outputs are global memory.  An address formed from an integer
 // would make the atomic a flat instruction, which also counts on the LDS
@@ -410,32 +410,41 @@ __global__ void __launch_bounds__(kWave) raster_bwd_rgb_kernel(RasterBwdArgs a, 
 
     for (int hi = stop + 1; hi > start; hi -= kTileBatch) {
         const int base = max(start, hi - kTileBatch);
-        const int k = base + lane;
-        uint32_t qm = 0u;
-        PackedGauss r;
-        int g = 0;
-        if (k < hi) {
-            g = a.ids[k];
-            if ((unsigned)g >= (unsigned)a.CN) g = 0;   // ids come from the sort; this only bounds a bad input
-            r = a.gauss[g];
-            qm = refine_quad_mask(quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0), r.xyoh,
-                                  r.conh, r.col.w, tile_x0, tile_y0);
+        // two entries per lane, the batch's first and second halves: both ids loaded first (clamped,
+        // in-bounds positions), then each half's records
+        int gh[2];
 #pragma unroll
-            for (int q = 0; q < 4; q++)
-                if (k > qlast[q]) qm &= ~(1u << q);      // past every pixel of the quad's last entry
+        for (int h = 0; h < 2; h++) {
+            const int g = a.ids[min(base + h * kWave + lane, hi - 1)];
+            gh[h] = (unsigned)g < (unsigned)a.CN ? g : 0;   // ids come from the sort; this only bounds a bad input
         }
         // the entries that reach a quad, compacted in list order; the records' spare words carry the list
         // index, the quad mask and the id
-        const uint64_t bal = __ballot(qm != 0u);
-        if (qm != 0u) {
-            const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-            const int slot = __popcll(bal & below);
-            s_xyo[slot] = make_float4(r.xyoh.x, r.xyoh.y, r.xyoh.z, __int_as_float(k));
-            s_con[slot] = make_float4(r.conh.x, r.conh.y, r.conh.z, __uint_as_float(qm));
-            s_col[slot] = make_float4(r.col.x, r.col.y, r.col.z, __int_as_float(g));
+        int nslot = 0;
+        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int k = base + h * kWave + lane;
+            const PackedGauss r = a.gauss[gh[h]];
+            uint32_t qm = 0u;
+            if (k < hi) {
+                qm = refine_quad_mask(quad_mask(r.xyoh.x, r.xyoh.y, r.xyoh.w, r.conh.w, tile_x0, tile_y0), r.xyoh,
+                                      r.conh, r.col.w, tile_x0, tile_y0);
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    if (k > qlast[q]) qm &= ~(1u << q);      // past every pixel of the quad's last entry
+            }
+            const uint64_t bal = __ballot(qm != 0u);
+            if (qm != 0u) {
+                const int slot = nslot + __popcll(bal & below);
+                s_xyo[slot] = make_float4(r.xyoh.x, r.xyoh.y, r.xyoh.z, __int_as_float(k));
+                s_con[slot] = make_float4(r.conh.x, r.conh.y, r.conh.z, __uint_as_float(qm));
+                s_col[slot] = make_float4(r.col.x, r.col.y, r.col.z, __int_as_float(gh[h]));
+            }
+            nslot += __popcll(bal);
         }
         __syncthreads();
-        for (int j = __popcll(bal) - 1; j >= 0; j--) {
+        for (int j = nslot - 1; j >= 0; j--) {
             const float4 xyo = s_xyo[j];
             const float4 con = s_con[j];
             const float4 col = s_col[j];
