@@ -141,10 +141,8 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
             for (int j0 = 0; j0 < cnt; j0 += 8) {
                 const int jn = min(cnt - j0, 8);
                 const uint4 o8 = *reinterpret_cast<const uint4 *>(&s_qlist[w][j0]);
-                const uint32_t o2[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(o8.x),
-                                        (uint32_t)__builtin_amdgcn_readfirstlane(o8.y),
-                                        (uint32_t)__builtin_amdgcn_readfirstlane(o8.z),
-                                        (uint32_t)__builtin_amdgcn_readfirstlane(o8.w)};
+                const uint32_t o2[4] = {o8.x, o8.y, o8.z, o8.w};   // kept in vector registers: the offsets
+                                                                    // address the records with no scalar step
 #pragma unroll
                 for (int u = 0; u < 8; u++) {
                     if (u >= jn) break;
