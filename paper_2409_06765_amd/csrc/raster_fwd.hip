@@ -134,15 +134,15 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
             // The timed instance: the same decisions with the per-lane state in vector registers and
             // every condition applied by a select, so no lane mask is combined by scalar instructions
             // (the scalar unit, shared by the waves of a compute unit, limits this loop more than the
-            // vector units), the list entries as byte offsets of the records, eight per LDS read (one
-            // scalar shift or mask each), the list position of the last composited entry taken from the
-            // record, and the all-stopped test once per eight entries.  With the default thresholds an entry that reaches a live pixel has alpha >= 1/255
-            // and T >= 1e-4 before it, so it composites exactly where its weight alpha T is positive.
+            // vector units); the list entries are the records' byte offsets, eight per LDS read, kept in
+            // vector registers; the list position of the last composited entry comes with the record;
+            // the all-stopped test runs once per eight entries.  With the default thresholds an entry
+            // that reaches a live pixel has alpha >= 1/255 and T >= 1e-4 before it, so it composites
+            // exactly where its weight alpha T is positive.
             for (int j0 = 0; j0 < cnt; j0 += 8) {
                 const int jn = min(cnt - j0, 8);
                 const uint4 o8 = *reinterpret_cast<const uint4 *>(&s_qlist[w][j0]);
-                const uint32_t o2[4] = {o8.x, o8.y, o8.z, o8.w};   // kept in vector registers: the offsets
-                                                                    // address the records with no scalar step
+                const uint32_t o2[4] = {o8.x, o8.y, o8.z, o8.w};
 #pragma unroll
                 for (int u = 0; u < 8; u++) {
                     if (u >= jn) break;
