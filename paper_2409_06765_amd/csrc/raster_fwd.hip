@@ -114,6 +114,7 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
         if (__syncthreads_count(done) == kThreads) break;
         const int k = b0 + (int)threadIdx.x;
         uint32_t qm = 0u;
+        bool rec_ok = true;
         if (k < end) {
             int g = a.ids[k];
             if ((unsigned)g >= (unsigned)a.CN) g = 0;   // ids come from the sort; this only bounds a bad input
@@ -124,11 +125,17 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
             // plain RGB walk records for the last composited entry without scalar arithmetic
             s_xyo[threadIdx.x] = make_float4(r.xyoh.x, r.xyoh.y, r.xyoh.z, __int_as_float(k));
             s_con[threadIdx.x] = r.conh;
+            rec_ok = isfinite(r.xyoh.x) && isfinite(r.xyoh.y) && isfinite(r.conh.y) && r.conh.x >= 0.0f &&
+                     r.conh.z >= 0.0f && r.conh.x < INFINITY && r.conh.z < INFINITY;
             s_col[threadIdx.x] = r.col;
             if (!kRGB) stage_features<DM, kBatch>(a, c, g, threadIdx.x, s_feat);
         }
         compact_quads(qm, s_qlist, s_wcnt, s_qcnt);
         const int cnt = __builtin_amdgcn_readfirstlane(s_qcnt[w]);   // entries that can reach this wave's quad
+        // a batch whose records are all finite with A, Q >= 0 has sigma >= 0 at every pixel (a sum of
+        // two non-negative terms): its walk needs no sign test
+        bool sig_free = true;
+        if constexpr (kRGB && kStd && !kCount) sig_free = __syncthreads_and(rec_ok) != 0;
         if (__all(done)) continue;
         if constexpr (kRGB && kStd && !kCount) {
             // The timed instance: the same decisions with the per-lane state in vector registers and
@@ -139,6 +146,8 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
             // the all-stopped test runs once per eight entries.  With the default thresholds an entry
             // that reaches a live pixel has alpha >= 1/255 and T >= 1e-4 before it, so it composites
             // exactly where its weight alpha T is positive.
+            auto walk = [&](auto check) {
+            constexpr bool CHECK_SIG = decltype(check)::value;
             for (int j0 = 0; j0 < cnt; j0 += 8) {
                 const int jn = min(cnt - j0, 8);
                 const uint4 o8 = *reinterpret_cast<const uint4 *>(&s_qlist[w][j0]);
@@ -152,7 +161,7 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
                     const float dx = xyo.x - px, dy = xyo.y - py;
                     const float sig = scaled_sigma(con, dx, dy);
                     const float al = min_alpha(xyo.z * __builtin_amdgcn_exp2f(-sig), amax);
-                    float ae = sig >= 0.0f ? al : 0.0f;           // alpha where the entry is used, else 0
+                    float ae = (CHECK_SIG && sig < 0.0f) ? 0.0f : al;   // alpha where the entry is used, else 0
                     ae = ae >= amin ? ae : 0.0f;
                     ae *= live;
                     const float Tn = T * (1.0f - ae);
@@ -168,6 +177,9 @@ __global__ void __launch_bounds__(kThreads) raster_fwd_kernel(RasterArgs a, CamT
                 }
                 if (__all(live == 0.0f)) break;
             }
+            };
+            if (sig_free) walk(std::false_type{});
+            else walk(std::true_type{});
             done = live == 0.0f;
             continue;
         }
